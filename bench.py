@@ -1,0 +1,183 @@
+"""Throughput benchmark: photons propagated per second on one MI355X.
+
+One step = one pass of the whole hot path over the full-detector workload
+(86 strings x 60 modules, 171 layers with a dust bump, 1000 Cherenkov
+segments x 1e5 photons = 1e8 photons): emission, propagation to absorption
+or a module, hit compaction (pp_propagate) and the per-module histogram
+(pp_dom_counts). Ice, geometry and sources are resident in HBM before the
+timed region; hits stay on the device.
+
+Prints one JSON line. The roofline entry is for the propagation kernel,
+timed with HIP events on the stream it is launched on; the CPU baseline is
+the FP64 oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic VALU work per propagation step, in lane issue slots (one
+# full-rate VALU op on one lane = 1; transcendentals and 32-bit wide
+# multiplies = 4). Frozen count of the arithmetic the method needs per
+# step in FP32, derivation in the design notes.
+SLOTS_PER_STEP = 236
+SLOTS_PER_PHOTON = 172      # emission step (Philox block 0 + source setup)
+SLOTS_PER_CROSSING = 18     # one extra layer of the layer walk
+SLOTS_PER_DOM_TEST = 24     # one ray-sphere test
+PEAK_CLOCK_GHZ = 2.4
+N_CU, SIMD_PER_CU, LANES_PER_SIMD = 256, 4, 16
+PEAK_SLOTS = N_CU * SIMD_PER_CU * LANES_PER_SIMD * PEAK_CLOCK_GHZ * 1e9  # lane-slots/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sources", type=int, default=1000)
+    ap.add_argument("--photons-per-source", type=int, default=100_000)
+    ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--chunk-size", type=int, default=0)
+    ap.add_argument("--grid-blocks", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-photons-per-source", type=int, default=0,
+                    help="oracle sample: first N photons of every source (0 = auto, ~15 s)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for HBM counter scaling)")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 28  # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+
+
+def cpu_baseline(w, per_source: int):
+    from oracle import pyoracle
+    import numpy as np
+    threads = min(16, len(os.sched_getaffinity(0)))
+    if per_source == 0:
+        # calibrate on a tiny sample, then size the sample to ~15 s
+        probe = max(1, 2 * threads // len(w.sources) + 1)
+        sel_src = np.repeat(np.arange(len(w.sources)), probe)
+        sel_loc = np.tile(np.arange(probe), len(w.sources))
+        t0 = time.perf_counter()
+        pyoracle.run(w, sel_src=sel_src, sel_local=sel_loc, dom_mode=1, threads=threads,
+                     records=False, dom_counts=False)
+        dt = time.perf_counter() - t0
+        per_source = int(max(1, min(w.sources["n_photons"].min(), probe * 15.0 / max(dt, 1e-3))))
+    sel_src = np.repeat(np.arange(len(w.sources)), per_source)
+    sel_loc = np.tile(np.arange(per_source), len(w.sources))
+    t0 = time.perf_counter()
+    r = pyoracle.run(w, sel_src=sel_src, sel_local=sel_loc, dom_mode=1, threads=threads,
+                     records=False, dom_counts=False)
+    dt = time.perf_counter() - t0
+    return {"value": r.counters["photons"] / dt, "unit": "photons/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {per_source} photons of each of the {len(w.sources)} sources "
+                      f"({r.counters['photons']} photons, FP64, per-string pre-filter), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the photon "
+              "propagation path is single-GPU in this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    from paper_2405_05700_amd import pp
+    from paper_2405_05700_amd import workloads as W
+
+    w = W.full_detector(n_sources=args.sources, photons_per_source=args.photons_per_source)
+    n_photons = w.n_photons
+    ctx = pp.Context(0, seed=0)
+    ctx.load_workload(w)
+    ctx.set_launch_config(args.block_size, args.chunk_size, args.grid_blocks)
+    batch = ctx.submit(w.sources)
+    stream = torch.cuda.Stream()
+    counts = torch.empty(len(w.doms), dtype=torch.int32, device="cuda:0")
+
+    def step():
+        ctx.propagate(batch, stream)
+        ctx.dom_counts(batch, counts, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    n_hits = ctx.hit_count(batch)  # grows the hit buffer once if needed (not timed)
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        ctx.propagate(batch, stream)
+        ev[i][1].record(stream)
+        ctx.dom_counts(batch, counts, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    kernel_ms = [a.elapsed_time(b) for a, b in ev]
+    st = ctx.stats(batch)
+    assert st["photons"] == n_photons
+    assert st["hits"] + st["absorbed"] + st["capped"] + st["escaped"] == n_photons
+
+    avg_s = sum(kernel_ms) / len(kernel_ms) / 1e3
+    slots = (SLOTS_PER_STEP * st["iterations"] + SLOTS_PER_PHOTON * st["photons"]
+             + SLOTS_PER_CROSSING * st["layer_crossings"] + SLOTS_PER_DOM_TEST * st["dom_tests"])
+    achieved = slots / avg_s
+    value = n_photons * args.steps / elapsed
+    cfg = ctx.launch_config()
+    out = {
+        "metric": "photons propagated/s on 1 MI355X",
+        "value": value,
+        "unit": "photons/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "full_detector: 86x60 modules, 171 layers with dust bump, "
+                               f"{len(w.sources)} Cherenkov segments x {args.photons_per_source} "
+                               "photons",
+                   "photons_per_step": n_photons, "seed": 0,
+                   "block_size": cfg["block_size"], "chunk_size": args.chunk_size or "auto",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+                     "unit": "T lane-slots/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                     "kernel": "k_propagate", "kernel_ms_avg": avg_s * 1e3},
+        "detail": {"iterations": st["iterations"], "layer_crossings": st["layer_crossings"],
+                   "dom_tests": st["dom_tests"], "hits": st["hits"], "absorbed": st["absorbed"],
+                   "capped": st["capped"], "escaped": st["escaped"],
+                   "iterations_per_photon": st["iterations"] / n_photons,
+                   "kernel_ms": kernel_ms, "lib_kernel_ms_last": st["kernel_ms"],
+                   "hits_fetched_count": n_hits},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_photons_per_source)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,272 @@
+/*
+ * pp.h - C ABI of the MI355X photon-propagation library (libpp).
+ *
+ * The library propagates optical photons from light sources through ice made
+ * of horizontal layers, each with its own absorption and scattering, until
+ * each photon is absorbed or reaches an optical module (DOM), and returns
+ * the hits. This is the GPU stage of the air-shower simulation chain of
+ * Meagher & van Santen, "Parallelizing Air Shower Simulation for Background
+ * Characterization in IceCube": energy losses inside the detector are light
+ * sources (Sec. 2), the ice is split into 10 m layers with their own
+ * scattering and absorption coefficients (Sec. 2), a Monte Carlo draws the
+ * distance to the next scatter and a new direction until the photon hits a
+ * module or is absorbed (Sec. 2), and each hit is stored compactly as the
+ * producing particle's id, the hit time and a weight (Sec. 4, hit-record
+ * paragraph). The paper's photon server takes blocks of light-emitting steps
+ * from many events at once (Sec. 4, propagation-client paragraph); here a
+ * block of sources is one submitted batch.
+ *
+ * Conventions for every entry point:
+ *   - Host pointers are read during the call only; the library copies what
+ *     it keeps. Output pointers are caller-owned. The context owns all device
+ *     memory it allocates.
+ *   - Errors are returned as pp_status; pp_last_error() gives a message.
+ *     Nothing throws across the ABI.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Units: metres, nanoseconds, nanometres. z points up.
+ *   - Results depend only on (seed, event_id, photon_index, inputs): never on
+ *     batch composition, launch configuration or hardware scheduling.
+ *     Randomness is Philox4x32-10 (Salmon et al., SC'11) with key = seed and
+ *     counter = (block k, event_id, photon_index low, high); block 0 is
+ *     emission, block 2 + j is propagation step j.
+ */
+#ifndef PP_H_
+#define PP_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pp_context pp_context;
+
+typedef enum {
+  PP_OK = 0,
+  PP_EINVAL = -1,  /* invalid argument or input value */
+  PP_ENOMEM = -2,  /* device or host allocation failed */
+  PP_EDEVICE = -3, /* HIP runtime error, or no device on this context */
+  PP_ESTATE = -4,  /* call out of order (e.g. submit before loading ice) */
+  PP_ETRUNC = -5   /* output buffer smaller than the result; *n_total set */
+} pp_status;
+
+/* Ice model (Sec. 2: 10 m layers with their own scattering and absorption).
+ * Layer i covers z in [z_lo_m + i dz_m, z_lo_m + (i+1) dz_m); layer 0 is the
+ * lowest and the two edge layers extend to infinity. A photon's layer is
+ * taken from its z once, at emission, and then changed only by crossings. */
+typedef struct {
+  float z_lo_m;      /* bottom of layer 0 */
+  float dz_m;        /* layer thickness, > 0 */
+  uint32_t n_layers; /* 1 .. 1024 */
+  float n_group;     /* group refractive index: time advances by path * n_group / c */
+} pp_ice_header;
+
+typedef struct {
+  float abs_len_m;      /* absorption length lambda_a > 0 (+inf: no absorption) */
+  float eff_scat_len_m; /* effective scattering length lambda_e = lambda_s / (1 - g) > 0
+                           (+inf: no scattering) */
+  float g;              /* Henyey-Greenstein mean cosine, -1 < g < 1 */
+} pp_ice_layer;
+
+/* Optical module: a sphere of the geometry's common radius. The module id of
+ * row k of the array passed to pp_load_geometry is k. Modules sharing a
+ * string_id form a string (a near-vertical line); (string_id, om_index)
+ * pairs must be unique. */
+typedef struct {
+  float x, y, z;
+  uint32_t string_id;
+  uint32_t om_index;
+} pp_dom;
+
+enum { PP_SOURCE_POINT = 0, PP_SOURCE_CHERENKOV = 1 };
+
+/* Light source (Sec. 2: energy losses in the detector are the light sources).
+ *   PP_SOURCE_POINT: isotropic emission from (x, y, z) at t0_ns; direction,
+ *     length and cherenkov_deg are ignored.
+ *   PP_SOURCE_CHERENKOV: a straight track segment from (x, y, z) along the
+ *     unit vector (dx, dy, dz) (|d| within 1e-3 of 1; renormalised) of
+ *     length_m, travelled at the speed of light from t0_ns; photons leave at
+ *     cherenkov_deg to the track, from a point uniform along it.
+ * Wavelengths: lambda_min_nm == lambda_max_nm gives that fixed wavelength,
+ * otherwise a density proportional to 1/lambda^2 on [min, max].
+ * Photons of a source get photon indices first_photon_index ..
+ * first_photon_index + n_photons - 1 within event event_id; index ranges of
+ * one event must not overlap within a batch. n_photons == 0 is allowed. */
+typedef struct {
+  uint32_t type;
+  uint32_t event_id;
+  uint32_t particle_id;
+  uint32_t reserved0;
+  float x, y, z;
+  float dx, dy, dz;
+  float t0_ns;
+  float length_m;
+  float cherenkov_deg;
+  float lambda_min_nm;
+  float lambda_max_nm;
+  float reserved1;
+  uint64_t n_photons;
+  uint64_t first_photon_index;
+} pp_source; /* 80 bytes */
+
+/* Hit (Sec. 4: the compact record keeps the producing particle's id, the
+ * hit time and a weight; the event id, photon index and module id identify
+ * it). weight is 1: the paper gives no photoelectron-probability formula. */
+typedef struct {
+  uint64_t photon_index;
+  uint32_t event_id;
+  uint32_t particle_id;
+  uint32_t dom_id;
+  float time_ns;
+  float weight;
+  uint32_t reserved;
+} pp_hit; /* 32 bytes */
+
+enum { PP_FATE_ABSORBED = 0, PP_FATE_HIT = 1, PP_FATE_CAPPED = 2, PP_FATE_ESCAPED = 3 };
+
+/* Per-photon terminal record, for parity checks only (Sec. 4 calls such
+ * diagnostic records useful for debugging and unnecessary in production, so
+ * they are off by default). Position and direction are those at the end: the
+ * hit point, the absorption point, the point after the last capped step, or
+ * for an escaping photon the start of its infinite last step. */
+typedef struct {
+  uint32_t fate;   /* PP_FATE_* */
+  uint32_t dom_id; /* hit module, 0xFFFFFFFF otherwise */
+  uint32_t n_iter; /* propagation steps taken */
+  uint32_t n_cross;/* layer boundaries crossed */
+  float time_ns;
+  float x, y, z;
+  float vx, vy, vz;
+  float wavelength_nm;
+} pp_photon_record; /* 48 bytes */
+
+typedef struct {
+  uint64_t photons;         /* photons emitted */
+  uint64_t iterations;      /* propagation steps */
+  uint64_t layer_crossings;
+  uint64_t dom_tests;       /* ray-sphere tests performed */
+  uint64_t hits, absorbed, capped, escaped;
+  float kernel_ms;          /* device time of the propagation kernel */
+  uint32_t reserved;
+} pp_stats;
+
+/* Launch parameters. They change speed only, never results. Zero picks the
+ * default. */
+typedef struct {
+  uint32_t block_size;  /* threads per workgroup, multiple of 64, <= 1024 (default 256) */
+  uint32_t chunk_size;  /* photon ids taken per queue grab by one wavefront (default 1024) */
+  uint32_t grid_blocks; /* workgroups launched (default: enough to fill every CU) */
+  uint32_t reserved;
+  uint64_t hit_capacity;/* initial device hit-buffer size in hits (default from photons) */
+} pp_launch_config;
+
+typedef struct {
+  uint32_t n_doms, n_strings;
+  uint32_t grid_nx, grid_ny;
+  float grid_x0_m, grid_y0_m, cell_m;
+  float max_reach_m; /* largest horizontal DOM offset from its string centre + radius */
+} pp_geometry_info;
+
+/* Creates a context on HIP device hip_device (>= 0) with the given Philox
+ * seed. hip_device == -1 creates a host-only context: loading and
+ * submission work (validation, geometry indexing) but device calls return
+ * PP_EDEVICE. *out receives the context; on failure *out is NULL. */
+pp_status pp_create(int hip_device, uint64_t seed, pp_context **out);
+
+/* Frees the context and all its device memory; NULL is a no-op. Synchronises
+ * the streams of pending batches first. */
+void pp_destroy(pp_context *ctx);
+
+/* Message of the last error on ctx (NULL ctx: last pp_create failure).
+ * Valid until the next call on ctx. */
+const char *pp_last_error(const pp_context *ctx);
+
+/* Sets / reads launch parameters for later pp_propagate calls. PP_EINVAL
+ * on a block size that is not a multiple of 64 in 64..1024. */
+pp_status pp_set_launch_config(pp_context *ctx, const pp_launch_config *cfg);
+pp_status pp_get_launch_config(const pp_context *ctx, pp_launch_config *cfg);
+
+/* Number of propagation steps after which a photon stops as
+ * PP_FATE_CAPPED (default 100000; 0 stops every photon at emission). Unlike
+ * the launch parameters this changes results. At most 2^31. */
+pp_status pp_set_step_cap(pp_context *ctx, uint64_t step_cap);
+
+/* Loads (replaces) the layered ice model; copies it. layers has
+ * header->n_layers entries, index 0 lowest. PP_EINVAL on non-finite header
+ * values, dz <= 0, n_group <= 0, lengths <= 0 or NaN, g outside (-1, 1), or
+ * n_layers outside 1..1024. */
+pp_status pp_load_ice(pp_context *ctx, const pp_ice_header *header, const pp_ice_layer *layers);
+
+/* Loads (replaces) the module geometry (5160 modules between 1450 m and
+ * 2450 m depth in the paper's detector, Sec. 1), copies it, and builds the
+ * string table and horizontal search grid used to find candidate modules.
+ * n_doms 0 .. 2^24, at most 512 strings; dom_radius_m > 0. PP_EINVAL on
+ * non-finite coordinates or duplicate (string_id, om_index). */
+pp_status pp_load_geometry(pp_context *ctx, const pp_dom *doms, uint32_t n_doms,
+                           float dom_radius_m);
+pp_status pp_get_geometry_info(const pp_context *ctx, pp_geometry_info *out);
+
+/* Host-side query of the search grid at (x, y): the string tested for every
+ * photon in that cell (0xFFFFFFFF if none) and a lower bound on the
+ * horizontal distance from any point of the cell to any other string's
+ * reach (+inf if none). For tests of the grid's conservativeness. */
+pp_status pp_geometry_cell(const pp_context *ctx, float x, float y, uint32_t *nearest_string,
+                           float *clearance_m);
+
+/* Submits a batch of n_sources light sources (a block of light-emitting
+ * steps, Sec. 4); copies and validates them, uploads them to the device and
+ * returns a batch handle in *batch_out. Needs ice and geometry loaded
+ * (PP_ESTATE otherwise). PP_EINVAL on a bad type, non-finite values, a
+ * non-unit direction, lambda_min > lambda_max or <= 0, index overflow, or
+ * overlapping photon-index ranges within one event. */
+pp_status pp_submit(pp_context *ctx, const pp_source *sources, uint32_t n_sources,
+                    uint64_t *batch_out);
+
+/* Frees a batch's device memory. */
+pp_status pp_release(pp_context *ctx, uint64_t batch);
+
+/* Turns per-photon terminal records on or off for later pp_propagate calls
+ * (48 bytes of device memory per photon). */
+pp_status pp_set_debug_records(pp_context *ctx, int on);
+
+/* Propagates every photon of the batch: one persistent kernel on hip_stream
+ * (a hipStream_t; NULL is the null stream), asynchronous. Ice, geometry and
+ * sources are already resident on the device. May be called again on the
+ * same batch; the result is the same. */
+pp_status pp_propagate(pp_context *ctx, uint64_t batch, void *hip_stream);
+
+/* Number of hits (synchronises the batch's stream). If the device hit buffer
+ * overflowed, the batch is propagated again with a large enough buffer
+ * first; the rerun gives the same hits. */
+pp_status pp_hit_count(pp_context *ctx, uint64_t batch, uint64_t *n_total);
+
+/* Copies up to cap hits into host memory out (order unspecified) and sets
+ * *n_total. Returns PP_ETRUNC if n_total > cap (cap hits copied). */
+pp_status pp_fetch_hits(pp_context *ctx, uint64_t batch, pp_hit *out, uint64_t cap,
+                        uint64_t *n_total);
+
+/* Same, into device memory dev_out (e.g. a torch tensor's data_ptr), copied
+ * on hip_stream. */
+pp_status pp_fetch_hits_device(pp_context *ctx, uint64_t batch, void *dev_out, uint64_t cap,
+                               uint64_t *n_total, void *hip_stream);
+
+/* Per-module hit counts: writes n_doms uint32 counts into device memory
+ * dev_counts on hip_stream, from the batch's hits on the device, without
+ * synchronising. Needs a complete hit buffer: call after pp_hit_count if the
+ * buffer may have overflowed (the counts then cover every hit). */
+pp_status pp_dom_counts(pp_context *ctx, uint64_t batch, uint32_t *dev_counts, void *hip_stream);
+
+/* Copies terminal records first .. first + count - 1 of the batch (photons
+ * numbered in submission order: source by source, index by index) into
+ * host memory out. Needs debug records on when the batch was propagated. */
+pp_status pp_fetch_records(pp_context *ctx, uint64_t batch, pp_photon_record *out,
+                           uint64_t first, uint64_t count);
+
+/* Counters and kernel time of the batch's last propagation (synchronises). */
+pp_status pp_get_stats(pp_context *ctx, uint64_t batch, pp_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PP_H_ */

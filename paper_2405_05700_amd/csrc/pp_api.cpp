@@ -1,0 +1,809 @@
+// Host side of the C ABI declared in include/pp.h: validation, geometry
+// indexing (string table and horizontal search grid), device memory, the
+// photon work queue and kernel launches.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/pp.h"
+#include "pp_device.h"
+
+namespace {
+
+constexpr uint32_t kMaxLayers = 1024;
+constexpr uint32_t kMaxStrings = 512;
+constexpr uint32_t kGridSide = 64;  // at most 64 x 64 cells
+constexpr double kGridMargin = 1.0;
+constexpr double kClearanceMargin = 0.02;
+constexpr uint64_t kDefaultStepCap = 100000;
+
+std::string g_create_error;
+
+struct Batch {
+  std::vector<pp::DevSource> src;
+  uint64_t n_photons = 0;
+  pp::DevSource *d_src = nullptr;
+  pp::DevChunk *d_chunks = nullptr;
+  uint32_t n_chunks = 0, chunk_size = 0;
+  unsigned long long *d_counters = nullptr;
+  pp::DevHit *d_hits = nullptr;
+  uint64_t hit_cap = 0;
+  void *d_rec = nullptr;
+  pp::Records rec{};
+  bool propagated = false, rec_valid = false;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  pp_launch_config used{};
+};
+
+}  // namespace
+
+struct pp_context {
+  int device = -1;
+  uint64_t seed = 0;
+  std::string err;
+  pp_launch_config cfg{};
+  uint64_t step_cap = kDefaultStepCap;
+  bool records = false;
+  int n_cu = 0;
+  // ice
+  bool ice_loaded = false;
+  pp_ice_header ice{};
+  std::vector<pp::DevLayer> layers;
+  pp::DevLayer *d_layers = nullptr;
+  // geometry
+  bool geo_loaded = false;
+  uint32_t n_doms = 0;
+  float radius = 0;
+  std::vector<pp::DevString> strings;
+  std::vector<uint32_t> cells;
+  std::vector<float4> doms_sorted;
+  pp_geometry_info geo{};
+  pp::DevString *d_strings = nullptr;
+  uint32_t *d_cells = nullptr;
+  float4 *d_doms = nullptr;
+  // batches
+  std::map<uint64_t, Batch> batches;
+  uint64_t next_batch = 1;
+};
+
+namespace {
+
+pp_status fail(pp_context *ctx, pp_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  ctx->err = buf;
+  return st;
+}
+
+#define PP_HIP(ctx, expr)                                                                   \
+  do {                                                                                      \
+    const hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                                   \
+      return fail((ctx), e_ == hipErrorOutOfMemory ? PP_ENOMEM : PP_EDEVICE, "%s: %s", #expr, \
+                  hipGetErrorString(e_));                                                   \
+  } while (0)
+
+bool finite(float v) { return std::isfinite(v); }
+
+pp_status need_device(pp_context *ctx) {
+  if (ctx->device < 0) return fail(ctx, PP_EDEVICE, "host-only context has no device");
+  PP_HIP(ctx, hipSetDevice(ctx->device));
+  return PP_OK;
+}
+
+template <class T>
+pp_status upload(pp_context *ctx, T **dptr, const std::vector<T> &host) {
+  if (*dptr) {
+    (void)hipFree(*dptr);
+    *dptr = nullptr;
+  }
+  if (host.empty()) return PP_OK;
+  PP_HIP(ctx, hipMalloc(reinterpret_cast<void **>(dptr), sizeof(T) * host.size()));
+  PP_HIP(ctx, hipMemcpy(*dptr, host.data(), sizeof(T) * host.size(), hipMemcpyHostToDevice));
+  return PP_OK;
+}
+
+void free_batch(Batch &b) {
+  if (b.ev1) (void)hipEventSynchronize(b.ev1);
+  (void)hipFree(b.d_src);
+  (void)hipFree(b.d_chunks);
+  (void)hipFree(b.d_counters);
+  (void)hipFree(b.d_hits);
+  (void)hipFree(b.d_rec);
+  if (b.ev0) (void)hipEventDestroy(b.ev0);
+  if (b.ev1) (void)hipEventDestroy(b.ev1);
+  b = Batch{};
+}
+
+pp_status find_batch(pp_context *ctx, uint64_t id, Batch **out) {
+  auto it = ctx->batches.find(id);
+  if (it == ctx->batches.end()) return fail(ctx, PP_EINVAL, "unknown batch %llu", (unsigned long long)id);
+  *out = &it->second;
+  return PP_OK;
+}
+
+uint32_t default_block() { return 256; }
+uint32_t default_chunk() { return 1024; }
+
+// Horizontal distance from the rectangle [x0,x1] x [y0,y1] to the point.
+double rect_point_distance(double x0, double x1, double y0, double y1, double px, double py) {
+  const double dx = px < x0 ? x0 - px : (px > x1 ? px - x1 : 0.0);
+  const double dy = py < y0 ? y0 - py : (py > y1 ? py - y1 : 0.0);
+  return std::hypot(dx, dy);
+}
+
+// Builds the string table, the z-sorted module array and the search grid.
+// Grid cell word: low 16 bits = the string nearest to the cell (tested for
+// every photon starting there), high 16 bits = floor(16 * (clearance -
+// margin)), where clearance is a lower bound on the horizontal distance
+// from any point of the cell to the reach cylinder of any other string
+// (0xFFFF = no other string).
+void build_geometry(pp_context *ctx, const pp_dom *doms, uint32_t n, float radius,
+                    const std::vector<uint32_t> &string_keys) {
+  ctx->strings.clear();
+  ctx->cells.clear();
+  ctx->doms_sorted.clear();
+  std::map<uint32_t, std::vector<uint32_t>> by_string;
+  for (uint32_t k = 0; k < n; ++k) by_string[doms[k].string_id].push_back(k);
+  std::vector<double> cx, cy, reach;
+  for (auto &kv : by_string) {
+    std::vector<uint32_t> &ids = kv.second;
+    std::sort(ids.begin(), ids.end(), [&](uint32_t a, uint32_t b) {
+      return doms[a].z < doms[b].z || (doms[a].z == doms[b].z && a < b);
+    });
+    double sx = 0, sy = 0;
+    for (uint32_t k : ids) sx += doms[k].x, sy += doms[k].y;
+    sx /= ids.size();
+    sy /= ids.size();
+    double rmax = 0;
+    for (uint32_t k : ids) rmax = std::max(rmax, std::hypot(doms[k].x - sx, doms[k].y - sy));
+    const double rch = rmax + radius;
+    pp::DevString st{};
+    const int m = static_cast<int>(ids.size());
+    const double z0 = doms[ids[0]].z;
+    st.first = static_cast<int>(ctx->doms_sorted.size());
+    st.n = m;
+    st.inv_dz = 0.0f;
+    st.kpad = static_cast<float>(m);
+    if (m >= 2) {
+      const double dz = (static_cast<double>(doms[ids[m - 1]].z) - z0) / (m - 1);
+      double tol = 0;
+      for (int k = 0; k < m; ++k)
+        tol = std::max(tol, std::fabs(doms[ids[k]].z - (z0 + k * dz)));
+      if (dz > 0 && tol <= 0.25 * dz) {
+        st.inv_dz = static_cast<float>(1.0 / dz);
+        st.kpad = static_cast<float>(tol / dz + 1.0);
+      }
+    }
+    st.xy_reach_z0 = make_float4(static_cast<float>(sx), static_cast<float>(sy),
+                                 static_cast<float>(rch), static_cast<float>(z0));
+    for (uint32_t k : ids) {
+      uint32_t bits = k;
+      float fid;
+      std::memcpy(&fid, &bits, 4);
+      ctx->doms_sorted.push_back(make_float4(doms[k].x, doms[k].y, doms[k].z, fid));
+    }
+    ctx->strings.push_back(st);
+    cx.push_back(sx);
+    cy.push_back(sy);
+    reach.push_back(rch);
+  }
+  (void)string_keys;
+  const size_t S = ctx->strings.size();
+  pp_geometry_info &gi = ctx->geo;
+  gi = pp_geometry_info{};
+  gi.n_doms = n;
+  gi.n_strings = static_cast<uint32_t>(S);
+  double max_reach = 0;
+  for (double r : reach) max_reach = std::max(max_reach, r);
+  gi.max_reach_m = static_cast<float>(max_reach);
+  if (S == 0) {
+    gi.grid_nx = gi.grid_ny = 1;
+    gi.cell_m = 1.0f;
+    ctx->cells.push_back(0xFFFFFFFFu);
+    return;
+  }
+  double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+  for (size_t s = 0; s < S; ++s) {
+    x0 = std::min(x0, cx[s] - reach[s]);
+    x1 = std::max(x1, cx[s] + reach[s]);
+    y0 = std::min(y0, cy[s] - reach[s]);
+    y1 = std::max(y1, cy[s] + reach[s]);
+  }
+  x0 -= kGridMargin, x1 += kGridMargin, y0 -= kGridMargin, y1 += kGridMargin;
+  const double cell = std::max(std::max(x1 - x0, y1 - y0) / kGridSide, 1.0);
+  const uint32_t nx = std::min<uint32_t>(kGridSide, static_cast<uint32_t>(std::ceil((x1 - x0) / cell)));
+  const uint32_t ny = std::min<uint32_t>(kGridSide, static_cast<uint32_t>(std::ceil((y1 - y0) / cell)));
+  // The grid origin and cell are rounded to float first so that the host
+  // cell rectangles are the ones the kernel indexes.
+  const float fx0 = static_cast<float>(x0), fy0 = static_cast<float>(y0);
+  const float fcell = static_cast<float>(cell);
+  gi.grid_nx = nx;
+  gi.grid_ny = ny;
+  gi.grid_x0_m = fx0;
+  gi.grid_y0_m = fy0;
+  gi.cell_m = fcell;
+  ctx->cells.assign(static_cast<size_t>(nx) * ny, 0);
+  for (uint32_t iy = 0; iy < ny; ++iy) {
+    for (uint32_t ix = 0; ix < nx; ++ix) {
+      const double rx0 = fx0 + static_cast<double>(fcell) * ix, rx1 = rx0 + fcell;
+      const double ry0 = fy0 + static_cast<double>(fcell) * iy, ry1 = ry0 + fcell;
+      double best = std::numeric_limits<double>::infinity(), second = best;
+      uint32_t s1 = 0;
+      for (size_t s = 0; s < S; ++s) {
+        const double d = std::max(0.0, rect_point_distance(rx0, rx1, ry0, ry1, cx[s], cy[s]) - reach[s]);
+        if (d < best) {
+          second = best;
+          best = d;
+          s1 = static_cast<uint32_t>(s);
+        } else if (d < second) {
+          second = d;
+        }
+      }
+      uint32_t q = 0xFFFFu;
+      if (std::isfinite(second)) {
+        const double v = std::floor((second - kClearanceMargin) * 16.0);
+        q = v <= 0 ? 0u : static_cast<uint32_t>(std::min(v, 65534.0));
+      }
+      ctx->cells[static_cast<size_t>(iy) * nx + ix] = (q << 16) | s1;
+    }
+  }
+}
+
+pp_status build_chunks(pp_context *ctx, Batch &b, uint32_t chunk) {
+  if (b.d_chunks && b.chunk_size == chunk) return PP_OK;
+  std::vector<pp::DevChunk> ch;
+  for (uint32_t s = 0; s < b.src.size(); ++s) {
+    const uint64_t begin = b.src[s].seq_base;
+    const uint64_t total = (s + 1 < b.src.size() ? b.src[s + 1].seq_base : b.n_photons) - begin;
+    for (uint64_t l = 0; l < total; l += chunk) {
+      pp::DevChunk c{};
+      c.src = s;
+      c.count = static_cast<uint32_t>(std::min<uint64_t>(chunk, total - l));
+      c.local = l;
+      ch.push_back(c);
+    }
+  }
+  if (ch.size() >= 0xFFFFFFFFull) return fail(ctx, PP_EINVAL, "too many work chunks; raise chunk_size");
+  pp_status st = upload(ctx, &b.d_chunks, ch);
+  if (st != PP_OK) return st;
+  b.n_chunks = static_cast<uint32_t>(ch.size());
+  b.chunk_size = chunk;
+  return PP_OK;
+}
+
+pp_status alloc_hits(pp_context *ctx, Batch &b, uint64_t cap) {
+  (void)hipFree(b.d_hits);
+  b.d_hits = nullptr;
+  b.hit_cap = 0;
+  PP_HIP(ctx, hipMalloc(reinterpret_cast<void **>(&b.d_hits), sizeof(pp::DevHit) * std::max<uint64_t>(cap, 1)));
+  b.hit_cap = cap;
+  return PP_OK;
+}
+
+pp_status alloc_records(pp_context *ctx, Batch &b) {
+  if (b.d_rec) return PP_OK;
+  const uint64_t n = std::max<uint64_t>(b.n_photons, 1);
+  PP_HIP(ctx, hipMalloc(&b.d_rec, 48 * n));
+  char *base = static_cast<char *>(b.d_rec);
+  uint32_t **u[] = {&b.rec.fate, &b.rec.dom, &b.rec.n_iter, &b.rec.n_cross};
+  float **f[] = {&b.rec.t, &b.rec.x, &b.rec.y, &b.rec.z, &b.rec.vx, &b.rec.vy, &b.rec.vz, &b.rec.wavelength};
+  for (int i = 0; i < 4; ++i) *u[i] = reinterpret_cast<uint32_t *>(base + 4 * n * i);
+  for (int i = 0; i < 8; ++i) *f[i] = reinterpret_cast<float *>(base + 4 * n * (4 + i));
+  return PP_OK;
+}
+
+pp_status launch(pp_context *ctx, Batch &b, hipStream_t stream) {
+  const pp_launch_config &c = ctx->cfg;
+  const uint32_t block = c.block_size ? c.block_size : default_block();
+  const size_t lds = pp::propagate_lds_bytes(static_cast<int>(ctx->ice.n_layers),
+                                             static_cast<int>(ctx->strings.size()),
+                                             static_cast<int>(ctx->geo.grid_nx * ctx->geo.grid_ny));
+  uint32_t grid = c.grid_blocks;
+  if (grid == 0) {
+    int per_cu = 0;
+    PP_HIP(ctx, pp::propagate_occupancy(static_cast<int>(block), lds, &per_cu));
+    grid = static_cast<uint32_t>(std::max(per_cu, 1) * std::max(ctx->n_cu, 1));
+  }
+  // Default chunk: 1024 ids, smaller for small batches so that every
+  // resident wavefront gets several chunks.
+  uint32_t chunk = c.chunk_size;
+  if (chunk == 0) {
+    const uint64_t waves = static_cast<uint64_t>(grid) * (block / 64);
+    chunk = static_cast<uint32_t>(std::min<uint64_t>(default_chunk(),
+                                                     std::max<uint64_t>(64, b.n_photons / (waves * 8) + 1)));
+  }
+  pp_status st = build_chunks(ctx, b, chunk);
+  if (st != PP_OK) return st;
+  // no more workgroups than there are chunks to share among their wavefronts
+  grid = static_cast<uint32_t>(std::min<uint64_t>(
+      grid, std::max<uint64_t>(1, (static_cast<uint64_t>(b.n_chunks) * 64 + block - 1) / block)));
+  if (!b.d_counters)
+    PP_HIP(ctx, hipMalloc(reinterpret_cast<void **>(&b.d_counters), sizeof(unsigned long long) * pp::kNumCounters));
+  if (!b.d_hits) {
+    const uint64_t cap = c.hit_capacity ? c.hit_capacity : std::max<uint64_t>(65536, b.n_photons / 64);
+    st = alloc_hits(ctx, b, cap);
+    if (st != PP_OK) return st;
+  }
+  if (ctx->records) {
+    st = alloc_records(ctx, b);
+    if (st != PP_OK) return st;
+  }
+  if (!b.ev0) PP_HIP(ctx, hipEventCreate(&b.ev0));
+  if (!b.ev1) PP_HIP(ctx, hipEventCreate(&b.ev1));
+
+  pp::PropagateArgs a{};
+  a.layers = ctx->d_layers;
+  a.n_layers = static_cast<int>(ctx->ice.n_layers);
+  a.z_lo = ctx->ice.z_lo_m;
+  a.dz = ctx->ice.dz_m;
+  a.inv_dz = 1.0f / ctx->ice.dz_m;
+  a.time_per_m = static_cast<float>(static_cast<double>(ctx->ice.n_group) / 0.299792458);
+  a.strings = ctx->d_strings;
+  a.n_strings = static_cast<int>(ctx->strings.size());
+  a.cells = ctx->d_cells;
+  a.nx = static_cast<int>(ctx->geo.grid_nx);
+  a.ny = static_cast<int>(ctx->geo.grid_ny);
+  a.gx0 = ctx->geo.grid_x0_m;
+  a.gy0 = ctx->geo.grid_y0_m;
+  a.inv_cell = 1.0f / ctx->geo.cell_m;
+  a.doms = ctx->d_doms;
+  a.radius = ctx->radius;
+  a.radius2 = ctx->radius * ctx->radius;
+  a.sources = b.d_src;
+  a.chunks = b.d_chunks;
+  a.n_chunks = b.n_chunks;
+  a.seed_lo = static_cast<uint32_t>(ctx->seed);
+  a.seed_hi = static_cast<uint32_t>(ctx->seed >> 32);
+  a.step_cap = static_cast<uint32_t>(ctx->step_cap);
+  a.counters = b.d_counters;
+  a.hits = b.d_hits;
+  a.hit_capacity = b.hit_cap;
+  if (ctx->records) a.rec = b.rec;
+
+  PP_HIP(ctx, pp::launch_reset(b.d_counters, pp::kNumCounters, stream));
+  PP_HIP(ctx, hipEventRecord(b.ev0, stream));
+  if (b.n_chunks > 0) PP_HIP(ctx, pp::launch_propagate(a, static_cast<int>(grid), static_cast<int>(block), stream));
+  PP_HIP(ctx, hipEventRecord(b.ev1, stream));
+  b.stream = stream;
+  b.propagated = true;
+  b.rec_valid = ctx->records;
+  b.used = c;
+  b.used.block_size = block;
+  b.used.chunk_size = chunk;
+  b.used.grid_blocks = grid;
+  b.used.hit_capacity = b.hit_cap;
+  return PP_OK;
+}
+
+pp_status sync_counters(pp_context *ctx, Batch &b, unsigned long long *host) {
+  if (!b.propagated) return fail(ctx, PP_ESTATE, "batch not propagated");
+  PP_HIP(ctx, hipEventSynchronize(b.ev1));
+  PP_HIP(ctx, hipMemcpy(host, b.d_counters, sizeof(unsigned long long) * pp::kNumCounters,
+                        hipMemcpyDeviceToHost));
+  return PP_OK;
+}
+
+// Makes sure the device hit buffer holds every hit of the batch (rerunning
+// with a larger buffer if it overflowed) and returns the hit count.
+pp_status complete_hits(pp_context *ctx, Batch &b, uint64_t *n_total) {
+  unsigned long long cnt[pp::kNumCounters];
+  pp_status st = sync_counters(ctx, b, cnt);
+  if (st != PP_OK) return st;
+  if (cnt[pp::kHitCount] > b.hit_cap) {
+    const uint64_t need = cnt[pp::kHitCount];
+    st = alloc_hits(ctx, b, need + need / 8 + 1024);
+    if (st != PP_OK) return st;
+    const pp_launch_config saved = ctx->cfg;
+    const bool saved_rec = ctx->records;
+    ctx->cfg = b.used;
+    ctx->cfg.hit_capacity = 0;
+    ctx->records = b.rec_valid;
+    st = launch(ctx, b, b.stream);
+    ctx->cfg = saved;
+    ctx->records = saved_rec;
+    if (st != PP_OK) return st;
+    st = sync_counters(ctx, b, cnt);
+    if (st != PP_OK) return st;
+    if (cnt[pp::kHitCount] != need)
+      return fail(ctx, PP_EDEVICE, "rerun after hit-buffer overflow gave %llu hits, expected %llu",
+                  cnt[pp::kHitCount], (unsigned long long)need);
+  }
+  *n_total = cnt[pp::kHitCount];
+  return PP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pp_status pp_create(int hip_device, uint64_t seed, pp_context **out) {
+  if (!out) return PP_EINVAL;
+  *out = nullptr;
+  if (hip_device < -1) {
+    g_create_error = "hip_device must be >= -1";
+    return PP_EINVAL;
+  }
+  pp_context *ctx = new (std::nothrow) pp_context;
+  if (!ctx) return PP_ENOMEM;
+  ctx->device = hip_device;
+  ctx->seed = seed;
+  if (hip_device >= 0) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || hip_device >= count) {
+      g_create_error = std::string("no HIP device ") + std::to_string(hip_device) + ": " +
+                       (e != hipSuccess ? hipGetErrorString(e) : "index out of range");
+      delete ctx;
+      return PP_EDEVICE;
+    }
+    hipDeviceProp_t prop;
+    e = hipSetDevice(hip_device);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, hip_device);
+    if (e != hipSuccess) {
+      g_create_error = hipGetErrorString(e);
+      delete ctx;
+      return PP_EDEVICE;
+    }
+    ctx->n_cu = prop.multiProcessorCount;
+  }
+  *out = ctx;
+  return PP_OK;
+}
+
+void pp_destroy(pp_context *ctx) {
+  if (!ctx) return;
+  if (ctx->device >= 0) {
+    (void)hipSetDevice(ctx->device);
+    for (auto &kv : ctx->batches) free_batch(kv.second);
+    (void)hipFree(ctx->d_layers);
+    (void)hipFree(ctx->d_strings);
+    (void)hipFree(ctx->d_cells);
+    (void)hipFree(ctx->d_doms);
+  }
+  delete ctx;
+}
+
+const char *pp_last_error(const pp_context *ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+pp_status pp_set_launch_config(pp_context *ctx, const pp_launch_config *cfg) {
+  if (!ctx || !cfg) return PP_EINVAL;
+  if (cfg->block_size != 0 && (cfg->block_size % 64 != 0 || cfg->block_size > 1024))
+    return fail(ctx, PP_EINVAL, "block_size must be a multiple of 64 in 64..1024");
+  ctx->cfg = *cfg;
+  return PP_OK;
+}
+
+pp_status pp_get_launch_config(const pp_context *ctx, pp_launch_config *cfg) {
+  if (!ctx || !cfg) return PP_EINVAL;
+  *cfg = ctx->cfg;
+  if (!cfg->block_size) cfg->block_size = default_block();
+  if (!cfg->chunk_size) cfg->chunk_size = default_chunk();
+  return PP_OK;
+}
+
+pp_status pp_set_step_cap(pp_context *ctx, uint64_t step_cap) {
+  if (!ctx) return PP_EINVAL;
+  if (step_cap > (1ull << 31)) return fail(ctx, PP_EINVAL, "step_cap above 2^31");
+  ctx->step_cap = step_cap;
+  return PP_OK;
+}
+
+pp_status pp_set_debug_records(pp_context *ctx, int on) {
+  if (!ctx) return PP_EINVAL;
+  ctx->records = on != 0;
+  return PP_OK;
+}
+
+pp_status pp_load_ice(pp_context *ctx, const pp_ice_header *h, const pp_ice_layer *layers) {
+  if (!ctx || !h || (!layers && h->n_layers)) return ctx ? fail(ctx, PP_EINVAL, "null argument") : PP_EINVAL;
+  if (h->n_layers < 1 || h->n_layers > kMaxLayers)
+    return fail(ctx, PP_EINVAL, "n_layers %u outside 1..%u", h->n_layers, kMaxLayers);
+  if (!finite(h->z_lo_m) || !finite(h->dz_m) || !(h->dz_m > 0))
+    return fail(ctx, PP_EINVAL, "z_lo_m and dz_m must be finite with dz_m > 0");
+  if (!finite(h->n_group) || !(h->n_group > 0)) return fail(ctx, PP_EINVAL, "n_group must be finite and > 0");
+  std::vector<pp::DevLayer> L(h->n_layers);
+  for (uint32_t i = 0; i < h->n_layers; ++i) {
+    const pp_ice_layer &l = layers[i];
+    if (!(l.abs_len_m > 0) || !(l.eff_scat_len_m > 0))
+      return fail(ctx, PP_EINVAL, "layer %u: lengths must be > 0 (NaN rejected)", i);
+    if (!finite(l.g) || !(l.g > -1.0f && l.g < 1.0f))
+      return fail(ctx, PP_EINVAL, "layer %u: g must lie in (-1, 1)", i);
+    const double g = l.g;
+    const double a = 1.0 / static_cast<double>(l.abs_len_m);
+    const double b = 1.0 / (static_cast<double>(l.eff_scat_len_m) * (1.0 - g));
+    const float inf = std::numeric_limits<float>::infinity();
+    L[i].coef = make_float4(static_cast<float>(a), static_cast<float>(b),
+                            a > 0 ? static_cast<float>(1.0 / a) : inf,
+                            b > 0 ? static_cast<float>(1.0 / b) : inf);
+    L[i].hg = make_float4(static_cast<float>(1.0 - g), static_cast<float>(1.0 - g * g),
+                          static_cast<float>(2.0 * g), 0.0f);
+  }
+  if (ctx->device >= 0) {
+    pp_status st = need_device(ctx);
+    if (st != PP_OK) return st;
+    st = upload(ctx, &ctx->d_layers, L);
+    if (st != PP_OK) return st;
+  }
+  ctx->ice = *h;
+  ctx->layers = std::move(L);
+  ctx->ice_loaded = true;
+  return PP_OK;
+}
+
+pp_status pp_load_geometry(pp_context *ctx, const pp_dom *doms, uint32_t n, float radius) {
+  if (!ctx) return PP_EINVAL;
+  if (n > 0 && !doms) return fail(ctx, PP_EINVAL, "null doms");
+  if (n > (1u << 24)) return fail(ctx, PP_EINVAL, "more than 2^24 modules");
+  if (!finite(radius) || !(radius > 0)) return fail(ctx, PP_EINVAL, "dom_radius_m must be finite and > 0");
+  std::vector<std::pair<uint64_t, uint32_t>> keys(n);
+  std::vector<uint32_t> strings;
+  for (uint32_t k = 0; k < n; ++k) {
+    if (!finite(doms[k].x) || !finite(doms[k].y) || !finite(doms[k].z))
+      return fail(ctx, PP_EINVAL, "module %u: non-finite position", k);
+    keys[k] = {(static_cast<uint64_t>(doms[k].string_id) << 32) | doms[k].om_index, k};
+    strings.push_back(doms[k].string_id);
+  }
+  std::sort(keys.begin(), keys.end());
+  for (uint32_t k = 1; k < n; ++k)
+    if (keys[k].first == keys[k - 1].first)
+      return fail(ctx, PP_EINVAL, "modules %u and %u share (string_id, om_index)", keys[k - 1].second, keys[k].second);
+  std::sort(strings.begin(), strings.end());
+  strings.erase(std::unique(strings.begin(), strings.end()), strings.end());
+  if (strings.size() > kMaxStrings)
+    return fail(ctx, PP_EINVAL, "%zu strings; at most %u", strings.size(), kMaxStrings);
+  build_geometry(ctx, doms, n, radius, strings);
+  ctx->n_doms = n;
+  ctx->radius = radius;
+  if (ctx->device >= 0) {
+    pp_status st = need_device(ctx);
+    if (st != PP_OK) return st;
+    if ((st = upload(ctx, &ctx->d_strings, ctx->strings)) != PP_OK) return st;
+    if ((st = upload(ctx, &ctx->d_cells, ctx->cells)) != PP_OK) return st;
+    if ((st = upload(ctx, &ctx->d_doms, ctx->doms_sorted)) != PP_OK) return st;
+  }
+  ctx->geo_loaded = true;
+  return PP_OK;
+}
+
+pp_status pp_get_geometry_info(const pp_context *ctx, pp_geometry_info *out) {
+  if (!ctx || !out) return PP_EINVAL;
+  if (!ctx->geo_loaded) return PP_ESTATE;
+  *out = ctx->geo;
+  return PP_OK;
+}
+
+pp_status pp_geometry_cell(const pp_context *ctx, float x, float y, uint32_t *nearest, float *clearance) {
+  if (!ctx || !nearest || !clearance) return PP_EINVAL;
+  if (!ctx->geo_loaded) return PP_ESTATE;
+  const pp_geometry_info &g = ctx->geo;
+  const float inv = 1.0f / g.cell_m;
+  const float fx = std::fmin(std::fmax((x - g.grid_x0_m) * inv, 0.0f), static_cast<float>(g.grid_nx - 1));
+  const float fy = std::fmin(std::fmax((y - g.grid_y0_m) * inv, 0.0f), static_cast<float>(g.grid_ny - 1));
+  const uint32_t word = ctx->cells[static_cast<size_t>(fy) * g.grid_nx + static_cast<size_t>(fx)];
+  const uint32_t s1 = word & 0xFFFFu, q = word >> 16;
+  *nearest = s1 == 0xFFFFu ? 0xFFFFFFFFu : s1;
+  *clearance = q == 0xFFFFu ? std::numeric_limits<float>::infinity() : q * 0.0625f;
+  return PP_OK;
+}
+
+pp_status pp_submit(pp_context *ctx, const pp_source *src, uint32_t n, uint64_t *batch_out) {
+  if (!ctx || !batch_out || (n > 0 && !src)) return ctx ? fail(ctx, PP_EINVAL, "null argument") : PP_EINVAL;
+  if (!ctx->ice_loaded || !ctx->geo_loaded) return fail(ctx, PP_ESTATE, "load ice and geometry before submitting");
+  Batch b;
+  b.src.resize(n);
+  uint64_t total = 0;
+  std::vector<std::pair<std::pair<uint32_t, uint64_t>, uint64_t>> ranges;
+  for (uint32_t i = 0; i < n; ++i) {
+    const pp_source &s = src[i];
+    if (s.type != PP_SOURCE_POINT && s.type != PP_SOURCE_CHERENKOV)
+      return fail(ctx, PP_EINVAL, "source %u: unknown type %u", i, s.type);
+    if (!finite(s.x) || !finite(s.y) || !finite(s.z) || !finite(s.t0_ns))
+      return fail(ctx, PP_EINVAL, "source %u: non-finite position or time", i);
+    if (!finite(s.lambda_min_nm) || !finite(s.lambda_max_nm) || !(s.lambda_min_nm > 0) ||
+        s.lambda_min_nm > s.lambda_max_nm)
+      return fail(ctx, PP_EINVAL, "source %u: need 0 < lambda_min <= lambda_max", i);
+    if (s.first_photon_index + s.n_photons < s.first_photon_index)
+      return fail(ctx, PP_EINVAL, "source %u: photon index range overflows", i);
+    if (total + s.n_photons < total) return fail(ctx, PP_EINVAL, "photon count overflows");
+    pp::DevSource &d = b.src[i];
+    double dx = 0, dy = 0, dz = 1, len = 0, om = 0;
+    if (s.type == PP_SOURCE_CHERENKOV) {
+      if (!finite(s.dx) || !finite(s.dy) || !finite(s.dz) || !finite(s.length_m) || !(s.length_m >= 0) ||
+          !finite(s.cherenkov_deg) || !(s.cherenkov_deg > 0 && s.cherenkov_deg < 180))
+        return fail(ctx, PP_EINVAL, "source %u: bad direction, length or Cherenkov angle", i);
+      const double nrm = std::sqrt(static_cast<double>(s.dx) * s.dx + static_cast<double>(s.dy) * s.dy +
+                                   static_cast<double>(s.dz) * s.dz);
+      if (!(std::fabs(nrm - 1.0) <= 1e-3)) return fail(ctx, PP_EINVAL, "source %u: |direction| not within 1e-3 of 1", i);
+      dx = s.dx / nrm, dy = s.dy / nrm, dz = s.dz / nrm;
+      len = s.length_m;
+      const double half = 0.5 * s.cherenkov_deg * M_PI / 180.0;
+      om = 2.0 * std::sin(half) * std::sin(half);  // 1 - cos(angle) without cancellation
+    }
+    d.pos_t0 = make_float4(s.x, s.y, s.z, s.t0_ns);
+    d.dir_len = make_float4(static_cast<float>(dx), static_cast<float>(dy), static_cast<float>(dz),
+                            static_cast<float>(len));
+    const double inv_min = 1.0 / s.lambda_min_nm, inv_max = 1.0 / s.lambda_max_nm;
+    const bool fixed = s.lambda_min_nm == s.lambda_max_nm;
+    d.emit = make_float4(static_cast<float>(om), fixed ? s.lambda_min_nm : 0.0f,
+                         static_cast<float>(inv_min), fixed ? 0.0f : static_cast<float>(inv_min - inv_max));
+    d.ids = make_uint4(s.type, s.event_id, s.particle_id, 0u);
+    d.first_index = s.first_photon_index;
+    d.seq_base = total;
+    total += s.n_photons;
+    if (s.n_photons > 0) ranges.push_back({{s.event_id, s.first_photon_index}, s.n_photons});
+  }
+  std::sort(ranges.begin(), ranges.end());
+  for (size_t i = 1; i < ranges.size(); ++i) {
+    const auto &p = ranges[i - 1], &q = ranges[i];
+    if (p.first.first == q.first.first && q.first.second < p.first.second + p.second)
+      return fail(ctx, PP_EINVAL, "overlapping photon-index ranges in event %u", q.first.first);
+  }
+  b.n_photons = total;
+  if (ctx->device >= 0) {
+    pp_status st = need_device(ctx);
+    if (st != PP_OK) return st;
+    st = upload(ctx, &b.d_src, b.src);
+    if (st != PP_OK) {
+      free_batch(b);
+      return st;
+    }
+  }
+  const uint64_t id = ctx->next_batch++;
+  ctx->batches.emplace(id, std::move(b));
+  *batch_out = id;
+  return PP_OK;
+}
+
+pp_status pp_release(pp_context *ctx, uint64_t batch) {
+  if (!ctx) return PP_EINVAL;
+  Batch *b;
+  pp_status st = find_batch(ctx, batch, &b);
+  if (st != PP_OK) return st;
+  if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
+  free_batch(*b);
+  ctx->batches.erase(batch);
+  return PP_OK;
+}
+
+pp_status pp_propagate(pp_context *ctx, uint64_t batch, void *hip_stream) {
+  if (!ctx) return PP_EINVAL;
+  Batch *b;
+  pp_status st = find_batch(ctx, batch, &b);
+  if (st != PP_OK) return st;
+  if ((st = need_device(ctx)) != PP_OK) return st;
+  return launch(ctx, *b, static_cast<hipStream_t>(hip_stream));
+}
+
+pp_status pp_hit_count(pp_context *ctx, uint64_t batch, uint64_t *n_total) {
+  if (!ctx || !n_total) return PP_EINVAL;
+  Batch *b;
+  pp_status st = find_batch(ctx, batch, &b);
+  if (st != PP_OK) return st;
+  if ((st = need_device(ctx)) != PP_OK) return st;
+  return complete_hits(ctx, *b, n_total);
+}
+
+pp_status pp_fetch_hits(pp_context *ctx, uint64_t batch, pp_hit *out, uint64_t cap, uint64_t *n_total) {
+  if (!ctx || !n_total || (cap > 0 && !out)) return PP_EINVAL;
+  Batch *b;
+  pp_status st = find_batch(ctx, batch, &b);
+  if (st != PP_OK) return st;
+  if ((st = need_device(ctx)) != PP_OK) return st;
+  uint64_t n = 0;
+  if ((st = complete_hits(ctx, *b, &n)) != PP_OK) return st;
+  *n_total = n;
+  const uint64_t m = std::min(n, cap);
+  if (m > 0) PP_HIP(ctx, hipMemcpy(out, b->d_hits, sizeof(pp_hit) * m, hipMemcpyDeviceToHost));
+  return n > cap ? fail(ctx, PP_ETRUNC, "%llu hits, buffer holds %llu", (unsigned long long)n,
+                        (unsigned long long)cap)
+                 : PP_OK;
+}
+
+pp_status pp_fetch_hits_device(pp_context *ctx, uint64_t batch, void *dev_out, uint64_t cap, uint64_t *n_total,
+                               void *hip_stream) {
+  if (!ctx || !n_total || (cap > 0 && !dev_out)) return PP_EINVAL;
+  Batch *b;
+  pp_status st = find_batch(ctx, batch, &b);
+  if (st != PP_OK) return st;
+  if ((st = need_device(ctx)) != PP_OK) return st;
+  uint64_t n = 0;
+  if ((st = complete_hits(ctx, *b, &n)) != PP_OK) return st;
+  *n_total = n;
+  const uint64_t m = std::min(n, cap);
+  if (m > 0)
+    PP_HIP(ctx, hipMemcpyAsync(dev_out, b->d_hits, sizeof(pp_hit) * m, hipMemcpyDeviceToDevice,
+                               static_cast<hipStream_t>(hip_stream)));
+  return n > cap ? fail(ctx, PP_ETRUNC, "%llu hits, buffer holds %llu", (unsigned long long)n,
+                        (unsigned long long)cap)
+                 : PP_OK;
+}
+
+pp_status pp_dom_counts(pp_context *ctx, uint64_t batch, uint32_t *dev_counts, void *hip_stream) {
+  if (!ctx || (!dev_counts && ctx->n_doms > 0)) return PP_EINVAL;
+  Batch *b;
+  pp_status st = find_batch(ctx, batch, &b);
+  if (st != PP_OK) return st;
+  if ((st = need_device(ctx)) != PP_OK) return st;
+  if (!b->propagated) return fail(ctx, PP_ESTATE, "batch not propagated");
+  PP_HIP(ctx, pp::launch_dom_histogram(b->d_hits, b->d_counters + pp::kHitCount, b->hit_cap, dev_counts,
+                                       ctx->n_doms, static_cast<hipStream_t>(hip_stream)));
+  return PP_OK;
+}
+
+pp_status pp_fetch_records(pp_context *ctx, uint64_t batch, pp_photon_record *out, uint64_t first,
+                           uint64_t count) {
+  if (!ctx || (count > 0 && !out)) return PP_EINVAL;
+  Batch *b;
+  pp_status st = find_batch(ctx, batch, &b);
+  if (st != PP_OK) return st;
+  if ((st = need_device(ctx)) != PP_OK) return st;
+  if (!b->propagated || !b->rec_valid) return fail(ctx, PP_ESTATE, "no records: enable them before pp_propagate");
+  if (first > b->n_photons || count > b->n_photons - first) return fail(ctx, PP_EINVAL, "record range out of bounds");
+  PP_HIP(ctx, hipEventSynchronize(b->ev1));
+  std::vector<uint32_t> u(4 * count);
+  std::vector<float> f(8 * count);
+  uint32_t *du[] = {b->rec.fate, b->rec.dom, b->rec.n_iter, b->rec.n_cross};
+  float *df[] = {b->rec.t, b->rec.x, b->rec.y, b->rec.z, b->rec.vx, b->rec.vy, b->rec.vz, b->rec.wavelength};
+  for (int i = 0; i < 4; ++i)
+    PP_HIP(ctx, hipMemcpy(u.data() + i * count, du[i] + first, 4 * count, hipMemcpyDeviceToHost));
+  for (int i = 0; i < 8; ++i)
+    PP_HIP(ctx, hipMemcpy(f.data() + i * count, df[i] + first, 4 * count, hipMemcpyDeviceToHost));
+  for (uint64_t k = 0; k < count; ++k) {
+    pp_photon_record &r = out[k];
+    r.fate = u[k];
+    r.dom_id = u[count + k];
+    r.n_iter = u[2 * count + k];
+    r.n_cross = u[3 * count + k];
+    r.time_ns = f[k];
+    r.x = f[count + k];
+    r.y = f[2 * count + k];
+    r.z = f[3 * count + k];
+    r.vx = f[4 * count + k];
+    r.vy = f[5 * count + k];
+    r.vz = f[6 * count + k];
+    r.wavelength_nm = f[7 * count + k];
+  }
+  return PP_OK;
+}
+
+pp_status pp_get_stats(pp_context *ctx, uint64_t batch, pp_stats *out) {
+  if (!ctx || !out) return PP_EINVAL;
+  Batch *b;
+  pp_status st = find_batch(ctx, batch, &b);
+  if (st != PP_OK) return st;
+  if ((st = need_device(ctx)) != PP_OK) return st;
+  unsigned long long c[pp::kNumCounters];
+  if ((st = sync_counters(ctx, *b, c)) != PP_OK) return st;
+  out->photons = c[pp::kStatPhotons];
+  out->iterations = c[pp::kStatIterations];
+  out->layer_crossings = c[pp::kStatCrossings];
+  out->dom_tests = c[pp::kStatDomTests];
+  out->hits = c[pp::kStatHits];
+  out->absorbed = c[pp::kStatAbsorbed];
+  out->capped = c[pp::kStatCapped];
+  out->escaped = c[pp::kStatEscaped];
+  float ms = 0;
+  PP_HIP(ctx, hipEventElapsedTime(&ms, b->ev0, b->ev1));
+  out->kernel_ms = ms;
+  out->reserved = 0;
+  return PP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Internal interface between the host library (pp_api.cpp) and the gfx950
+// kernels (pp_kernels.hip): device-side table layouts and kernel arguments.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pp {
+
+// Per-layer coefficients, staged into LDS: {a = 1/lambda_a, b = 1/lambda_s,
+// 1/a, 1/b} and the Henyey-Greenstein constants {1 - g, 1 - g^2, 2 g, 0}.
+struct DevLayer {
+  float4 coef;
+  float4 hg;
+};
+
+// Per-string search data, staged into LDS. Modules of string s sit at
+// positions first .. first + n - 1 of the sorted module array, ordered by
+// z. If the string is evenly spaced (spacing 1/inv_dz within a tolerance)
+// the modules a segment can reach are found arithmetically, widened by
+// kpad slots; otherwise inv_dz = 0 and kpad = n cover the whole string.
+struct DevString {
+  float4 xy_reach_z0;  // centre x, centre y, reach (max horizontal offset + r), z of slot 0
+  float inv_dz, kpad;
+  int first, n;
+};
+
+// Light source as the kernel reads it (one record per submitted source).
+struct DevSource {
+  float4 pos_t0;      // start point, emission time
+  float4 dir_len;     // unit direction (+z for point sources), segment length (0 for points)
+  float4 emit;        // 1 - cos(cone angle) (0 for points), fixed wavelength (0 if spread),
+                      // 1/lambda_min, 1/lambda_min - 1/lambda_max
+  uint4 ids;          // type, event id, particle id, 0
+  unsigned long long first_index;  // photon index of local photon 0
+  unsigned long long seq_base;     // submission-order number of local photon 0
+};
+
+// Work queue entry: photons [local, local + count) of source src.
+struct DevChunk {
+  uint32_t src, count;
+  unsigned long long local;
+};
+
+// Device hit record, bit-compatible with pp_hit.
+struct DevHit {
+  unsigned long long photon_index;
+  uint32_t event_id, particle_id, dom_id;
+  float time_ns, weight;
+  uint32_t reserved;
+};
+
+// Counters, zeroed before each propagation.
+enum Counter {
+  kChunkNext = 0,
+  kHitCount,
+  kStatPhotons,
+  kStatIterations,
+  kStatCrossings,
+  kStatDomTests,
+  kStatHits,
+  kStatAbsorbed,
+  kStatCapped,
+  kStatEscaped,
+  kNumCounters
+};
+
+struct Records {  // terminal records, structure of arrays (null if off)
+  uint32_t *fate, *dom, *n_iter, *n_cross;
+  float *t, *x, *y, *z, *vx, *vy, *vz, *wavelength;
+};
+
+struct PropagateArgs {
+  // ice
+  const DevLayer *layers;
+  int n_layers;
+  float z_lo, dz, inv_dz;
+  float time_per_m;  // n_group / c
+  // geometry
+  const DevString *strings;
+  int n_strings;
+  const uint32_t *cells;  // nearest string (low 16 bits, 0xFFFF none) | clearance * 16 (high)
+  int nx, ny;
+  float gx0, gy0, inv_cell;
+  const float4 *doms;  // sorted by string then z: x, y, z, module id (as bits)
+  float radius, radius2;
+  // work
+  const DevSource *sources;
+  const DevChunk *chunks;
+  uint32_t n_chunks;
+  uint32_t seed_lo, seed_hi;
+  uint32_t step_cap;
+  // outputs
+  unsigned long long *counters;
+  DevHit *hits;
+  unsigned long long hit_capacity;
+  Records rec;
+};
+
+// Dynamic LDS bytes the propagation kernel needs for these tables.
+size_t propagate_lds_bytes(int n_layers, int n_strings, int n_cells);
+
+hipError_t launch_reset(unsigned long long *counters, int n, hipStream_t stream);
+hipError_t launch_propagate(const PropagateArgs &args, int grid, int block, hipStream_t stream);
+hipError_t propagate_occupancy(int block, size_t lds_bytes, int *blocks_per_cu);
+hipError_t launch_dom_histogram(const DevHit *hits, const unsigned long long *hit_count,
+                                unsigned long long hit_capacity, uint32_t *counts, uint32_t n_doms,
+                                hipStream_t stream);
+
+}  // namespace pp

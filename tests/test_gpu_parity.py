@@ -1,0 +1,272 @@
+"""GPU parity: the FP32 HIP path against the FP64 oracle, photon by photon.
+
+Both sides draw the same Philox words for the same (seed, event, photon
+index), so each photon's fate, module id and step count must agree exactly
+and its time within 1e-4 relative, for at least 99.9% of photons (a few
+photons may flip on a near-tie of FP32 vs FP64 rounding). Every input is
+seeded and synthetic; no expected value comes from the GPU.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2405_05700_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TIME_RTOL = 1e-4
+MIN_AGREE = 0.999
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2405_05700_amd import pp as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def oracle():
+    from oracle import pyoracle
+    pyoracle.lib()
+    return pyoracle
+
+
+def gpu_run(pp, w, seed=0, records=True, step_cap=None, launch=None):
+    ctx = pp.Context(0, seed=seed)
+    ctx.load_workload(w)
+    ctx.set_debug_records(records)
+    if step_cap is not None:
+        ctx.set_step_cap(step_cap)
+    if launch:
+        ctx.set_launch_config(**launch)
+    b = ctx.submit(w.sources)
+    ctx.propagate(b)
+    out = {"stats": ctx.stats(b), "hits": ctx.fetch_hits(b)}
+    if records:
+        out["rec"] = ctx.fetch_records(b, 0, w.n_photons)
+    out["ctx"], out["batch"] = ctx, b
+    return out
+
+
+def agreement(rec, ref, pos_atol=1e-3):
+    """Fraction of photons whose fate, module and step count agree exactly,
+    with time within TIME_RTOL and end position within pos_atol."""
+    same = (rec["fate"] == ref.fate) & (rec["dom_id"] == ref.dom) & (rec["n_iter"] == ref.n_iter)
+    t_ok = np.abs(rec["time_ns"] - ref.t) <= TIME_RTOL * np.abs(ref.t) + 1e-6
+    pos = np.stack([rec["x"], rec["y"], rec["z"]], 1)
+    p_ok = np.abs(pos - ref.pos).max(1) <= pos_atol
+    ok = same & t_ok & p_ok
+    return float(ok.mean()), ok
+
+
+def check_conservation(st, n):
+    assert st["photons"] == n
+    assert st["hits"] + st["absorbed"] + st["capped"] + st["escaped"] == n
+
+
+def test_emission_parity(pp, oracle):
+    """Step cap 0: every photon stops at emission; its position, direction,
+    time and wavelength match the oracle's emission (point and Cherenkov)."""
+    for w in [W.tiny_point_source(50000), W.full_detector(n_sources=20, photons_per_source=3000)]:
+        say("emission", w.name, w.n_photons)
+        g = gpu_run(pp, w, step_cap=0)
+        ref = oracle.run(w, step_cap=0, threads=THREADS)
+        rec = g["rec"]
+        assert (rec["fate"] == pp.FATE_CAPPED).all() and (rec["n_iter"] == 0).all()
+        check_conservation(g["stats"], w.n_photons)
+        pos = np.stack([rec["x"], rec["y"], rec["z"]], 1)
+        dirs = np.stack([rec["vx"], rec["vy"], rec["vz"]], 1)
+        assert np.abs(pos - ref.pos).max() < 2e-4
+        assert np.abs(dirs - ref.dir).max() < 2e-5
+        assert np.allclose(rec["time_ns"], ref.t, rtol=1e-6, atol=1e-5)
+        assert np.allclose(rec["wavelength_nm"], ref.wavelength, rtol=1e-6)
+
+
+def test_tiny_point_source_per_photon(pp, oracle):
+    """1e5 photons of the tiny configuration (r = 0.1651 m): per-photon
+    terminal records agree with the oracle for >= 99.9% of photons, and the
+    step and crossing totals agree."""
+    w = W.tiny_point_source(100_000)
+    g = gpu_run(pp, w)
+    ref = oracle.run(w, threads=THREADS)
+    frac, ok = agreement(g["rec"], ref)
+    say("tiny per-photon agreement", frac, "hits", len(g["hits"]), ref.counters["hits"])
+    assert frac >= MIN_AGREE
+    check_conservation(g["stats"], w.n_photons)
+    assert abs(g["stats"]["iterations"] - ref.counters["iterations"]) <= 1e-3 * ref.counters["iterations"]
+
+
+def compare_hits(hits, ref, w):
+    """GPU hit list vs oracle terminal records: same photons, modules and
+    times (within tolerance) for >= 99.9% of the union."""
+    seq_base = np.concatenate([[0], np.cumsum(w.sources["n_photons"].astype(np.int64))])
+    src_of_event = {int(e): i for i, e in enumerate(w.sources["event_id"])}
+    s = np.array([src_of_event[int(e)] for e in hits["event_id"]], np.int64)
+    seq = seq_base[s] + (hits["photon_index"].astype(np.int64) -
+                         w.sources["first_photon_index"][s].astype(np.int64))
+    gpu = dict(zip(seq.tolist(), zip(hits["dom_id"].tolist(), hits["time_ns"].tolist())))
+    ref_hit = np.nonzero(ref.fate == 1)[0]
+    orc = dict(zip(ref_hit.tolist(), zip(ref.dom[ref_hit].tolist(), ref.t[ref_hit].tolist())))
+    union = set(gpu) | set(orc)
+    good = 0
+    for k in union:
+        if k in gpu and k in orc and gpu[k][0] == orc[k][0] and \
+                abs(gpu[k][1] - orc[k][1]) <= TIME_RTOL * abs(orc[k][1]) + 1e-6:
+            good += 1
+    return good, len(union)
+
+
+def test_enlarged_modules_hits(pp, oracle):
+    """r = 2 m: ~550 hits per 1e5 photons. The hit lists agree photon by
+    photon; per-module counts from the device histogram equal those of the
+    fetched hits; hits carry event, particle and weight 1."""
+    w = W.tiny_point_source(200_000, dom_radius_m=2.0)
+    g = gpu_run(pp, w)
+    ref = oracle.run(w, threads=THREADS, dom_mode=1)
+    good, total = compare_hits(g["hits"], ref, w)
+    say("r=2 hits", good, "/", total)
+    assert total > 500 and good >= MIN_AGREE * total
+    frac, _ = agreement(g["rec"], ref)
+    assert frac >= MIN_AGREE
+    counts = g["ctx"].dom_counts(g["batch"]).cpu().numpy()
+    assert (counts == np.bincount(g["hits"]["dom_id"], minlength=60)).all()
+    assert (g["hits"]["weight"] == 1.0).all() and (g["hits"]["event_id"] == 0).all()
+    assert (g["hits"]["particle_id"] == 0).all()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_geometries_grid_equals_brute_force(pp, oracle, seed):
+    """P10: tilted random strings; the GPU's grid search gives the oracle's
+    brute-force result photon by photon."""
+    w = W.random_tiny(seed, n_strings=3 + 2 * seed)
+    g = gpu_run(pp, w)
+    ref = oracle.run(w, dom_mode=0, threads=THREADS)
+    frac, _ = agreement(g["rec"], ref)
+    say("random", seed, frac, "hits", ref.counters["hits"])
+    assert ref.counters["hits"] > 20
+    assert frac >= 0.995  # 2000 photons: at most a few near-tie flips
+
+
+def test_launch_configuration_invariance(pp):
+    """P16: records are bit-identical across block size, chunk size (ragged
+    chunks included) and grid size."""
+    w = W.tiny_point_source(30_000, dom_radius_m=2.0)
+    base = gpu_run(pp, w, launch=dict())["rec"]
+    for launch in [dict(block_size=64, chunk_size=7), dict(block_size=1024, chunk_size=4096),
+                   dict(block_size=256, chunk_size=64, grid_blocks=3),
+                   dict(block_size=128, chunk_size=1, grid_blocks=1)]:
+        rec = gpu_run(pp, w, launch=launch)["rec"]
+        say("launch", launch)
+        assert (rec == base).all(), launch
+
+
+def test_seed_and_step_cap(pp, oracle):
+    """Other seeds and small step caps follow the oracle; capped photons
+    stop after exactly step_cap steps."""
+    w = W.tiny_point_source(20_000, dom_radius_m=2.0)
+    for seed, cap in [(12345, 100000), (2**40 + 7, 5), (1, 1)]:
+        g = gpu_run(pp, w, seed=seed, step_cap=cap)
+        ref = oracle.run(w, seed=seed, step_cap=cap, threads=THREADS)
+        frac, _ = agreement(g["rec"], ref)
+        assert frac >= MIN_AGREE, (seed, cap, frac)
+        assert g["rec"]["n_iter"].max() <= cap
+
+
+def test_no_medium_escape(pp, oracle):
+    """No absorption and no scattering: photons fly straight; they hit or
+    escape exactly as in the oracle (infinite steps handled)."""
+    w = W.tiny_point_source(20_000, dom_radius_m=3.0, abs_len_m=np.inf, eff_scat_len_m=np.inf)
+    g = gpu_run(pp, w)
+    ref = oracle.run(w, threads=THREADS)
+    frac, _ = agreement(g["rec"], ref)
+    assert frac >= MIN_AGREE
+    assert g["stats"]["escaped"] > 0 and g["stats"]["hits"] > 0
+    check_conservation(g["stats"], w.n_photons)
+
+
+def test_empty_and_ragged_batches(pp, oracle):
+    ctx = pp.Context(0, seed=0)
+    w = W.tiny_point_source(1, dom_radius_m=2.0)
+    ctx.load_workload(w)
+    ctx.set_debug_records(True)
+    b = ctx.submit(w.sources[:0])
+    ctx.propagate(b)
+    assert ctx.hit_count(b) == 0 and ctx.stats(b)["photons"] == 0
+    for n in [1, 63, 65, 4097]:
+        src = W.point_source(n_photons=n, first_photon_index=1000)
+        zero = W.point_source(n_photons=0, event_id=3)
+        wk = w.with_sources(np.concatenate([zero, src, zero]))
+        b = ctx.submit(wk.sources)
+        ctx.propagate(b)
+        st = ctx.stats(b)
+        check_conservation(st, n)
+        rec = ctx.fetch_records(b, 0, n)
+        ref = oracle.run(wk, threads=THREADS)
+        frac, _ = agreement(rec, ref)
+        assert frac >= 0.99 if n < 100 else frac >= MIN_AGREE
+        ctx.release(b)
+
+
+def test_hit_buffer_overflow_reruns_identically(pp):
+    """A device hit buffer of 8 hits overflows; fetching reruns the batch
+    with a large enough buffer and returns the same hits as a roomy run. A
+    host buffer that is too small gives PP_ETRUNC with the true total."""
+    w = W.tiny_point_source(50_000, dom_radius_m=2.0)
+    roomy = gpu_run(pp, w, records=False)["hits"]
+    small = gpu_run(pp, w, records=False, launch=dict(hit_capacity=8))
+    hits = small["hits"]
+    key = lambda h: np.sort(h, order=["event_id", "photon_index"])
+    assert len(hits) == len(roomy) > 8
+    assert (key(hits) == key(roomy)).all()
+    out = np.zeros(5, pp.HIT_DTYPE)
+    total = small["ctx"].fetch_hits_into(small["batch"], out)
+    assert total == len(roomy)
+
+
+def test_device_fetch_and_counts(pp):
+    import torch
+    w = W.tiny_point_source(50_000, dom_radius_m=2.0)
+    g = gpu_run(pp, w, records=False)
+    ctx, b = g["ctx"], g["batch"]
+    n = ctx.hit_count(b)
+    buf = torch.zeros(32 * n, dtype=torch.uint8, device="cuda:0")
+    assert ctx.fetch_hits_device(b, buf) == n
+    torch.cuda.synchronize()
+    dev = np.frombuffer(buf.cpu().numpy().tobytes(), dtype=pp.HIT_DTYPE)
+    key = lambda h: np.sort(h, order=["event_id", "photon_index"])
+    assert (key(dev) == key(g["hits"])).all()
+
+
+def test_statistical_consistency_independent_seeds(pp, oracle):
+    """Per-module counts of the GPU at seed 1 and the oracle at seed 0 are
+    consistent by chi-square (p > 0.01): 2e6 photons at r = 2 m and 1e7
+    photons at the nominal r = 0.1651 m."""
+    for n, r in [(2_000_000, 2.0), (10_000_000, W.DOM_RADIUS_M)]:
+        w = W.tiny_point_source(n, dom_radius_m=r)
+        ctx = pp.Context(0, seed=1)
+        ctx.load_workload(w)
+        b = ctx.submit(w.sources)
+        ctx.propagate(b)
+        c1 = ctx.dom_counts(b).cpu().numpy().astype(float)
+        ref = oracle.run(w, seed=0, threads=THREADS, records=False, dom_mode=1)
+        c0 = ref.dom_counts.astype(float)
+        keep = (c0 + c1) >= 5
+        chi2 = (((c1 - c0) ** 2) / np.maximum(c0 + c1, 1))[keep].sum()
+        pool0, pool1 = c0[~keep].sum(), c1[~keep].sum()
+        dof = int(keep.sum())
+        if pool0 + pool1 > 0:
+            chi2 += (pool1 - pool0) ** 2 / (pool0 + pool1)
+            dof += 1
+        p = stats.chi2.sf(chi2, dof)
+        say("chi2", n, r, chi2, dof, p, c0.sum(), c1.sum())
+        assert p > 0.01
