@@ -154,9 +154,10 @@ typedef struct {
  * default. */
 typedef struct {
   uint32_t block_size;  /* threads per workgroup, multiple of 64, <= 1024 (default 256) */
-  uint32_t chunk_size;  /* photon ids taken per queue grab by one wavefront (default 1024) */
+  uint32_t chunk_size;  /* photon ids taken per queue grab by one wavefront (default 256) */
   uint32_t grid_blocks; /* workgroups launched (default: enough to fill every CU) */
-  uint32_t reserved;
+  uint32_t refill_interval; /* propagation steps between refills of a wavefront's ended
+                               lanes (default 8) */
   uint64_t hit_capacity;/* initial device hit-buffer size in hits (default from photons) */
 } pp_launch_config;
 

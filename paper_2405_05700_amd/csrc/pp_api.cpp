@@ -60,7 +60,9 @@ struct pp_context {
   bool ice_loaded = false;
   pp_ice_header ice{};
   std::vector<pp::DevLayer> layers;
+  std::vector<float> bounds;
   pp::DevLayer *d_layers = nullptr;
+  float *d_bounds = nullptr;
   // geometry
   bool geo_loaded = false;
   uint32_t n_doms = 0;
@@ -137,7 +139,8 @@ pp_status find_batch(pp_context *ctx, uint64_t id, Batch **out) {
 }
 
 uint32_t default_block() { return 256; }
-uint32_t default_chunk() { return 1024; }
+uint32_t default_chunk() { return 256; }
+uint32_t default_refill_interval() { return 8; }
 
 // Horizontal distance from the rectangle [x0,x1] x [y0,y1] to the point.
 double rect_point_distance(double x0, double x1, double y0, double y1, double px, double py) {
@@ -189,8 +192,10 @@ void build_geometry(pp_context *ctx, const pp_dom *doms, uint32_t n, float radiu
         st.kpad = static_cast<float>(tol / dz + 1.0);
       }
     }
+    // the kernel's horizontal reach test carries a 0.01 m margin for FP32
+    // rounding of positions up to a few km
     st.xy_reach_z0 = make_float4(static_cast<float>(sx), static_cast<float>(sy),
-                                 static_cast<float>(rch), static_cast<float>(z0));
+                                 static_cast<float>(rch + 0.01), static_cast<float>(z0));
     for (uint32_t k : ids) {
       uint32_t bits = k;
       float fid;
@@ -214,7 +219,7 @@ void build_geometry(pp_context *ctx, const pp_dom *doms, uint32_t n, float radiu
   if (S == 0) {
     gi.grid_nx = gi.grid_ny = 1;
     gi.cell_m = 1.0f;
-    ctx->cells.push_back(0xFFFFFFFFu);
+    ctx->cells.push_back(0x7F80FFFFu);  // no string, infinite clearance
     return;
   }
   double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
@@ -254,12 +259,14 @@ void build_geometry(pp_context *ctx, const pp_dom *doms, uint32_t n, float radiu
           second = d;
         }
       }
-      uint32_t q = 0xFFFFu;
-      if (std::isfinite(second)) {
-        const double v = std::floor((second - kClearanceMargin) * 16.0);
-        q = v <= 0 ? 0u : static_cast<uint32_t>(std::min(v, 65534.0));
-      }
-      ctx->cells[static_cast<size_t>(iy) * nx + ix] = (q << 16) | s1;
+      // clearance stored as the upper half of its float (truncation rounds
+      // a positive value down, so the bound stays conservative)
+      const float clr = std::isfinite(second)
+                            ? static_cast<float>(std::max(0.0, second - kClearanceMargin))
+                            : std::numeric_limits<float>::infinity();
+      uint32_t bits;
+      std::memcpy(&bits, &clr, 4);
+      ctx->cells[static_cast<size_t>(iy) * nx + ix] = (bits & 0xFFFF0000u) | s1;
     }
   }
 }
@@ -316,11 +323,11 @@ pp_status launch(pp_context *ctx, Batch &b, hipStream_t stream) {
   uint32_t grid = c.grid_blocks;
   if (grid == 0) {
     int per_cu = 0;
-    PP_HIP(ctx, pp::propagate_occupancy(static_cast<int>(block), lds, &per_cu));
+    PP_HIP(ctx, pp::propagate_occupancy(ctx->records, static_cast<int>(block), lds, &per_cu));
     grid = static_cast<uint32_t>(std::max(per_cu, 1) * std::max(ctx->n_cu, 1));
   }
-  // Default chunk: 1024 ids, smaller for small batches so that every
-  // resident wavefront gets several chunks.
+  // Default chunk: 256 ids (measured best on the full detector), smaller
+  // for small batches so that every resident wavefront gets several chunks.
   uint32_t chunk = c.chunk_size;
   if (chunk == 0) {
     const uint64_t waves = static_cast<uint64_t>(grid) * (block / 64);
@@ -348,10 +355,10 @@ pp_status launch(pp_context *ctx, Batch &b, hipStream_t stream) {
 
   pp::PropagateArgs a{};
   a.layers = ctx->d_layers;
+  a.bounds = ctx->d_bounds;
   a.n_layers = static_cast<int>(ctx->ice.n_layers);
   a.z_lo = ctx->ice.z_lo_m;
-  a.dz = ctx->ice.dz_m;
-  a.inv_dz = 1.0f / ctx->ice.dz_m;
+  a.inv_dz = static_cast<float>(1.0 / ctx->ice.dz_m);
   a.time_per_m = static_cast<float>(static_cast<double>(ctx->ice.n_group) / 0.299792458);
   a.strings = ctx->d_strings;
   a.n_strings = static_cast<int>(ctx->strings.size());
@@ -361,6 +368,8 @@ pp_status launch(pp_context *ctx, Batch &b, hipStream_t stream) {
   a.gx0 = ctx->geo.grid_x0_m;
   a.gy0 = ctx->geo.grid_y0_m;
   a.inv_cell = 1.0f / ctx->geo.cell_m;
+  a.nx_max = static_cast<float>(a.nx - 1);
+  a.ny_max = static_cast<float>(a.ny - 1);
   a.doms = ctx->d_doms;
   a.radius = ctx->radius;
   a.radius2 = ctx->radius * ctx->radius;
@@ -370,6 +379,7 @@ pp_status launch(pp_context *ctx, Batch &b, hipStream_t stream) {
   a.seed_lo = static_cast<uint32_t>(ctx->seed);
   a.seed_hi = static_cast<uint32_t>(ctx->seed >> 32);
   a.step_cap = static_cast<uint32_t>(ctx->step_cap);
+  a.refill_interval = c.refill_interval ? c.refill_interval : default_refill_interval();
   a.counters = b.d_counters;
   a.hits = b.d_hits;
   a.hit_capacity = b.hit_cap;
@@ -386,6 +396,7 @@ pp_status launch(pp_context *ctx, Batch &b, hipStream_t stream) {
   b.used.block_size = block;
   b.used.chunk_size = chunk;
   b.used.grid_blocks = grid;
+  b.used.refill_interval = a.refill_interval;
   b.used.hit_capacity = b.hit_cap;
   return PP_OK;
 }
@@ -471,6 +482,7 @@ void pp_destroy(pp_context *ctx) {
     (void)hipSetDevice(ctx->device);
     for (auto &kv : ctx->batches) free_batch(kv.second);
     (void)hipFree(ctx->d_layers);
+    (void)hipFree(ctx->d_bounds);
     (void)hipFree(ctx->d_strings);
     (void)hipFree(ctx->d_cells);
     (void)hipFree(ctx->d_doms);
@@ -495,6 +507,7 @@ pp_status pp_get_launch_config(const pp_context *ctx, pp_launch_config *cfg) {
   *cfg = ctx->cfg;
   if (!cfg->block_size) cfg->block_size = default_block();
   if (!cfg->chunk_size) cfg->chunk_size = default_chunk();
+  if (!cfg->refill_interval) cfg->refill_interval = default_refill_interval();
   return PP_OK;
 }
 
@@ -535,14 +548,22 @@ pp_status pp_load_ice(pp_context *ctx, const pp_ice_header *h, const pp_ice_laye
     L[i].hg = make_float4(static_cast<float>(1.0 - g), static_cast<float>(1.0 - g * g),
                           static_cast<float>(2.0 * g), 0.0f);
   }
+  // boundary heights: bounds[i] is the bottom of layer i; the edge layers
+  // extend to infinity
+  std::vector<float> B(h->n_layers + 1);
+  for (uint32_t i = 0; i <= h->n_layers; ++i)
+    B[i] = static_cast<float>(static_cast<double>(h->z_lo_m) + static_cast<double>(i) * h->dz_m);
+  B[0] = -std::numeric_limits<float>::infinity();
+  B[h->n_layers] = std::numeric_limits<float>::infinity();
   if (ctx->device >= 0) {
     pp_status st = need_device(ctx);
     if (st != PP_OK) return st;
-    st = upload(ctx, &ctx->d_layers, L);
-    if (st != PP_OK) return st;
+    if ((st = upload(ctx, &ctx->d_layers, L)) != PP_OK) return st;
+    if ((st = upload(ctx, &ctx->d_bounds, B)) != PP_OK) return st;
   }
   ctx->ice = *h;
   ctx->layers = std::move(L);
+  ctx->bounds = std::move(B);
   ctx->ice_loaded = true;
   return PP_OK;
 }
@@ -597,9 +618,9 @@ pp_status pp_geometry_cell(const pp_context *ctx, float x, float y, uint32_t *ne
   const float fx = std::fmin(std::fmax((x - g.grid_x0_m) * inv, 0.0f), static_cast<float>(g.grid_nx - 1));
   const float fy = std::fmin(std::fmax((y - g.grid_y0_m) * inv, 0.0f), static_cast<float>(g.grid_ny - 1));
   const uint32_t word = ctx->cells[static_cast<size_t>(fy) * g.grid_nx + static_cast<size_t>(fx)];
-  const uint32_t s1 = word & 0xFFFFu, q = word >> 16;
+  const uint32_t s1 = word & 0xFFFFu, hi = word & 0xFFFF0000u;
   *nearest = s1 == 0xFFFFu ? 0xFFFFFFFFu : s1;
-  *clearance = q == 0xFFFFu ? std::numeric_limits<float>::infinity() : q * 0.0625f;
+  std::memcpy(clearance, &hi, 4);
   return PP_OK;
 }
 

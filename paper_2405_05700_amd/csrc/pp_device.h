@@ -8,7 +8,8 @@
 namespace pp {
 
 // Per-layer coefficients, staged into LDS: {a = 1/lambda_a, b = 1/lambda_s,
-// 1/a, 1/b} and the Henyey-Greenstein constants {1 - g, 1 - g^2, 2 g, 0}.
+// 1/a, 1/b} (a reciprocal is +inf where the coefficient is 0) and the
+// Henyey-Greenstein constants {1 - g, 1 - g^2, 2 g, 0}.
 struct DevLayer {
   float4 coef;
   float4 hg;
@@ -20,7 +21,7 @@ struct DevLayer {
 // the modules a segment can reach are found arithmetically, widened by
 // kpad slots; otherwise inv_dz = 0 and kpad = n cover the whole string.
 struct DevString {
-  float4 xy_reach_z0;  // centre x, centre y, reach (max horizontal offset + r), z of slot 0
+  float4 xy_reach_z0;  // centre x, centre y, reach + 0.01 m margin, z of slot 0
   float inv_dz, kpad;
   int first, n;
 };
@@ -71,17 +72,20 @@ struct Records {  // terminal records, structure of arrays (null if off)
 };
 
 struct PropagateArgs {
-  // ice
+  // ice: layer table and the n_layers + 1 boundary heights (first -inf,
+  // last +inf, so the edge layers extend to infinity)
   const DevLayer *layers;
+  const float *bounds;
   int n_layers;
-  float z_lo, dz, inv_dz;
+  float z_lo, inv_dz;
   float time_per_m;  // n_group / c
-  // geometry
+  // geometry: grid cell word = nearest string (low 16 bits, 0xFFFF none) |
+  // upper half of the float clearance to every other string (rounded down)
   const DevString *strings;
   int n_strings;
-  const uint32_t *cells;  // nearest string (low 16 bits, 0xFFFF none) | clearance * 16 (high)
+  const uint32_t *cells;
   int nx, ny;
-  float gx0, gy0, inv_cell;
+  float gx0, gy0, inv_cell, nx_max, ny_max;  // nx_max = nx - 1 as float
   const float4 *doms;  // sorted by string then z: x, y, z, module id (as bits)
   float radius, radius2;
   // work
@@ -90,6 +94,7 @@ struct PropagateArgs {
   uint32_t n_chunks;
   uint32_t seed_lo, seed_hi;
   uint32_t step_cap;
+  uint32_t refill_interval;
   // outputs
   unsigned long long *counters;
   DevHit *hits;
@@ -102,7 +107,7 @@ size_t propagate_lds_bytes(int n_layers, int n_strings, int n_cells);
 
 hipError_t launch_reset(unsigned long long *counters, int n, hipStream_t stream);
 hipError_t launch_propagate(const PropagateArgs &args, int grid, int block, hipStream_t stream);
-hipError_t propagate_occupancy(int block, size_t lds_bytes, int *blocks_per_cu);
+hipError_t propagate_occupancy(bool records, int block, size_t lds_bytes, int *blocks_per_cu);
 hipError_t launch_dom_histogram(const DevHit *hits, const unsigned long long *hit_count,
                                 unsigned long long hit_capacity, uint32_t *counts, uint32_t n_doms,
                                 hipStream_t stream);

@@ -89,6 +89,7 @@ struct Segment {
   float px, py, pz, vx, vy, vz, len;
 };
 
+
 // Ray-sphere test of one module against the segment; keeps the nearest
 // entry point, ties to the lower module id. A sphere containing the start
 // point is ignored.
@@ -115,7 +116,7 @@ __device__ __forceinline__ void test_string(const DevString &st, const float4 *_
                                             const Segment &s, float radius, float r2,
                                             float &best_t, uint32_t &best_id, uint32_t &tests) {
   const float dx = st.xy_reach_z0.x - s.px, dy = st.xy_reach_z0.y - s.py;
-  const float lim = __builtin_fmaf(s.len, 1.00001f, st.xy_reach_z0.z + 0.01f);
+  const float lim = __builtin_fmaf(s.len, 1.00001f, st.xy_reach_z0.z);
   if (dx * dx + dy * dy > lim * lim) return;
   const float zend = __builtin_fmaf(s.len, s.vz, s.pz);
   const float zmin = fminf(s.pz, zend) - radius;  // fminf drops a NaN end (infinite flat step)
@@ -156,246 +157,63 @@ __device__ __forceinline__ void rotate(float rx, float ry, float rz, float om, f
   vz = z * inv;
 }
 
-__global__ void __launch_bounds__(1024) k_propagate(const PropagateArgs a) {
+template <bool kRecords>
+__global__ void __launch_bounds__(1024)
+k_propagate(const PropagateArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   DevLayer *s_layers = reinterpret_cast<DevLayer *>(lds_raw);
   DevString *s_strings = reinterpret_cast<DevString *>(s_layers + a.n_layers);
   uint32_t *s_cells = reinterpret_cast<uint32_t *>(s_strings + a.n_strings);
+  float *s_bounds = reinterpret_cast<float *>(s_cells + a.nx * a.ny);
   for (int i = threadIdx.x; i < a.n_layers; i += blockDim.x) s_layers[i] = a.layers[i];
   for (int i = threadIdx.x; i < a.n_strings; i += blockDim.x) s_strings[i] = a.strings[i];
   for (int i = threadIdx.x; i < a.nx * a.ny; i += blockDim.x) s_cells[i] = a.cells[i];
+  for (int i = threadIdx.x; i <= a.n_layers; i += blockDim.x) s_bounds[i] = a.bounds[i];
   __syncthreads();
 
   const uint32_t lane = __lane_id();
   const float r2 = a.radius2;
 
-  // wave-uniform queue state
-  uint32_t ch_src = 0, ch_left = 0;
+  // wave-uniform queue state and counters
+  uint32_t ch_src = 0, ch_left = 0, countdown = 0;
   unsigned long long ch_local = 0;
   bool more = true;
+  uint32_t n_photons = 0, n_hits = 0, n_abs = 0, n_cap = 0, n_esc = 0;
 
-  // lane state
-  bool alive = false, fresh = false;
-  uint32_t src = 0, event = 0, iter = 0, ncross = 0;
-  unsigned long long local = 0, pidx = 0, seq = 0;
+  // lane state: a lane is live (propagating), ended (stopped, output not yet
+  // written) or free
+  bool alive = false, ended = false;
+  uint32_t event = 0, particle = 0, iter = 0, ncross = 0, fate = 0, hit_dom = kNoDom;
+  unsigned long long pidx = 0, seq = 0;
   float px = 0, py = 0, pz = 0, vx = 0, vy = 0, vz = 1, t = 0, tau_a = 0, lambda = 0;
   int layer = 0;
-
-  uint32_t st_photons = 0, st_iter = 0, st_cross = 0, st_tests = 0;
-  uint32_t st_hits = 0, st_abs = 0, st_cap = 0, st_esc = 0;
+  uint32_t st_iter = 0, st_cross = 0, st_tests = 0;
 
   for (;;) {
-    // Refill lanes whose photon ended from the wavefront's chunk; grab a new
-    // chunk when it runs out.
-    if (more) {
-      unsigned long long dead = __ballot(!alive);
-      while (dead != 0 && more) {
-        if (ch_left == 0) {
-          unsigned long long c = 0;
-          if (lane == 0) c = atomicAdd(&a.counters[kChunkNext], 1ull);
-          c = first_lane_u64(c);
-          if (c >= a.n_chunks) {
-            more = false;
-            break;
-          }
-          const DevChunk e = a.chunks[c];
-          ch_src = e.src;
-          ch_left = e.count;
-          ch_local = e.local;
-        }
-        const uint32_t take = min((uint32_t)__popcll(dead), ch_left);
-        const uint32_t rank = lane_rank(dead);
-        if (!alive && rank < take) {
-          alive = true;
-          fresh = true;
-          src = ch_src;
-          local = ch_local + rank;
-        }
-        ch_left -= take;
-        ch_local += take;
-        dead = __ballot(!alive);
-      }
-    }
-    if (__ballot(alive) == 0) break;
-
-    uint32_t fate = kLive, hit_dom = kNoDom;
-    if (alive) {
-      // Source data for new photons.
-      float4 sp = make_float4(0, 0, 0, 0), sd = sp, se = sp;
-      uint32_t stype = 0;
-      if (fresh) {
-        const DevSource &S = a.sources[src];
-        sp = S.pos_t0;
-        sd = S.dir_len;
-        se = S.emit;
-        stype = S.ids.x;
-        event = S.ids.y;
-        pidx = S.first_index + local;
-        seq = S.seq_base + local;
-      }
-      uint32_t w[4];
-      philox4x32_10(fresh ? 0u : 2u + iter, event, (uint32_t)pidx, (uint32_t)(pidx >> 32),
-                    a.seed_lo, a.seed_hi, w);
-      const float u0 = u01(w[0]), u1 = u01(w[1]), u2 = u01(w[2]);
-      // one logarithm: the absorption budget at emission, the scattering
-      // optical depth of the step otherwise
-      const float neg_log = -kLn2 * __builtin_amdgcn_logf(fresh ? u2 : u0);
-
-      float rx = 0, ry = 0, rz = 1, om = 0, phi = 0;
-      bool turn = false;
-      if (fresh) {
-        // Emission: a point source rotates +z by cos(theta) = 2 u0 - 1; a
-        // Cherenkov segment emits from u0 * length along the track, on the
-        // cone about the track axis. Azimuth u1 in both cases.
-        const bool point = stype == 0;
-        const float sdist = point ? 0.0f : u0 * sd.w;
-        px = __builtin_fmaf(sdist, sd.x, sp.x);
-        py = __builtin_fmaf(sdist, sd.y, sp.y);
-        pz = __builtin_fmaf(sdist, sd.z, sp.z);
-        t = __builtin_fmaf(sdist, kNsPerMetreLight, sp.w);
-        rx = sd.x;
-        ry = sd.y;
-        rz = sd.z;
-        om = point ? 2.0f * (1.0f - u0) : se.x;
-        phi = u1;
-        turn = true;
-        tau_a = neg_log;
-        lambda = se.y != 0.0f ? se.y : __builtin_amdgcn_rcpf(__builtin_fmaf(-u01(w[3]), se.w, se.z));
-        const float lf = floorf((pz - a.z_lo) / a.dz);
-        layer = lf >= 0.0f ? (lf >= (float)(a.n_layers - 1) ? a.n_layers - 1 : (int)lf) : 0;
-        iter = 0;
-        ncross = 0;
-        fresh = false;
-        ++st_photons;
-      } else {
-        ++iter;
-        ++st_iter;
-        float tau_s = neg_log;
-        // Layer walk: consume both optical-depth budgets layer by layer
-        // until one runs out (ties: absorb <= scatter <= boundary).
-        const int dir = vz > 0.0f ? 1 : (vz < 0.0f ? -1 : 0);
-        const float rvz = __builtin_amdgcn_rcpf(vz);
-        float len = 0.0f, zc = pz;
-        int i = layer;
-        uint32_t end;  // 0 absorb, 1 scatter, 2 escape
-        for (;;) {
-          const float4 c = s_layers[i].coef;
-          const float d_abs = c.x > 0.0f ? tau_a * c.z : inf_f();
-          const float d_sca = c.y > 0.0f ? tau_s * c.w : inf_f();
-          const int nb = dir > 0 ? i + 1 : i;
-          const bool bounded = (dir > 0 && i < a.n_layers - 1) || (dir < 0 && i > 0);
-          const float zb = __builtin_fmaf((float)nb, a.dz, a.z_lo);
-          const float d_bnd = bounded ? fmaxf(0.0f, (zb - zc) * rvz) : inf_f();
-          if (d_abs == inf_f() && d_sca == inf_f() && d_bnd == inf_f()) {
-            len = inf_f();
-            end = 2;
-            break;
-          }
-          if (d_abs <= d_sca && d_abs <= d_bnd) {
-            len += d_abs;
-            tau_a = 0.0f;
-            end = 0;
-            break;
-          }
-          if (d_sca <= d_bnd) {
-            len += d_sca;
-            tau_a = fmaxf(0.0f, tau_a - c.x * d_sca);
-            end = 1;
-            break;
-          }
-          len += d_bnd;
-          tau_a = fmaxf(0.0f, tau_a - c.x * d_bnd);
-          tau_s = fmaxf(0.0f, tau_s - c.y * d_bnd);
-          zc = zb;
-          i += dir;
-          ++ncross;
-          ++st_cross;
-        }
-        layer = i;
-
-        // Nearest module on the segment: the string listed for the grid
-        // cell of the start point, and every other string only when the step
-        // is longer than the cell's clearance to them.
-        Segment seg{px, py, pz, vx, vy, vz, len};
-        float best_t = inf_f();
-        uint32_t best_id = kNoDom;
-        {
-          const float fx = fminf(fmaxf((px - a.gx0) * a.inv_cell, 0.0f), (float)(a.nx - 1));
-          const float fy = fminf(fmaxf((py - a.gy0) * a.inv_cell, 0.0f), (float)(a.ny - 1));
-          const uint32_t word = s_cells[(int)fy * a.nx + (int)fx];
-          const uint32_t s1 = word & 0xFFFFu, q = word >> 16;
-          const float clearance = q == 0xFFFFu ? inf_f() : (float)q * 0.0625f;
-          if (s1 != 0xFFFFu)
-            test_string(s_strings[s1], a.doms, seg, a.radius, r2, best_t, best_id, st_tests);
-          if (len >= clearance) {
-            for (int s = 0; s < a.n_strings; ++s)
-              if ((uint32_t)s != s1)
-                test_string(s_strings[s], a.doms, seg, a.radius, r2, best_t, best_id, st_tests);
-          }
-        }
-
-        if (best_id != kNoDom) {
-          px = __builtin_fmaf(best_t, vx, px);
-          py = __builtin_fmaf(best_t, vy, py);
-          pz = __builtin_fmaf(best_t, vz, pz);
-          t = __builtin_fmaf(best_t, a.time_per_m, t);
-          fate = kFateHit;
-          hit_dom = best_id;
-        } else if (end == 2) {
-          fate = kFateEscaped;
-        } else {
-          px = __builtin_fmaf(len, vx, px);
-          py = __builtin_fmaf(len, vy, py);
-          pz = __builtin_fmaf(len, vz, pz);
-          t = __builtin_fmaf(len, a.time_per_m, t);
-          if (end == 0) {
-            fate = kFateAbsorbed;
-          } else {
-            // Henyey-Greenstein polar angle in the cancellation-free form
-            // 1 - mu = (1 - g)(1 - u)(s + 1 - g)/w, w = 1 - g + 2 g u,
-            // s = (1 - g^2)/w; azimuth u2.
-            const float4 hg = s_layers[layer].hg;
-            const float wv = __builtin_fmaf(hg.z, u1, hg.x);
-            const float rw = __builtin_amdgcn_rcpf(wv);
-            const float sv = hg.y * rw;
-            om = hg.x * (1.0f - u1) * (sv + hg.x) * rw;
-            phi = u2;
-            rx = vx;
-            ry = vy;
-            rz = vz;
-            turn = true;
+    // Every refill_interval steps (or when no lane is live): write out the
+    // lanes that ended, then refill free lanes from the wavefront's chunk,
+    // emitting their photons (Philox block 0).
+    if (countdown == 0 || __ballot(alive) == 0) {
+      countdown = a.refill_interval;
+      const unsigned long long hmask = __ballot(ended && fate == kFateHit);
+      if (hmask != 0) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&a.counters[kHitCount], (unsigned long long)__popcll(hmask));
+        base = first_lane_u64(base);
+        if (ended && fate == kFateHit) {
+          const unsigned long long slot = base + lane_rank(hmask);
+          if (slot < a.hit_capacity) {
+            uint4 *out = reinterpret_cast<uint4 *>(a.hits + slot);
+            out[0] = make_uint4((uint32_t)pidx, (uint32_t)(pidx >> 32), event, particle);
+            out[1] = make_uint4(hit_dom, __float_as_uint(t), __float_as_uint(1.0f), 0u);
           }
         }
       }
-      if (turn) {
-        rotate(rx, ry, rz, om, phi, vx, vy, vz);
-        if (iter >= a.step_cap) fate = kFateCapped;
-      }
-    }
-
-    // Wave-compacted hit output: one atomic per wavefront.
-    const bool is_hit = fate == kFateHit;
-    const unsigned long long hmask = __ballot(is_hit);
-    if (hmask != 0) {
-      unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(&a.counters[kHitCount], (unsigned long long)__popcll(hmask));
-      base = first_lane_u64(base);
-      if (is_hit) {
-        const unsigned long long slot = base + lane_rank(hmask);
-        if (slot < a.hit_capacity) {
-          uint4 *out = reinterpret_cast<uint4 *>(a.hits + slot);
-          const uint32_t particle = a.sources[src].ids.z;
-          out[0] = make_uint4((uint32_t)pidx, (uint32_t)(pidx >> 32), event, particle);
-          out[1] = make_uint4(hit_dom, __float_as_uint(t), __float_as_uint(1.0f), 0u);
-        }
-      }
-    }
-    if (fate != kLive) {
-      st_hits += fate == kFateHit;
-      st_abs += fate == kFateAbsorbed;
-      st_cap += fate == kFateCapped;
-      st_esc += fate == kFateEscaped;
-      if (a.rec.fate != nullptr) {
+      n_hits += __popcll(hmask);
+      n_abs += __popcll(__ballot(ended && fate == kFateAbsorbed));
+      n_cap += __popcll(__ballot(ended && fate == kFateCapped));
+      n_esc += __popcll(__ballot(ended && fate == kFateEscaped));
+      if (kRecords && ended) {
         a.rec.fate[seq] = fate;
         a.rec.dom[seq] = hit_dom;
         a.rec.n_iter[seq] = iter;
@@ -409,18 +227,185 @@ __global__ void __launch_bounds__(1024) k_propagate(const PropagateArgs a) {
         a.rec.vz[seq] = vz;
         a.rec.wavelength[seq] = lambda;
       }
-      alive = false;
+      ended = false;
+
+      unsigned long long free_mask = __ballot(!alive);
+      while (free_mask != 0 && more) {
+        if (ch_left == 0) {
+          unsigned long long c = 0;
+          if (lane == 0) c = atomicAdd(&a.counters[kChunkNext], 1ull);
+          c = first_lane_u64(c);
+          if (c >= a.n_chunks) {
+            more = false;
+            break;
+          }
+          const DevChunk e = a.chunks[c];
+          ch_src = e.src;
+          ch_left = e.count;
+          ch_local = e.local;
+        }
+        const uint32_t take = min((uint32_t)__popcll(free_mask), ch_left);
+        const uint32_t rank = lane_rank(free_mask);
+        if (((free_mask >> lane) & 1ull) && rank < take) {
+          // Emission from the chunk's source (uniform across the wavefront):
+          // a point source rotates +z by cos(theta) = 2 u0 - 1; a Cherenkov
+          // segment emits from u0 * length along the track, on the cone about
+          // the track axis. Azimuth u1, absorption budget -ln u2.
+          const DevSource &S = a.sources[ch_src];
+          const unsigned long long local = ch_local + rank;
+          pidx = S.first_index + local;
+          if (kRecords) seq = S.seq_base + local;
+          event = S.ids.y;
+          particle = S.ids.z;
+          uint32_t w[4];
+          philox4x32_10(0u, event, (uint32_t)pidx, (uint32_t)(pidx >> 32), a.seed_lo, a.seed_hi, w);
+          const float u0 = u01(w[0]);
+          const bool point = S.ids.x == 0;
+          const float sdist = point ? 0.0f : u0 * S.dir_len.w;
+          px = __builtin_fmaf(sdist, S.dir_len.x, S.pos_t0.x);
+          py = __builtin_fmaf(sdist, S.dir_len.y, S.pos_t0.y);
+          pz = __builtin_fmaf(sdist, S.dir_len.z, S.pos_t0.z);
+          t = __builtin_fmaf(sdist, kNsPerMetreLight, S.pos_t0.w);
+          const float om = point ? 2.0f * (1.0f - u0) : S.emit.x;
+          rotate(S.dir_len.x, S.dir_len.y, S.dir_len.z, om, u01(w[1]), vx, vy, vz);
+          tau_a = -kLn2 * __builtin_amdgcn_logf(u01(w[2]));
+          if (kRecords)
+            lambda = S.emit.y != 0.0f ? S.emit.y
+                                      : __builtin_amdgcn_rcpf(__builtin_fmaf(-u01(w[3]), S.emit.w, S.emit.z));
+          const float lf = floorf((pz - a.z_lo) * a.inv_dz);
+          layer = lf >= 0.0f ? (lf >= (float)(a.n_layers - 1) ? a.n_layers - 1 : (int)lf) : 0;
+          iter = 0;
+          ncross = 0;
+          alive = a.step_cap != 0;
+          ended = !alive;
+          fate = kFateCapped;
+          hit_dom = kNoDom;
+        }
+        n_photons += take;
+        ch_left -= take;
+        ch_local += take;
+        free_mask = __ballot(!alive && !ended);
+      }
+      if (!more && __ballot(alive || ended) == 0) break;
+    }
+    --countdown;
+
+    if (alive) {
+      // The round keys are recomputed with scalar adds each step rather than
+      // held in 20 SGPRs across the loop (which would cap occupancy).
+      uint32_t k0 = a.seed_lo, k1 = a.seed_hi;
+      asm volatile("" : "+s"(k0), "+s"(k1));
+      uint32_t w[4];
+      philox4x32_10(2u + iter, event, (uint32_t)pidx, (uint32_t)(pidx >> 32), k0, k1, w);
+      ++iter;
+      ++st_iter;
+      const float u1 = u01(w[1]), u2 = u01(w[2]);
+      float tau_s = -kLn2 * __builtin_amdgcn_logf(u01(w[0]));
+
+      // Layer walk: consume both optical-depth budgets layer by layer until
+      // one runs out (ties: absorb <= scatter <= boundary). A zero
+      // coefficient has an infinite reciprocal; fminf turns the 0 * inf of
+      // an exhausted budget there into +inf (an infinite distance), so no
+      // distance is NaN and a crossing always has a finite boundary
+      // distance (the edge layers' boundaries are at infinity).
+      const bool up = vz > 0.0f;
+      const bool flat = vz == 0.0f;
+      const float rvz = __builtin_amdgcn_rcpf(vz);
+      float len = 0.0f, zc = pz;
+      int i = layer;
+      int end;  // 0 absorb, 1 scatter, 2 escape
+      for (;;) {
+        const float4 c = s_layers[i].coef;
+        const float d_abs = fminf(tau_a * c.z, inf_f());
+        const float d_sca = fminf(tau_s * c.w, inf_f());
+        const float zb = s_bounds[up ? i + 1 : i];
+        const float d_bnd = flat ? inf_f() : fmaxf(0.0f, (zb - zc) * rvz);
+        if (d_abs == inf_f() && d_sca == inf_f() && d_bnd == inf_f()) {
+          len = inf_f();
+          end = 2;
+          break;
+        }
+        if (d_abs <= d_sca && d_abs <= d_bnd) {
+          len += d_abs;
+          end = 0;
+          break;
+        }
+        if (d_sca <= d_bnd) {
+          len += d_sca;
+          tau_a = fmaxf(0.0f, tau_a - c.x * d_sca);
+          end = 1;
+          break;
+        }
+        len += d_bnd;
+        tau_a = fmaxf(0.0f, tau_a - c.x * d_bnd);
+        tau_s = fmaxf(0.0f, tau_s - c.y * d_bnd);
+        zc = zb;
+        i += up ? 1 : -1;
+        ++ncross;
+        ++st_cross;
+      }
+
+      // Nearest module on the segment: the string listed for the grid cell
+      // of the start point, and every other string only when the step is at
+      // least the cell's clearance to them.
+      const Segment seg{px, py, pz, vx, vy, vz, len};
+      float best_t = inf_f();
+      uint32_t best_id = kNoDom;
+      {
+        const float fx = __builtin_amdgcn_fmed3f((px - a.gx0) * a.inv_cell, 0.0f, a.nx_max);
+        const float fy = __builtin_amdgcn_fmed3f((py - a.gy0) * a.inv_cell, 0.0f, a.ny_max);
+        const uint32_t word = s_cells[__umul24((uint32_t)fy, (uint32_t)a.nx) + (uint32_t)fx];
+        const uint32_t s1 = word & 0xFFFFu;
+        const float clearance = __uint_as_float(word & 0xFFFF0000u);
+        if (s1 != 0xFFFFu)
+          test_string(s_strings[s1], a.doms, seg, a.radius, r2, best_t, best_id, st_tests);
+        if (len >= clearance) {
+          for (int s = 0; s < a.n_strings; ++s)
+            if ((uint32_t)s != s1)
+              test_string(s_strings[s], a.doms, seg, a.radius, r2, best_t, best_id, st_tests);
+        }
+      }
+
+      const bool hit = best_id != kNoDom;
+      const float dmove = hit ? best_t : (end == 2 ? 0.0f : len);
+      px = __builtin_fmaf(dmove, vx, px);
+      py = __builtin_fmaf(dmove, vy, py);
+      pz = __builtin_fmaf(dmove, vz, pz);
+      t = __builtin_fmaf(dmove, a.time_per_m, t);
+      layer = i;
+      uint32_t f = hit ? kFateHit : (end == 2 ? kFateEscaped : (end == 0 ? kFateAbsorbed : kLive));
+
+      // Henyey-Greenstein polar angle in the cancellation-free form
+      // 1 - mu = (1 - g)(1 - u)(s + 1 - g)/w, w = 1 - g + 2 g u,
+      // s = (1 - g^2)/w, and azimuth u2, evaluated by every live lane; it is
+      // kept only by lanes that scatter.
+      const float4 hg = s_layers[i].hg;
+      const float rw = __builtin_amdgcn_rcpf(__builtin_fmaf(hg.z, u1, hg.x));
+      const float om = hg.x * (1.0f - u1) * __builtin_fmaf(hg.y, rw, hg.x) * rw;
+      float nx, ny, nz;
+      rotate(vx, vy, vz, om, u2, nx, ny, nz);
+      if (f == kLive) {
+        vx = nx;
+        vy = ny;
+        vz = nz;
+        if (iter >= a.step_cap) f = kFateCapped;
+      }
+      if (f != kLive) {
+        alive = false;
+        ended = true;
+        fate = f;
+        hit_dom = best_id;
+      }
     }
   }
 
   // Per-wavefront reduction of the counters, then one atomic each.
-  const uint32_t sums[8] = {wave_sum(st_photons), wave_sum(st_iter), wave_sum(st_cross),
-                            wave_sum(st_tests),   wave_sum(st_hits), wave_sum(st_abs),
-                            wave_sum(st_cap),     wave_sum(st_esc)};
+  const uint32_t it = wave_sum(st_iter), cr = wave_sum(st_cross), te = wave_sum(st_tests);
   if (lane == 0) {
+    const uint32_t v[8] = {n_photons, it, cr, te, n_hits, n_abs, n_cap, n_esc};
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      if (sums[k] != 0) atomicAdd(&a.counters[kStatPhotons + k], (unsigned long long)sums[k]);
+      if (v[k] != 0) atomicAdd(&a.counters[kStatPhotons + k], (unsigned long long)v[k]);
   }
 }
 
@@ -470,7 +455,8 @@ __global__ void k_dom_histogram_global(const DevHit *__restrict__ hits,
 }  // namespace
 
 size_t propagate_lds_bytes(int n_layers, int n_strings, int n_cells) {
-  return sizeof(DevLayer) * n_layers + sizeof(DevString) * n_strings + 4u * n_cells;
+  return sizeof(DevLayer) * n_layers + sizeof(DevString) * n_strings + 4u * n_cells +
+         4u * (n_layers + 1);
 }
 
 hipError_t launch_reset(unsigned long long *counters, int n, hipStream_t stream) {
@@ -480,12 +466,18 @@ hipError_t launch_reset(unsigned long long *counters, int n, hipStream_t stream)
 
 hipError_t launch_propagate(const PropagateArgs &args, int grid, int block, hipStream_t stream) {
   const size_t lds = propagate_lds_bytes(args.n_layers, args.n_strings, args.nx * args.ny);
-  hipLaunchKernelGGL(k_propagate, dim3(grid), dim3(block), lds, stream, args);
+  if (args.rec.fate != nullptr)
+    hipLaunchKernelGGL(k_propagate<true>, dim3(grid), dim3(block), lds, stream, args);
+  else
+    hipLaunchKernelGGL(k_propagate<false>, dim3(grid), dim3(block), lds, stream, args);
   return hipGetLastError();
 }
 
-hipError_t propagate_occupancy(int block, size_t lds_bytes, int *blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_propagate, block, lds_bytes);
+hipError_t propagate_occupancy(bool records, int block, size_t lds_bytes, int *blocks_per_cu) {
+  return records ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_propagate<true>, block,
+                                                                lds_bytes)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_propagate<false>, block,
+                                                                lds_bytes);
 }
 
 hipError_t launch_dom_histogram(const DevHit *hits, const unsigned long long *hit_count,

@@ -50,7 +50,7 @@ class _Stats(C.Structure):
 
 class _LaunchConfig(C.Structure):
     _fields_ = [("block_size", C.c_uint32), ("chunk_size", C.c_uint32),
-                ("grid_blocks", C.c_uint32), ("reserved", C.c_uint32),
+                ("grid_blocks", C.c_uint32), ("refill_interval", C.c_uint32),
                 ("hit_capacity", C.c_uint64)]
 
 
@@ -153,14 +153,15 @@ class Context:
         return st
 
     # -- configuration
-    def set_launch_config(self, block_size=0, chunk_size=0, grid_blocks=0, hit_capacity=0):
-        cfg = _LaunchConfig(block_size, chunk_size, grid_blocks, 0, hit_capacity)
+    def set_launch_config(self, block_size=0, chunk_size=0, grid_blocks=0, hit_capacity=0,
+                          refill_interval=0):
+        cfg = _LaunchConfig(block_size, chunk_size, grid_blocks, refill_interval, hit_capacity)
         self._check(_lib.pp_set_launch_config(self._h, C.byref(cfg)))
 
     def launch_config(self) -> dict:
         cfg = _LaunchConfig()
         self._check(_lib.pp_get_launch_config(self._h, C.byref(cfg)))
-        return {k: getattr(cfg, k) for k, _ in _LaunchConfig._fields_ if k != "reserved"}
+        return {k: getattr(cfg, k) for k, _ in _LaunchConfig._fields_}
 
     def set_step_cap(self, cap: int):
         self._check(_lib.pp_set_step_cap(self._h, int(cap)))

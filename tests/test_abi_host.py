@@ -160,9 +160,11 @@ def test_launch_config_validation(pp):
     ctx = host_ctx(pp)
     expect(pp, pp.PP_EINVAL, ctx.set_launch_config, 100)
     expect(pp, pp.PP_EINVAL, ctx.set_launch_config, 2048)
-    ctx.set_launch_config(512, 77, 3, 10)
+    ctx.set_launch_config(512, 77, 3, 10, 6)
     assert ctx.launch_config() == {"block_size": 512, "chunk_size": 77, "grid_blocks": 3,
-                                   "hit_capacity": 10}
+                                   "hit_capacity": 10, "refill_interval": 6}
+    ctx.set_launch_config()
+    assert ctx.launch_config()["refill_interval"] == 8
     expect(pp, pp.PP_EINVAL, ctx.set_step_cap, 2**31 + 1)
     ctx.set_step_cap(0)
 

@@ -164,7 +164,8 @@ def test_launch_configuration_invariance(pp):
     base = gpu_run(pp, w, launch=dict())["rec"]
     for launch in [dict(block_size=64, chunk_size=7), dict(block_size=1024, chunk_size=4096),
                    dict(block_size=256, chunk_size=64, grid_blocks=3),
-                   dict(block_size=128, chunk_size=1, grid_blocks=1)]:
+                   dict(block_size=128, chunk_size=1, grid_blocks=1),
+                   dict(refill_interval=1), dict(refill_interval=17, chunk_size=100)]:
         rec = gpu_run(pp, w, launch=launch)["rec"]
         say("launch", launch)
         assert (rec == base).all(), launch
