@@ -28,15 +28,35 @@ sys.path.insert(0, ROOT)
 # the issue rates measured on gfx950 relative to v_fma_f32. Frozen counts of
 # the arithmetic each unit needs in the FP32 formulation (derivation table
 # in the design notes):
-SLOTS_PER_STEP = 264        # one propagation step (Philox block 121 of it)
-SLOTS_PER_CROSSING = 29     # each extra layer of the layer walk
-SLOTS_PER_DOM_TEST = 30     # each ray-sphere test
-SLOTS_PER_PHOTON = 200      # emission (Philox block 0, cone rotation, setup)
-FLOPS_PER_STEP = 118        # FP32 FLOPs of a step (FMA = 2), for the FLOP form
+SLOTS_PER_STEP = 260        # one propagation step (Philox block 121 of it)
+SLOTS_PER_CROSSING = 28     # each extra layer of the layer walk
+SLOTS_PER_DOM_TEST = 32     # each ray-sphere test
+SLOTS_PER_PHOTON = 205      # emission (Philox block 0, cone rotation, setup)
+FLOPS_PER_STEP = 90         # FP32 FLOPs of a step (FMA = 2), for the FLOP form
 # Peak: MI355X FP32 vector 157.3 TFLOP/s = 256 CUs x 128 FP32 lanes/clock x
 # 2 FLOP per FMA x 2.4 GHz, i.e. 78.65e12 full-rate lane slots/s.
 PEAK_FP32_FLOPS = 157.3e12
 PEAK_SLOTS = PEAK_FP32_FLOPS / 2
+
+
+def measured_traffic():
+    """HBM bytes per launch of the propagation kernel from the committed
+    rocprofv3 summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's
+    reading), or None if the kernel source changed since it was taken."""
+    import hashlib
+    import re
+    prof = os.path.join(ROOT, "profiles", "k_propagate_full_detector.md")
+    src = os.path.join(ROOT, "paper_2405_05700_amd", "csrc", "pp_kernels.hip")
+    try:
+        text = open(prof).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    h = re.search(r"kernel_source_sha256: ([0-9a-f]+)", text)
+    t = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    if not h or not t or h.group(1) != digest:
+        return None
+    return int(t.group(1))
 
 
 def parse():
@@ -52,6 +72,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-photons-per-source", type=int, default=0,
                     help="oracle sample: first N photons of every source (0 = auto, ~15 s)")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--sur-train-sources", type=int, default=2000)
+    ap.add_argument("--sur-train-photons", type=int, default=1_000_000)
+    ap.add_argument("--sur-epochs", type=int, default=4)
+    ap.add_argument("--sur-lr", type=float, default=2e-3)
+    ap.add_argument("--sur-infer-sources", type=int, default=100_000)
+    ap.add_argument("--sur-eval-sources", type=int, default=1000)
+    ap.add_argument("--sur-truth-photons", type=int, default=4_000_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter scaling)")
     return ap.parse_args()
@@ -92,6 +120,98 @@ def cpu_baseline(w, per_source: int):
             "kind": "oracle",
             "sample": f"first {per_source} photons of each of the {len(w.sources)} sources "
                       f"({r.counters['photons']} photons, FP64, per-string pre-filter), {dt:.1f} s"}
+
+
+def surrogate_leg(args):
+    """Learned surrogate: train on Monte Carlo of 2000 segments x 5160
+    modules (about 1e7 pairs), time inference for 1e5 segments x 5160
+    modules, check per-module expected hits against high-statistics Monte
+    Carlo of held-out segments, and compare the time to per-module
+    expectations within 2% with plain Monte Carlo."""
+    import numpy as np
+    import torch
+    from paper_2405_05700_amd import pp, surrogate
+    from paper_2405_05700_amd import workloads as W
+
+    out = {}
+    w_tr = W.full_detector(n_sources=args.sur_train_sources, photons_per_source=args.sur_train_photons,
+                           seed=101)
+    ctx = pp.Context(0, seed=7)
+    ctx.load_workload(w_tr)
+    b_tr = ctx.submit(w_tr.sources)
+    ctx.propagate(b_tr)
+    sur = surrogate.Surrogate(ctx, seed=1)
+    t0 = time.perf_counter()
+    sur.set_training_set(b_tr)
+    torch.cuda.synchronize()
+    n_pairs = sur.training_size()
+    t1 = time.perf_counter()
+    losses = sur.train(epochs=args.sur_epochs, batch_size=8192, lr=args.sur_lr)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["train_pairs"] = n_pairs
+    out["train_epochs"] = args.sur_epochs
+    out["train_s"] = t2 - t1
+    out["train_pairs_per_s"] = n_pairs * args.sur_epochs / (t2 - t1)
+    out["epoch_loss"] = [float(x) for x in losses]
+    ctx.release(b_tr)
+
+    # inference throughput at 1e5 segments x all modules
+    w_inf = W.full_detector(n_sources=args.sur_infer_sources, photons_per_source=1, seed=303)
+    b_inf = ctx.submit(w_inf.sources)
+    sums = sur.expected_hits(b_inf)  # warm-up
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    sums = sur.expected_hits(b_inf)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    pairs_inf = args.sur_infer_sources * len(w_inf.doms)
+    out["infer_pairs"] = pairs_inf
+    out["infer_s"] = t4 - t3
+    out["infer_pairs_per_s"] = pairs_inf / (t4 - t3)
+    ctx.release(b_inf)
+
+    # accuracy: held-out segments, truth from high-statistics Monte Carlo
+    n_ev = args.sur_eval_sources
+    w_ev = W.full_detector(n_sources=n_ev, photons_per_source=args.sur_truth_photons, seed=202)
+    b_ev = ctx.submit(w_ev.sources)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s = torch.cuda.current_stream()
+    ev0.record(s)
+    ctx.propagate(b_ev, s)
+    truth = ctx.dom_counts(b_ev, stream=s).cpu().numpy().astype(np.float64)
+    ev1.record(s)
+    torch.cuda.synchronize()
+    mc_rate = w_ev.n_photons / (ev0.elapsed_time(ev1) / 1e3)
+    t5 = time.perf_counter()
+    pred = sur.expected_hits(b_ev).cpu().numpy()
+    torch.cuda.synchronize()
+    t_sur = time.perf_counter() - t5
+    graded = truth >= 10_000  # truth statistical error <= 1%
+    rel = np.abs(pred[graded] - truth[graded]) / truth[graded]
+    within = rel <= 0.02
+    # plain MC: photons per segment so that every graded module has >= 2500
+    # hits (2% Poisson error); the hybrid takes the surrogate for modules
+    # within 2% and Monte Carlo for the rest (fallback)
+    t_mc = 0.0
+    t_hybrid = t_sur
+    if graded.any():
+        n_mc = args.sur_truth_photons * 2500.0 / truth[graded].min()
+        t_mc = n_ev * n_mc / mc_rate
+        if (~within).any():
+            n_fb = args.sur_truth_photons * 2500.0 / truth[graded][~within].min()
+            t_hybrid += n_ev * n_fb / mc_rate
+    out.update({
+        "eval_sources": n_ev, "truth_photons_per_source": args.sur_truth_photons,
+        "graded_modules": int(graded.sum()),
+        "per_dom_rel_error_median": float(np.median(rel)) if graded.any() else None,
+        "per_dom_rel_error_p90": float(np.quantile(rel, 0.9)) if graded.any() else None,
+        "frac_modules_within_2pct": float(within.mean()) if graded.any() else None,
+        "mc_photons_per_s": mc_rate,
+        "t_plain_mc_s": t_mc, "t_surrogate_plus_mc_s": t_hybrid,
+        "speedup_at_2pct": (t_mc / t_hybrid) if t_hybrid > 0 and graded.any() else None,
+    })
+    return out
 
 
 def main():
@@ -169,7 +289,8 @@ def main():
                    "block_size": cfg["block_size"], "chunk_size": args.chunk_size or "auto",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
-                     "unit": "T lane-slots/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                     "unit": "T lane-slots/s", "frac": achieved / PEAK_SLOTS,
+                     "traffic": measured_traffic(),
                      "kernel": "k_propagate", "kernel_ms_avg": avg_s * 1e3,
                      "fp32_flop_frac": FLOPS_PER_STEP * st["iterations"] / avg_s / PEAK_FP32_FLOPS},
         "detail": {"iterations": st["iterations"], "layer_crossings": st["layer_crossings"],
@@ -181,6 +302,9 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_photons_per_source)
+    if not args.no_surrogate:
+        ctx.release(batch)
+        out["surrogate"] = surrogate_leg(args)
     print(json.dumps(out), flush=True)
 
 

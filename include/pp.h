@@ -266,6 +266,32 @@ pp_status pp_fetch_records(pp_context *ctx, uint64_t batch, pp_photon_record *ou
 /* Counters and kernel time of the batch's last propagation (synchronises). */
 pp_status pp_get_stats(pp_context *ctx, uint64_t batch, pp_stats *out);
 
+/* Batched uneven events. The paper's server aggregates light-emitting steps
+ * from many events and clients to keep the GPU busy, because one small
+ * event at a time starves it (Sec. 3, GPU-utilisation finding; Sec. 4,
+ * propagation-server paragraph). A batch may hold any number of events of
+ * any size: the propagation kernel is persistent and its wavefronts steal
+ * chunks of photon ids from one queue, so a 1e8-photon event and a
+ * 1e3-photon event share the device without imbalance. */
+
+/* Times the batch under a fixed set of launch configurations (workgroup
+ * size 256/512, chunk size 64/256/1024, refill interval 4/8/16), each one
+ * full propagation on hip_stream, and keeps the fastest as the context's
+ * launch configuration (also written to *best if non-NULL). Results do not
+ * change; only speed does. Synchronises the stream. */
+pp_status pp_autotune(pp_context *ctx, uint64_t batch, void *hip_stream, pp_launch_config *best);
+
+/* Captures the batch's propagation (counter reset and kernel, with the
+ * context's current launch configuration and debug-record setting) into a
+ * HIP graph held by the batch. hip_stream must be a non-null stream; it is
+ * used only for the capture. The graph is dropped when the batch's buffers
+ * change (hit-buffer growth, a new chunk size) or the batch is released. */
+pp_status pp_graph_capture(pp_context *ctx, uint64_t batch, void *hip_stream);
+
+/* Launches the captured graph on hip_stream: equivalent to pp_propagate
+ * with the captured configuration. PP_ESTATE if no graph is held. */
+pp_status pp_graph_launch(pp_context *ctx, uint64_t batch, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,98 @@
+/*
+ * pp_surrogate.h - C ABI of the learned surrogate in libpp.
+ *
+ * The paper notes that the depth-dependent optics of the ice make simple
+ * light models inaccurate and force photon-by-photon Monte Carlo, which is
+ * the expensive part of the chain (Sec. 1, detector paragraph; Sec. 2,
+ * photon-propagation paragraph). The surrogate learns, from hits that this
+ * library's own Monte Carlo generates, the expected number of hits of a
+ * module from a Cherenkov source and gamma parameters of the hit delay, so
+ * that expectations for many (source, module) pairs come from one network
+ * evaluation instead of many propagated photons. The Monte Carlo stays the
+ * judge of its error and the fallback where the error check fails.
+ *
+ * Model (fixed shape): features of a (source, module) pair -> five affine
+ * layers 64 -> 256 -> 256 -> 256 -> 256 -> 64 with GELU between them; BF16
+ * weights and activations, FP32 accumulation on the matrix cores, FP32
+ * master weights and Adam state. Output 0 is log(mu / mu_base), where
+ * mu_base is a diffusion estimate of the hit probability per photon;
+ * outputs 1 and 2 are log(kappa) and log(theta / 50 ns) of a gamma
+ * distribution of the hit delay. Loss per pair: the Poisson negative
+ * log-likelihood of the hit count plus 0.1 times the gamma negative
+ * log-likelihood of the delays, averaged over pairs.
+ *
+ * A pair set is every (source, module) pair of a batch submitted to the
+ * context (pp_submit), source-major: pair p = source p / n_doms, module
+ * p % n_doms. Surrogate sources must be Cherenkov segments.
+ *
+ * Conventions as in pp.h: status codes, caller-owned outputs, one surrogate
+ * per context at a time, not thread-safe.
+ */
+#ifndef PP_SURROGATE_H_
+#define PP_SURROGATE_H_
+
+#include <stdint.h>
+
+#include "pp.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pp_surrogate pp_surrogate;
+
+/* Creates a surrogate on ctx's device; ice and geometry must be loaded
+ * (PP_ESTATE otherwise). Weights are initialised from init_seed. */
+pp_status pp_sur_create(pp_context *ctx, uint64_t init_seed, pp_surrogate **out);
+void pp_sur_destroy(pp_surrogate *sur); /* NULL-safe */
+
+/* Number of f32 parameters: per layer, W (out x in, row-major) then b. */
+uint64_t pp_sur_param_count(void);
+pp_status pp_sur_get_params(pp_surrogate *sur, float *out, uint64_t n);
+/* Sets all parameters (n must equal the count) and clears the Adam state. */
+pp_status pp_sur_set_params(pp_surrogate *sur, const float *in, uint64_t n);
+
+/* Makes every (source, module) pair of the context's batch the training
+ * set: computes the pair features on the device, and labels from the
+ * batch's hits (which must have been propagated; the hit buffer is
+ * completed first). Each source of the batch needs its own event id. */
+pp_status pp_sur_set_training_set(pp_surrogate *sur, uint64_t batch);
+
+/* Number of pairs in the training set. */
+pp_status pp_sur_training_size(const pp_surrogate *sur, uint64_t *n_pairs);
+
+/* Copies training-set rows [first, first + count) to host memory: 16
+ * features per row, mu_base, and labels (k, n_t, sum of delays, sum of log
+ * delays). Any output pointer may be NULL. */
+pp_status pp_sur_get_training_rows(pp_surrogate *sur, uint64_t first, uint64_t count, float *features,
+                                   float *mu_base, float *k, float *n_t, float *s1, float *s2);
+
+/* Loss and gradient (f32, parameter layout) over training rows
+ * [first, first + count) as one batch, without an update. */
+pp_status pp_sur_loss_grad(pp_surrogate *sur, uint64_t first, uint64_t count, double *loss, float *grad);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr on
+ * rows [first, first + count); *loss gets the loss before the step. */
+pp_status pp_sur_train_step(pp_surrogate *sur, uint64_t first, uint64_t count, float lr, double *loss);
+
+/* Trains for the given epochs over the whole training set in minibatches of
+ * batch_size rows (a multiple of 64) on hip_stream; epoch_loss (may be
+ * NULL) receives the mean loss of each epoch. */
+pp_status pp_sur_train(pp_surrogate *sur, uint32_t epochs, uint32_t batch_size, float lr, void *hip_stream,
+                       float *epoch_loss);
+
+/* Expected hits (photons of the source times the predicted probability
+ * per photon) of every (source, module) pair of the context's batch,
+ * summed per module into dev_dom_sums (n_doms doubles in device memory,
+ * overwritten), on hip_stream. */
+pp_status pp_sur_expected_hits(pp_surrogate *sur, uint64_t batch, double *dev_dom_sums, void *hip_stream);
+
+/* Expected hits of every pair of the batch into host memory out (n_sources
+ * x n_doms f32, source-major). n must equal that size. */
+pp_status pp_sur_predict_pairs(pp_surrogate *sur, uint64_t batch, float *out, uint64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PP_SURROGATE_H_ */

@@ -1,0 +1,195 @@
+"""FP64 CPU oracle of the learned surrogate (test infrastructure only).
+
+The surrogate predicts, for a light source and an optical module, the
+expected number of hits per emitted photon and gamma parameters of the hit
+delay. It is a multilayer perceptron: five affine layers (16 features + 48 zero columns)
+-> 256 -> 256 -> 256 -> 256 -> 64, three outputs used) with GELU between
+them (GELU(z) = z Phi(z), Phi the standard normal CDF). Everything here is
+the plain definition, in float64:
+
+* features: geometry of the (source, module) pair and the optical
+  properties of the layers holding the source centre and the module;
+* baseline: the diffusion estimate of the hit probability,
+  mu_base = r^2 exp(-R/delta) / (4 D R), D = lambda_e/3,
+  delta = sqrt(D lambda_a), with lambda_e and lambda_a averaged over the two
+  layers; the network predicts log(mu / mu_base);
+* loss per pair: Poisson negative log-likelihood of the hit count,
+  mu_tot - k log mu_tot with mu_tot = N mu, plus the gamma negative
+  log-likelihood of the hit delays from their sufficient statistics
+  (n, sum delta, sum log delta): n (lgamma(kappa) + kappa log theta)
+  - (kappa - 1) sum log delta + sum delta / theta, kappa = exp(y1),
+  theta = tau0 exp(y2);
+* gradients by the chain rule written out layer by layer;
+* Adam (Kingma & Ba, 2015) with bias correction.
+
+Only the test suite imports it. Nothing in the product path does.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy import special
+
+C_LIGHT = 0.299792458
+IN_REAL, IN_PAD, HIDDEN, OUT_PAD, OUT_REAL = 16, 64, 256, 64, 3
+LAYER_SHAPES = [(HIDDEN, IN_PAD), (HIDDEN, HIDDEN), (HIDDEN, HIDDEN), (HIDDEN, HIDDEN),
+                (OUT_PAD, HIDDEN)]  # (out, in): weight matrices are out x in
+TAU0_NS = 50.0
+TIME_WEIGHT = 0.1
+
+
+def gelu(z):
+    return 0.5 * z * (1.0 + special.erf(z / math.sqrt(2.0)))
+
+
+def gelu_grad(z):
+    return 0.5 * (1.0 + special.erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2 * math.pi)
+
+
+# ---------------------------------------------------------------- features --
+
+def layer_index(z, z_lo, dz, n_layers):
+    f = np.floor((np.asarray(z, np.float64) - z_lo) / dz)
+    return np.clip(np.nan_to_num(f, nan=0.0), 0, n_layers - 1).astype(np.int64)
+
+
+def pair_features(w, src_idx, dom_idx):
+    """Features (P x 64, last 48 zero) and baseline mu_base (P) per photon
+    for (source, module) pairs of workload w (Cherenkov sources)."""
+    s = w.sources[np.asarray(src_idx)]
+    d = w.doms[np.asarray(dom_idx)]
+    L = w.layers
+    a_all = 1.0 / L["abs_len_m"].astype(np.float64)
+    g_all = L["g"].astype(np.float64)
+    le_all = L["eff_scat_len_m"].astype(np.float64)
+    dirv = np.stack([s["dx"], s["dy"], s["dz"]], 1).astype(np.float64)
+    dirv /= np.linalg.norm(dirv, axis=1, keepdims=True)
+    half = 0.5 * s["length_m"].astype(np.float64)
+    c = np.stack([s["x"], s["y"], s["z"]], 1).astype(np.float64) + half[:, None] * dirv
+    m = np.stack([d["x"], d["y"], d["z"]], 1).astype(np.float64)
+    delta = m - c
+    R = np.maximum(np.linalg.norm(delta, axis=1), 0.5)
+    u = delta / R[:, None]
+    cos_eta = (u * dirv).sum(1)
+    n_layers = len(L)
+    ls = layer_index(c[:, 2], w.z_lo_m, w.dz_m, n_layers)
+    ld = layer_index(m[:, 2], w.z_lo_m, w.dz_m, n_layers)
+    a_s, a_d = a_all[ls], a_all[ld]
+    b_s = 1.0 / (le_all[ls] * (1.0 - g_all[ls]))
+    b_d = 1.0 / (le_all[ld] * (1.0 - g_all[ld]))
+    X = np.zeros((len(R), IN_PAD))
+    X[:, 0:3] = u
+    X[:, 3] = R / 100.0
+    X[:, 4] = np.log(R / 10.0) / 3.0
+    X[:, 5] = cos_eta
+    X[:, 6] = cos_eta - math.cos(math.radians(41.0))
+    X[:, 7:10] = dirv
+    X[:, 10] = c[:, 2] / 500.0
+    X[:, 11] = m[:, 2] / 500.0
+    X[:, 12] = 100.0 * a_s
+    X[:, 13] = 10.0 * b_s
+    X[:, 14] = 100.0 * a_d
+    X[:, 15] = 10.0 * b_d
+    # diffusion baseline with the two layers' mean lengths
+    lam_a = 0.5 * (1.0 / a_s + 1.0 / a_d)
+    lam_e = 0.5 * (le_all[ls] + le_all[ld])
+    D = lam_e / 3.0
+    dl = np.sqrt(D * lam_a)
+    r = float(w.dom_radius_m)
+    mu_base = r * r * np.exp(-R / dl) / (4.0 * D * R)
+    return X, mu_base, R
+
+
+# ------------------------------------------------------------------- model --
+
+def init_params(seed: int):
+    """He-uniform init for each (out x in) weight; zero biases; the padded
+    input columns and padded outputs are zero."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for li, (n_out, n_in) in enumerate(LAYER_SHAPES):
+        fan_in = IN_REAL if li == 0 else n_in
+        lim = math.sqrt(6.0 / fan_in)
+        W = rng.uniform(-lim, lim, (n_out, n_in))
+        if li == 0:
+            W[:, IN_REAL:] = 0.0
+        if li == len(LAYER_SHAPES) - 1:
+            W *= 0.1
+            W[OUT_REAL:, :] = 0.0
+        params.append([W, np.zeros(n_out)])
+    return params
+
+
+def forward(params, X):
+    """Returns the outputs Y (P x 64) and the cache of pre-activations and
+    activations needed by backward."""
+    acts = [X]
+    pre = []
+    h = X
+    for li, (W, b) in enumerate(params):
+        z = h @ W.T + b
+        if li < len(params) - 1:
+            pre.append(z)
+            h = gelu(z)
+            acts.append(h)
+        else:
+            h = z
+    return h, (pre, acts)
+
+
+def loss_and_grad_out(Y, mu_base, n_photons, k, n_t, s1, s2):
+    """Mean over pairs of the Poisson + weighted gamma NLL, and dLoss/dY."""
+    P = Y.shape[0]
+    mu = n_photons * mu_base * np.exp(Y[:, 0])
+    kappa = np.exp(Y[:, 1])
+    theta = TAU0_NS * np.exp(Y[:, 2])
+    poisson = mu - k * np.log(mu)
+    gam = n_t * (special.gammaln(kappa) + kappa * np.log(theta)) - (kappa - 1.0) * s2 + s1 / theta
+    loss = (poisson + TIME_WEIGHT * gam).sum() / P
+    dY = np.zeros_like(Y)
+    dY[:, 0] = (mu - k) / P
+    dY[:, 1] = TIME_WEIGHT * kappa * (n_t * (special.digamma(kappa) + np.log(theta)) - s2) / P
+    dY[:, 2] = TIME_WEIGHT * (n_t * kappa - s1 / theta) / P
+    return loss, dY
+
+
+def backward(params, cache, dY):
+    """Gradients [(dW, db)] of the loss given dLoss/dY."""
+    pre, acts = cache
+    grads = [None] * len(params)
+    g = dY
+    for li in range(len(params) - 1, -1, -1):
+        W, _ = params[li]
+        h_in = acts[li]
+        grads[li] = (g.T @ h_in, g.sum(0))
+        if li > 0:
+            g = (g @ W) * gelu_grad(pre[li - 1])
+    return grads
+
+
+class Adam:
+    def __init__(self, params, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.lr, self.b1, self.b2, self.eps = lr, beta1, beta2, eps
+        self.m = [[np.zeros_like(W), np.zeros_like(b)] for W, b in params]
+        self.v = [[np.zeros_like(W), np.zeros_like(b)] for W, b in params]
+        self.t = 0
+
+    def step(self, params, grads):
+        self.t += 1
+        c1 = 1.0 - self.b1 ** self.t
+        c2 = 1.0 - self.b2 ** self.t
+        for li in range(len(params)):
+            for j in range(2):
+                g = grads[li][j]
+                self.m[li][j] = self.b1 * self.m[li][j] + (1 - self.b1) * g
+                self.v[li][j] = self.b2 * self.v[li][j] + (1 - self.b2) * g * g
+                mh = self.m[li][j] / c1
+                vh = self.v[li][j] / c2
+                params[li][j] = params[li][j] - self.lr * mh / (np.sqrt(vh) + self.eps)
+        return params
+
+
+def expected_hits_per_photon(params, X, mu_base):
+    Y, _ = forward(params, X)
+    return mu_base * np.exp(Y[:, 0])

@@ -10,8 +10,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpp.so")
-SOURCES = [os.path.join(CSRC, "pp_api.cpp"), os.path.join(CSRC, "pp_kernels.hip")]
-HEADERS = [os.path.join(CSRC, "pp_device.h"), os.path.join(ROOT, "include", "pp.h")]
+SOURCES = [os.path.join(CSRC, f) for f in ("pp_api.cpp", "pp_kernels.hip", "sur_api.cpp",
+                                            "sur_kernels.hip")]
+HEADERS = [os.path.join(CSRC, f) for f in ("pp_device.h", "pp_internal.h", "sur_device.h")] + \
+          [os.path.join(ROOT, "include", f) for f in ("pp.h", "pp_surrogate.h")]
 ARCH = "gfx950"
 
 # Packed-FP32 instructions are disabled: hipcc -O3 would otherwise form

@@ -17,69 +17,11 @@
 
 #include "../../include/pp.h"
 #include "pp_device.h"
-
-namespace {
-
-constexpr uint32_t kMaxLayers = 1024;
-constexpr uint32_t kMaxStrings = 512;
-constexpr uint32_t kGridSide = 64;  // at most 64 x 64 cells
-constexpr double kGridMargin = 1.0;
-constexpr double kClearanceMargin = 0.02;
-constexpr uint64_t kDefaultStepCap = 100000;
+#include "pp_internal.h"
 
 std::string g_create_error;
 
-struct Batch {
-  std::vector<pp::DevSource> src;
-  uint64_t n_photons = 0;
-  pp::DevSource *d_src = nullptr;
-  pp::DevChunk *d_chunks = nullptr;
-  uint32_t n_chunks = 0, chunk_size = 0;
-  unsigned long long *d_counters = nullptr;
-  pp::DevHit *d_hits = nullptr;
-  uint64_t hit_cap = 0;
-  void *d_rec = nullptr;
-  pp::Records rec{};
-  bool propagated = false, rec_valid = false;
-  hipStream_t stream = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  pp_launch_config used{};
-};
-
-}  // namespace
-
-struct pp_context {
-  int device = -1;
-  uint64_t seed = 0;
-  std::string err;
-  pp_launch_config cfg{};
-  uint64_t step_cap = kDefaultStepCap;
-  bool records = false;
-  int n_cu = 0;
-  // ice
-  bool ice_loaded = false;
-  pp_ice_header ice{};
-  std::vector<pp::DevLayer> layers;
-  std::vector<float> bounds;
-  pp::DevLayer *d_layers = nullptr;
-  float *d_bounds = nullptr;
-  // geometry
-  bool geo_loaded = false;
-  uint32_t n_doms = 0;
-  float radius = 0;
-  std::vector<pp::DevString> strings;
-  std::vector<uint32_t> cells;
-  std::vector<float4> doms_sorted;
-  pp_geometry_info geo{};
-  pp::DevString *d_strings = nullptr;
-  uint32_t *d_cells = nullptr;
-  float4 *d_doms = nullptr;
-  // batches
-  std::map<uint64_t, Batch> batches;
-  uint64_t next_batch = 1;
-};
-
-namespace {
+namespace ppi {
 
 pp_status fail(pp_context *ctx, pp_status st, const char *fmt, ...) {
   char buf[512];
@@ -91,13 +33,6 @@ pp_status fail(pp_context *ctx, pp_status st, const char *fmt, ...) {
   return st;
 }
 
-#define PP_HIP(ctx, expr)                                                                   \
-  do {                                                                                      \
-    const hipError_t e_ = (expr);                                                           \
-    if (e_ != hipSuccess)                                                                   \
-      return fail((ctx), e_ == hipErrorOutOfMemory ? PP_ENOMEM : PP_EDEVICE, "%s: %s", #expr, \
-                  hipGetErrorString(e_));                                                   \
-  } while (0)
 
 bool finite(float v) { return std::isfinite(v); }
 
@@ -119,8 +54,14 @@ pp_status upload(pp_context *ctx, T **dptr, const std::vector<T> &host) {
   return PP_OK;
 }
 
+void drop_graph(Batch &b) {
+  if (b.graph) (void)hipGraphExecDestroy(b.graph);
+  b.graph = nullptr;
+}
+
 void free_batch(Batch &b) {
   if (b.ev1) (void)hipEventSynchronize(b.ev1);
+  drop_graph(b);
   (void)hipFree(b.d_src);
   (void)hipFree(b.d_chunks);
   (void)hipFree(b.d_counters);
@@ -286,6 +227,7 @@ pp_status build_chunks(pp_context *ctx, Batch &b, uint32_t chunk) {
     }
   }
   if (ch.size() >= 0xFFFFFFFFull) return fail(ctx, PP_EINVAL, "too many work chunks; raise chunk_size");
+  drop_graph(b);
   pp_status st = upload(ctx, &b.d_chunks, ch);
   if (st != PP_OK) return st;
   b.n_chunks = static_cast<uint32_t>(ch.size());
@@ -294,6 +236,7 @@ pp_status build_chunks(pp_context *ctx, Batch &b, uint32_t chunk) {
 }
 
 pp_status alloc_hits(pp_context *ctx, Batch &b, uint64_t cap) {
+  drop_graph(b);
   (void)hipFree(b.d_hits);
   b.d_hits = nullptr;
   b.hit_cap = 0;
@@ -314,7 +257,15 @@ pp_status alloc_records(pp_context *ctx, Batch &b) {
   return PP_OK;
 }
 
-pp_status launch(pp_context *ctx, Batch &b, hipStream_t stream) {
+struct Prepared {
+  pp::PropagateArgs args;
+  uint32_t grid, block;
+  pp_launch_config used;
+};
+
+// Allocates what the batch needs for the context's launch configuration and
+// fills the kernel arguments. No work is enqueued.
+pp_status prepare(pp_context *ctx, Batch &b, Prepared *out) {
   const pp_launch_config &c = ctx->cfg;
   const uint32_t block = c.block_size ? c.block_size : default_block();
   const size_t lds = pp::propagate_lds_bytes(static_cast<int>(ctx->ice.n_layers),
@@ -385,19 +336,43 @@ pp_status launch(pp_context *ctx, Batch &b, hipStream_t stream) {
   a.hit_capacity = b.hit_cap;
   if (ctx->records) a.rec = b.rec;
 
+  out->args = a;
+  out->grid = grid;
+  out->block = block;
+  out->used = c;
+  out->used.block_size = block;
+  out->used.chunk_size = chunk;
+  out->used.grid_blocks = grid;
+  out->used.refill_interval = a.refill_interval;
+  out->used.hit_capacity = b.hit_cap;
+  return PP_OK;
+}
+
+// Counter reset and the propagation kernel on the stream (what a graph
+// captures).
+pp_status enqueue(pp_context *ctx, Batch &b, const Prepared &p, hipStream_t stream) {
   PP_HIP(ctx, pp::launch_reset(b.d_counters, pp::kNumCounters, stream));
-  PP_HIP(ctx, hipEventRecord(b.ev0, stream));
-  if (b.n_chunks > 0) PP_HIP(ctx, pp::launch_propagate(a, static_cast<int>(grid), static_cast<int>(block), stream));
-  PP_HIP(ctx, hipEventRecord(b.ev1, stream));
+  if (b.n_chunks > 0)
+    PP_HIP(ctx, pp::launch_propagate(p.args, static_cast<int>(p.grid), static_cast<int>(p.block), stream));
+  return PP_OK;
+}
+
+void mark_propagated(pp_context *ctx, Batch &b, const pp_launch_config &used, bool records, hipStream_t stream) {
+  (void)ctx;
   b.stream = stream;
   b.propagated = true;
-  b.rec_valid = ctx->records;
-  b.used = c;
-  b.used.block_size = block;
-  b.used.chunk_size = chunk;
-  b.used.grid_blocks = grid;
-  b.used.refill_interval = a.refill_interval;
-  b.used.hit_capacity = b.hit_cap;
+  b.rec_valid = records;
+  b.used = used;
+}
+
+pp_status launch(pp_context *ctx, Batch &b, hipStream_t stream) {
+  Prepared p;
+  pp_status st = prepare(ctx, b, &p);
+  if (st != PP_OK) return st;
+  PP_HIP(ctx, hipEventRecord(b.ev0, stream));
+  if ((st = enqueue(ctx, b, p, stream)) != PP_OK) return st;
+  PP_HIP(ctx, hipEventRecord(b.ev1, stream));
+  mark_propagated(ctx, b, p.used, ctx->records, stream);
   return PP_OK;
 }
 
@@ -438,7 +413,9 @@ pp_status complete_hits(pp_context *ctx, Batch &b, uint64_t *n_total) {
   return PP_OK;
 }
 
-}  // namespace
+}  // namespace ppi
+
+using namespace ppi;
 
 extern "C" {
 
@@ -824,6 +801,95 @@ pp_status pp_get_stats(pp_context *ctx, uint64_t batch, pp_stats *out) {
   PP_HIP(ctx, hipEventElapsedTime(&ms, b->ev0, b->ev1));
   out->kernel_ms = ms;
   out->reserved = 0;
+  return PP_OK;
+}
+
+pp_status pp_autotune(pp_context *ctx, uint64_t batch, void *hip_stream, pp_launch_config *best) {
+  if (!ctx) return PP_EINVAL;
+  Batch *b;
+  pp_status st = find_batch(ctx, batch, &b);
+  if (st != PP_OK) return st;
+  if ((st = need_device(ctx)) != PP_OK) return st;
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  const pp_launch_config base = ctx->cfg;
+  pp_launch_config winner = base;
+  float best_ms = -1.0f;
+  const uint32_t blocks[] = {256, 512};
+  const uint32_t chunks[] = {64, 256, 1024};
+  const uint32_t refills[] = {4, 8, 16};
+  bool first = true;
+  for (uint32_t blk : blocks)
+    for (uint32_t chk : chunks)
+      for (uint32_t rf : refills) {
+        pp_launch_config c = base;
+        c.block_size = blk;
+        c.chunk_size = chk;
+        c.refill_interval = rf;
+        c.grid_blocks = 0;
+        ctx->cfg = c;
+        if (first) {  // warm-up (allocations, code load)
+          if ((st = launch(ctx, *b, stream)) != PP_OK) break;
+          first = false;
+        }
+        if ((st = launch(ctx, *b, stream)) != PP_OK) break;
+        float ms = 0;
+        if (hipEventSynchronize(b->ev1) != hipSuccess || hipEventElapsedTime(&ms, b->ev0, b->ev1) != hipSuccess) {
+          st = fail(ctx, PP_EDEVICE, "timing failed during autotune");
+          break;
+        }
+        if (best_ms < 0 || ms < best_ms) {
+          best_ms = ms;
+          winner = c;
+        }
+      }
+  ctx->cfg = st == PP_OK ? winner : base;
+  if (st != PP_OK) return st;
+  if (best) *best = winner;
+  return PP_OK;
+}
+
+pp_status pp_graph_capture(pp_context *ctx, uint64_t batch, void *hip_stream) {
+  if (!ctx) return PP_EINVAL;
+  if (!hip_stream) return fail(ctx, PP_EINVAL, "graph capture needs a non-null stream");
+  Batch *b;
+  pp_status st = find_batch(ctx, batch, &b);
+  if (st != PP_OK) return st;
+  if ((st = need_device(ctx)) != PP_OK) return st;
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  Prepared p;
+  if ((st = prepare(ctx, *b, &p)) != PP_OK) return st;
+  drop_graph(*b);
+  PP_HIP(ctx, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  st = enqueue(ctx, *b, p, stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(stream, &g);
+  if (st != PP_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(ctx, PP_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) return fail(ctx, PP_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+  b->graph = exec;
+  b->graph_cfg = p.used;
+  b->graph_records = ctx->records;
+  return PP_OK;
+}
+
+pp_status pp_graph_launch(pp_context *ctx, uint64_t batch, void *hip_stream) {
+  if (!ctx) return PP_EINVAL;
+  Batch *b;
+  pp_status st = find_batch(ctx, batch, &b);
+  if (st != PP_OK) return st;
+  if ((st = need_device(ctx)) != PP_OK) return st;
+  if (!b->graph) return fail(ctx, PP_ESTATE, "no captured graph for this batch (captured buffers changed?)");
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  PP_HIP(ctx, hipEventRecord(b->ev0, stream));
+  PP_HIP(ctx, hipGraphLaunch(b->graph, stream));
+  PP_HIP(ctx, hipEventRecord(b->ev1, stream));
+  mark_propagated(ctx, *b, b->graph_cfg, b->graph_records, stream);
   return PP_OK;
 }
 

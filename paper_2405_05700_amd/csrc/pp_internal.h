@@ -1,0 +1,90 @@
+// Internal definitions shared by the host-side translation units of libpp
+// (pp_api.cpp and sur_api.cpp): the context, its batches, and helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/pp.h"
+#include "pp_device.h"
+
+namespace ppi {
+
+constexpr uint32_t kMaxLayers = 1024;
+constexpr uint32_t kMaxStrings = 512;
+constexpr uint32_t kGridSide = 64;  // at most 64 x 64 cells
+constexpr double kGridMargin = 1.0;
+constexpr double kClearanceMargin = 0.02;
+constexpr uint64_t kDefaultStepCap = 100000;
+
+struct Batch {
+  std::vector<pp::DevSource> src;
+  uint64_t n_photons = 0;
+  pp::DevSource *d_src = nullptr;
+  pp::DevChunk *d_chunks = nullptr;
+  uint32_t n_chunks = 0, chunk_size = 0;
+  unsigned long long *d_counters = nullptr;
+  pp::DevHit *d_hits = nullptr;
+  uint64_t hit_cap = 0;
+  void *d_rec = nullptr;
+  pp::Records rec{};
+  bool propagated = false, rec_valid = false;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  pp_launch_config used{};
+  hipGraphExec_t graph = nullptr;  // captured reset + propagation, if any
+  pp_launch_config graph_cfg{};
+  bool graph_records = false;
+};
+
+}  // namespace ppi
+
+struct pp_context {
+  int device = -1;
+  uint64_t seed = 0;
+  std::string err;
+  pp_launch_config cfg{};
+  uint64_t step_cap = ppi::kDefaultStepCap;
+  bool records = false;
+  int n_cu = 0;
+  // ice
+  bool ice_loaded = false;
+  pp_ice_header ice{};
+  std::vector<pp::DevLayer> layers;
+  std::vector<float> bounds;
+  pp::DevLayer *d_layers = nullptr;
+  float *d_bounds = nullptr;
+  // geometry
+  bool geo_loaded = false;
+  uint32_t n_doms = 0;
+  float radius = 0;
+  std::vector<pp::DevString> strings;
+  std::vector<uint32_t> cells;
+  std::vector<float4> doms_sorted;
+  pp_geometry_info geo{};
+  pp::DevString *d_strings = nullptr;
+  uint32_t *d_cells = nullptr;
+  float4 *d_doms = nullptr;
+  // batches
+  std::map<uint64_t, ppi::Batch> batches;
+  uint64_t next_batch = 1;
+};
+
+
+namespace ppi {
+pp_status fail(pp_context *ctx, pp_status st, const char *fmt, ...);
+pp_status need_device(pp_context *ctx);
+pp_status find_batch(pp_context *ctx, uint64_t id, Batch **out);
+pp_status complete_hits(pp_context *ctx, Batch &b, uint64_t *n_total);
+}  // namespace ppi
+
+#define PP_HIP(ctx, expr)                                                                   \
+  do {                                                                                      \
+    const hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                                   \
+      return fail((ctx), e_ == hipErrorOutOfMemory ? PP_ENOMEM : PP_EDEVICE, "%s: %s", #expr, \
+                  hipGetErrorString(e_));                                                   \
+  } while (0)

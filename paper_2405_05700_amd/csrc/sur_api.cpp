@@ -1,0 +1,570 @@
+// Host side of the surrogate C ABI (include/pp_surrogate.h): parameter and
+// Adam state, training set (features and Monte Carlo labels on the device),
+// minibatch forward/backward on the matrix cores, and chunked inference.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "../../include/pp_surrogate.h"
+#include "pp_internal.h"
+#include "sur_device.h"
+
+using namespace ppi;
+
+struct pp_surrogate {
+  pp_context *ctx = nullptr;
+  int n_doms = 0;
+  // parameters (f32 master), gradient, Adam moments, bf16 copies
+  float *theta = nullptr, *grad = nullptr, *adam_m = nullptr, *adam_v = nullptr;
+  uint16_t *wb = nullptr, *wt = nullptr;
+  int64_t adam_t = 0;
+  float4 *doms_by_id = nullptr;
+  // training set
+  int64_t P = 0, P_pad = 0;
+  uint16_t *X = nullptr, *XT = nullptr;
+  float *mu_base = nullptr, *nph = nullptr, *k = nullptr, *n_t = nullptr, *s1 = nullptr, *s2 = nullptr;
+  // minibatch work buffers (capacity Mcap rows)
+  int64_t Mcap = 0;
+  float *Z[4] = {};
+  uint16_t *H[4] = {}, *HT[4] = {};
+  float *Y = nullptr;
+  uint16_t *dY = nullptr, *dYT = nullptr, *dZ[2] = {}, *dZT = nullptr;
+  double *d_loss = nullptr;
+  double *epoch_loss = nullptr;  // device accumulator while training, else null
+  // inference buffers (capacity Icap rows)
+  int64_t Icap = 0;
+  uint16_t *iX = nullptr, *iH[2] = {};
+  float *i_mu = nullptr, *i_mub = nullptr, *i_nph = nullptr;
+};
+
+namespace {
+
+constexpr int64_t kInferRows = 1 << 21;  // pairs per inference chunk
+
+int64_t round64(int64_t n) { return (n + 63) / 64 * 64; }
+
+template <class T>
+pp_status dalloc(pp_context *ctx, T **p, int64_t n) {
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  PP_HIP(ctx, hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * std::max<int64_t>(n, 1)));
+  return PP_OK;
+}
+
+template <class T>
+void dfree(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+pp_status gemm(pp_context *ctx, int epi, const uint16_t *A, int64_t lda, const uint16_t *B, int64_t ldb, int M,
+               int N, int K, int splits, const float *bias, float *Z, uint16_t *H, uint16_t *HT, int64_t ldt,
+               const float *Zin, float *out, const float *nph, const float *mub, hipStream_t st) {
+  sur::GemmArgs g{};
+  g.A = A;
+  g.lda = lda;
+  g.B = B;
+  g.ldb = ldb;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  splits = std::max(1, std::min(splits, K / 32));
+  g.k_chunk = ((K + splits - 1) / splits + 31) / 32 * 32;
+  splits = (K + g.k_chunk - 1) / g.k_chunk;
+  g.bias = bias;
+  g.Z = Z;
+  g.H = H;
+  g.HT = HT;
+  g.ldt = ldt;
+  g.Zin = Zin;
+  g.out = out;
+  g.row_nph = nph;
+  g.row_mubase = mub;
+  PP_HIP(ctx, sur::launch_gemm(epi, g, splits, st));
+  return PP_OK;
+}
+
+const float *bias_ptr(const pp_surrogate *s, int l) { return s->theta + sur::b_offset(l); }
+const uint16_t *wb_ptr(const pp_surrogate *s, int l) { return s->wb + sur::wb_offset(l); }
+const uint16_t *wt_ptr(const pp_surrogate *s, int l) { return s->wt + sur::wb_offset(l); }
+
+pp_status ensure_work(pp_surrogate *s, int64_t M) {
+  if (M <= s->Mcap) return PP_OK;
+  pp_context *ctx = s->ctx;
+  pp_status st;
+  for (int l = 0; l < 4; ++l) {
+    if ((st = dalloc(ctx, &s->Z[l], M * sur::kHidden)) != PP_OK) return st;
+    if ((st = dalloc(ctx, &s->H[l], M * sur::kHidden)) != PP_OK) return st;
+    if ((st = dalloc(ctx, &s->HT[l], M * sur::kHidden)) != PP_OK) return st;
+  }
+  if ((st = dalloc(ctx, &s->Y, M * sur::kOutPad)) != PP_OK) return st;
+  if ((st = dalloc(ctx, &s->dY, M * sur::kOutPad)) != PP_OK) return st;
+  if ((st = dalloc(ctx, &s->dYT, M * sur::kOutPad)) != PP_OK) return st;
+  if ((st = dalloc(ctx, &s->dZ[0], M * sur::kHidden)) != PP_OK) return st;
+  if ((st = dalloc(ctx, &s->dZ[1], M * sur::kHidden)) != PP_OK) return st;
+  if ((st = dalloc(ctx, &s->dZT, M * sur::kHidden)) != PP_OK) return st;
+  s->Mcap = M;
+  return PP_OK;
+}
+
+// Forward, loss and backward over training rows [first, first + count);
+// leaves the gradient in s->grad and the summed loss in s->d_loss.
+pp_status forward_backward(pp_surrogate *s, int64_t first, int64_t count, hipStream_t st) {
+  pp_context *ctx = s->ctx;
+  if (first % 64 != 0 || count <= 0 || first + count > s->P)
+    return fail(ctx, PP_EINVAL, "rows [%lld, %lld) invalid: start must be a multiple of 64 within %lld pairs",
+                (long long)first, (long long)(first + count), (long long)s->P);
+  const int M = static_cast<int>(round64(count));
+  pp_status rc = ensure_work(s, M);
+  if (rc != PP_OK) return rc;
+  using namespace sur;
+  const uint16_t *X = s->X + first * kInPad;
+  const uint16_t *XT = s->XT + first;  // columns [first, first + M) of 64 x P_pad
+  // forward
+  const uint16_t *in = X;
+  int64_t ld_in = kInPad;
+  for (int l = 0; l < 4; ++l) {
+    if ((rc = gemm(ctx, kEpiGelu, in, ld_in, wb_ptr(s, l), in_dim(l), M, kHidden, in_dim(l), 1, bias_ptr(s, l),
+                   s->Z[l], s->H[l], s->HT[l], M, nullptr, nullptr, nullptr, nullptr, st)) != PP_OK)
+      return rc;
+    in = s->H[l];
+    ld_in = kHidden;
+  }
+  if ((rc = gemm(ctx, kEpiLinear, s->H[3], kHidden, wb_ptr(s, 4), kHidden, M, kOutPad, kHidden, 1, bias_ptr(s, 4),
+                 nullptr, nullptr, nullptr, 0, nullptr, s->Y, nullptr, nullptr, st)) != PP_OK)
+    return rc;
+  // loss and output gradient
+  PP_HIP(ctx, launch_zero_f64(s->d_loss, 1, st));
+  LossArgs la{};
+  la.Y = s->Y;
+  la.mu_base = s->mu_base + first;
+  la.nph = s->nph + first;
+  la.k = s->k + first;
+  la.n_t = s->n_t + first;
+  la.s1 = s->s1 + first;
+  la.s2 = s->s2 + first;
+  la.M_real = static_cast<int>(count);
+  la.M_pad = M;
+  la.inv_norm = 1.0f / static_cast<float>(count);
+  la.dY = s->dY;
+  la.dYT = s->dYT;
+  la.loss_sum = s->d_loss;
+  la.loss_epoch = s->epoch_loss;
+  PP_HIP(ctx, launch_loss(la, st));
+  // backward
+  PP_HIP(ctx, launch_zero_f32(s->grad, param_count(), st));
+  const int splits = std::max(1, M / 512);
+  // output layer
+  if ((rc = gemm(ctx, kEpiAccum, s->dYT, M, s->HT[3], M, kOutPad, kHidden, M, splits, nullptr, nullptr, nullptr,
+                 nullptr, 0, nullptr, s->grad + w_offset(4), nullptr, nullptr, st)) != PP_OK)
+    return rc;
+  PP_HIP(ctx, launch_rowsum(s->dYT, M, kOutPad, M, s->grad + b_offset(4), st));
+  // dZ3 = (dY . W4) * gelu'(Z3)
+  if ((rc = gemm(ctx, kEpiGeluBwd, s->dY, kOutPad, wt_ptr(s, 4), kOutPad, M, kHidden, kOutPad, 1, nullptr,
+                 nullptr, s->dZ[1], s->dZT, M, s->Z[3], nullptr, nullptr, nullptr, st)) != PP_OK)
+    return rc;
+  int cur = 1;
+  for (int l = 3; l >= 0; --l) {
+    // dW_l = dZ_l^T . H_{l-1} (X for l = 0), db_l = row sums of dZ_l^T
+    const uint16_t *prevT = l > 0 ? s->HT[l - 1] : XT;
+    const int64_t ld_prevT = l > 0 ? M : s->P_pad;
+    if ((rc = gemm(ctx, kEpiAccum, s->dZT, M, prevT, ld_prevT, kHidden, in_dim(l), M, splits, nullptr, nullptr,
+                   nullptr, nullptr, 0, nullptr, s->grad + w_offset(l), nullptr, nullptr, st)) != PP_OK)
+      return rc;
+    PP_HIP(ctx, launch_rowsum(s->dZT, M, kHidden, M, s->grad + b_offset(l), st));
+    if (l == 0) break;
+    // dZ_{l-1} = (dZ_l . W_l) * gelu'(Z_{l-1})
+    if ((rc = gemm(ctx, kEpiGeluBwd, s->dZ[cur], kHidden, wt_ptr(s, l), kHidden, M, kHidden, kHidden, 1, nullptr,
+                   nullptr, s->dZ[1 - cur], s->dZT, M, s->Z[l - 1], nullptr, nullptr, nullptr, st)) != PP_OK)
+      return rc;
+    cur = 1 - cur;
+  }
+  return PP_OK;
+}
+
+pp_status adam_step(pp_surrogate *s, float lr, hipStream_t st) {
+  s->adam_t += 1;
+  const float c1 = 1.0f - std::pow(0.9f, static_cast<float>(s->adam_t));
+  const float c2 = 1.0f - std::pow(0.999f, static_cast<float>(s->adam_t));
+  PP_HIP(s->ctx, sur::launch_adam(s->theta, s->grad, s->adam_m, s->adam_v, sur::param_count(), lr, c1, c2, st));
+  PP_HIP(s->ctx, sur::launch_pack_weights(s->theta, s->wb, s->wt, st));
+  return PP_OK;
+}
+
+// He-uniform initialisation (fan-in of the real inputs), zero biases, zero
+// padded input columns and padded outputs, output layer scaled by 0.1.
+std::vector<float> init_params(uint64_t seed) {
+  std::vector<float> th(sur::param_count(), 0.0f);
+  std::mt19937_64 rng(seed);
+  std::uniform_real_distribution<double> uni(-1.0, 1.0);
+  for (int l = 0; l < sur::kLayers; ++l) {
+    const int n_in = sur::in_dim(l), n_out = sur::out_dim(l);
+    const double lim = std::sqrt(6.0 / (l == 0 ? sur::kInReal : n_in)) * (l == sur::kLayers - 1 ? 0.1 : 1.0);
+    for (int o = 0; o < n_out; ++o)
+      for (int i = 0; i < n_in; ++i) {
+        const bool pad = (l == 0 && i >= sur::kInReal) || (l == sur::kLayers - 1 && o >= sur::kOutReal);
+        const double w = lim * uni(rng);
+        th[sur::w_offset(l) + static_cast<int64_t>(o) * n_in + i] = pad ? 0.0f : static_cast<float>(w);
+      }
+  }
+  return th;
+}
+
+pp_status upload_params(pp_surrogate *s, const float *host) {
+  PP_HIP(s->ctx, hipMemcpy(s->theta, host, sizeof(float) * sur::param_count(), hipMemcpyHostToDevice));
+  PP_HIP(s->ctx, hipMemset(s->adam_m, 0, sizeof(float) * sur::param_count()));
+  PP_HIP(s->ctx, hipMemset(s->adam_v, 0, sizeof(float) * sur::param_count()));
+  s->adam_t = 0;
+  PP_HIP(s->ctx, sur::launch_pack_weights(s->theta, s->wb, s->wt, nullptr));
+  PP_HIP(s->ctx, hipDeviceSynchronize());
+  return PP_OK;
+}
+
+sur::FeatureArgs feature_args(pp_surrogate *s, const Batch &b, const float *src_nph) {
+  pp_context *ctx = s->ctx;
+  sur::FeatureArgs f{};
+  f.sources = b.d_src;
+  f.src_nph = src_nph;
+  f.n_sources_set = static_cast<int>(b.src.size());
+  f.doms = s->doms_by_id;
+  f.n_doms = s->n_doms;
+  f.layers = ctx->d_layers;
+  f.n_layers = static_cast<int>(ctx->ice.n_layers);
+  f.z_lo = ctx->ice.z_lo_m;
+  f.inv_dz = static_cast<float>(1.0 / ctx->ice.dz_m);
+  f.radius = ctx->radius;
+  return f;
+}
+
+std::vector<float> source_photons(const Batch &b) {
+  std::vector<float> n(b.src.size());
+  for (size_t i = 0; i < b.src.size(); ++i) {
+    const uint64_t end = i + 1 < b.src.size() ? b.src[i + 1].seq_base : b.n_photons;
+    n[i] = static_cast<float>(end - b.src[i].seq_base);
+  }
+  return n;
+}
+
+pp_status check_cherenkov(pp_context *ctx, const Batch &b) {
+  for (size_t i = 0; i < b.src.size(); ++i)
+    if (b.src[i].ids.x != PP_SOURCE_CHERENKOV)
+      return fail(ctx, PP_EINVAL, "surrogate sources must be Cherenkov segments (source %zu is not)", i);
+  return PP_OK;
+}
+
+// Runs the network over every pair of batch b in chunks of whole sources;
+// calls sink(mu, first_source, n_sources) after each chunk.
+template <class Sink>
+pp_status infer(pp_surrogate *s, Batch &b, hipStream_t st, Sink sink) {
+  pp_context *ctx = s->ctx;
+  using namespace sur;
+  const int64_t n_src = static_cast<int64_t>(b.src.size());
+  const int64_t per_chunk = std::max<int64_t>(1, kInferRows / std::max(s->n_doms, 1));
+  const int64_t rows_cap = round64(per_chunk * s->n_doms);
+  pp_status rc;
+  if (rows_cap > s->Icap) {
+    if ((rc = dalloc(ctx, &s->iX, rows_cap * kInPad)) != PP_OK) return rc;
+    if ((rc = dalloc(ctx, &s->iH[0], rows_cap * kHidden)) != PP_OK) return rc;
+    if ((rc = dalloc(ctx, &s->iH[1], rows_cap * kHidden)) != PP_OK) return rc;
+    if ((rc = dalloc(ctx, &s->i_mu, rows_cap)) != PP_OK) return rc;
+    if ((rc = dalloc(ctx, &s->i_mub, rows_cap)) != PP_OK) return rc;
+    if ((rc = dalloc(ctx, &s->i_nph, rows_cap)) != PP_OK) return rc;
+    s->Icap = rows_cap;
+  }
+  const std::vector<float> nph = source_photons(b);
+  float *d_src_nph = nullptr;
+  if ((rc = dalloc(ctx, &d_src_nph, static_cast<int64_t>(nph.size()))) != PP_OK) return rc;
+  if (!nph.empty()) PP_HIP(ctx, hipMemcpy(d_src_nph, nph.data(), sizeof(float) * nph.size(), hipMemcpyHostToDevice));
+  for (int64_t s0 = 0; s0 < n_src; s0 += per_chunk) {
+    const int64_t ns = std::min(per_chunk, n_src - s0);
+    const int64_t pairs = ns * s->n_doms;
+    const int M = static_cast<int>(round64(pairs));
+    FeatureArgs f = feature_args(s, b, d_src_nph);
+    f.first_pair = s0 * s->n_doms;
+    f.n_pairs = pairs;
+    f.X = s->iX;
+    f.mu_base = s->i_mub;
+    f.nph = s->i_nph;
+    PP_HIP(ctx, launch_features(f, st));
+    const uint16_t *in = s->iX;
+    int64_t ld_in = kInPad;
+    for (int l = 0; l < 4; ++l) {
+      uint16_t *out = s->iH[l & 1];
+      if ((rc = gemm(ctx, kEpiGelu, in, ld_in, wb_ptr(s, l), in_dim(l), M, kHidden, in_dim(l), 1, bias_ptr(s, l),
+                     nullptr, out, nullptr, 0, nullptr, nullptr, nullptr, nullptr, st)) != PP_OK)
+        break;
+      in = out;
+      ld_in = kHidden;
+    }
+    if (rc != PP_OK) break;
+    if ((rc = gemm(ctx, kEpiMu, in, kHidden, wb_ptr(s, 4), kHidden, M, kOutPad, kHidden, 1, bias_ptr(s, 4),
+                   nullptr, nullptr, nullptr, 0, nullptr, s->i_mu, s->i_nph, s->i_mub, st)) != PP_OK)
+      break;
+    if ((rc = sink(s->i_mu, s0, ns)) != PP_OK) break;
+  }
+  (void)hipStreamSynchronize(st);
+  dfree(d_src_nph);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t pp_sur_param_count(void) { return static_cast<uint64_t>(sur::param_count()); }
+
+pp_status pp_sur_create(pp_context *ctx, uint64_t init_seed, pp_surrogate **out) {
+  if (!ctx || !out) return PP_EINVAL;
+  *out = nullptr;
+  pp_status st = need_device(ctx);
+  if (st != PP_OK) return st;
+  if (!ctx->ice_loaded || !ctx->geo_loaded) return fail(ctx, PP_ESTATE, "load ice and geometry first");
+  pp_surrogate *s = new (std::nothrow) pp_surrogate;
+  if (!s) return PP_ENOMEM;
+  s->ctx = ctx;
+  s->n_doms = static_cast<int>(ctx->n_doms);
+  const int64_t np = sur::param_count();
+  if ((st = dalloc(ctx, &s->theta, np)) != PP_OK || (st = dalloc(ctx, &s->grad, np)) != PP_OK ||
+      (st = dalloc(ctx, &s->adam_m, np)) != PP_OK || (st = dalloc(ctx, &s->adam_v, np)) != PP_OK ||
+      (st = dalloc(ctx, &s->wb, sur::wb_count())) != PP_OK || (st = dalloc(ctx, &s->wt, sur::wb_count())) != PP_OK ||
+      (st = dalloc(ctx, &s->d_loss, 1)) != PP_OK) {
+    pp_sur_destroy(s);
+    return st;
+  }
+  // module centres in module-id order
+  std::vector<float4> by_id(std::max<size_t>(ctx->doms_sorted.size(), 1));
+  for (const float4 &d : ctx->doms_sorted) {
+    uint32_t id;
+    std::memcpy(&id, &d.w, 4);
+    by_id[id] = d;
+  }
+  if ((st = dalloc(ctx, &s->doms_by_id, static_cast<int64_t>(by_id.size()))) != PP_OK) {
+    pp_sur_destroy(s);
+    return st;
+  }
+  (void)hipMemcpy(s->doms_by_id, by_id.data(), sizeof(float4) * by_id.size(), hipMemcpyHostToDevice);
+  const std::vector<float> th = init_params(init_seed);
+  if ((st = upload_params(s, th.data())) != PP_OK) {
+    pp_sur_destroy(s);
+    return st;
+  }
+  *out = s;
+  return PP_OK;
+}
+
+void pp_sur_destroy(pp_surrogate *s) {
+  if (!s) return;
+  if (s->ctx && s->ctx->device >= 0) (void)hipSetDevice(s->ctx->device);
+  (void)hipDeviceSynchronize();
+  dfree(s->theta), dfree(s->grad), dfree(s->adam_m), dfree(s->adam_v), dfree(s->wb), dfree(s->wt);
+  dfree(s->doms_by_id), dfree(s->X), dfree(s->XT), dfree(s->mu_base), dfree(s->nph);
+  dfree(s->k), dfree(s->n_t), dfree(s->s1), dfree(s->s2);
+  for (int l = 0; l < 4; ++l) dfree(s->Z[l]), dfree(s->H[l]), dfree(s->HT[l]);
+  dfree(s->Y), dfree(s->dY), dfree(s->dYT), dfree(s->dZ[0]), dfree(s->dZ[1]), dfree(s->dZT), dfree(s->d_loss);
+  dfree(s->iX), dfree(s->iH[0]), dfree(s->iH[1]), dfree(s->i_mu), dfree(s->i_mub), dfree(s->i_nph);
+  delete s;
+}
+
+pp_status pp_sur_get_params(pp_surrogate *s, float *out, uint64_t n) {
+  if (!s || !out) return PP_EINVAL;
+  if (n != pp_sur_param_count()) return fail(s->ctx, PP_EINVAL, "expected %llu parameters", (unsigned long long)pp_sur_param_count());
+  PP_HIP(s->ctx, hipSetDevice(s->ctx->device));
+  PP_HIP(s->ctx, hipDeviceSynchronize());
+  PP_HIP(s->ctx, hipMemcpy(out, s->theta, sizeof(float) * n, hipMemcpyDeviceToHost));
+  return PP_OK;
+}
+
+pp_status pp_sur_set_params(pp_surrogate *s, const float *in, uint64_t n) {
+  if (!s || !in) return PP_EINVAL;
+  if (n != pp_sur_param_count()) return fail(s->ctx, PP_EINVAL, "expected %llu parameters", (unsigned long long)pp_sur_param_count());
+  PP_HIP(s->ctx, hipSetDevice(s->ctx->device));
+  for (uint64_t i = 0; i < n; ++i)
+    if (!std::isfinite(in[i])) return fail(s->ctx, PP_EINVAL, "parameter %llu is not finite", (unsigned long long)i);
+  return upload_params(s, in);
+}
+
+pp_status pp_sur_set_training_set(pp_surrogate *s, uint64_t batch) {
+  if (!s) return PP_EINVAL;
+  pp_context *ctx = s->ctx;
+  pp_status st = need_device(ctx);
+  if (st != PP_OK) return st;
+  Batch *b;
+  if ((st = find_batch(ctx, batch, &b)) != PP_OK) return st;
+  if ((st = check_cherenkov(ctx, *b)) != PP_OK) return st;
+  uint64_t n_hits = 0;
+  if ((st = complete_hits(ctx, *b, &n_hits)) != PP_OK) return st;
+  const int64_t n_src = static_cast<int64_t>(b->src.size());
+  // event id -> source index (each source its own event)
+  uint32_t max_event = 0;
+  for (const auto &d : b->src) max_event = std::max(max_event, d.ids.y);
+  if (max_event > (1u << 26)) return fail(ctx, PP_EINVAL, "event ids up to 2^26 supported for training");
+  std::vector<int32_t> ev(max_event + 1, -1);
+  for (int64_t i = 0; i < n_src; ++i) {
+    if (ev[b->src[i].ids.y] >= 0) return fail(ctx, PP_EINVAL, "training sources need distinct event ids");
+    ev[b->src[i].ids.y] = static_cast<int32_t>(i);
+  }
+  s->P = n_src * s->n_doms;
+  s->P_pad = round64(s->P);
+  const int64_t R = s->P_pad;
+  if ((st = dalloc(ctx, &s->X, R * sur::kInPad)) != PP_OK || (st = dalloc(ctx, &s->XT, R * sur::kInPad)) != PP_OK ||
+      (st = dalloc(ctx, &s->mu_base, R)) != PP_OK || (st = dalloc(ctx, &s->nph, R)) != PP_OK ||
+      (st = dalloc(ctx, &s->k, R)) != PP_OK || (st = dalloc(ctx, &s->n_t, R)) != PP_OK ||
+      (st = dalloc(ctx, &s->s1, R)) != PP_OK || (st = dalloc(ctx, &s->s2, R)) != PP_OK)
+    return st;
+  const std::vector<float> nph = source_photons(*b);
+  float *d_src_nph = nullptr;
+  int32_t *d_ev = nullptr;
+  if ((st = dalloc(ctx, &d_src_nph, n_src)) != PP_OK) return st;
+  if ((st = dalloc(ctx, &d_ev, static_cast<int64_t>(ev.size()))) != PP_OK) return st;
+  PP_HIP(ctx, hipMemcpy(d_src_nph, nph.data(), sizeof(float) * nph.size(), hipMemcpyHostToDevice));
+  PP_HIP(ctx, hipMemcpy(d_ev, ev.data(), sizeof(int32_t) * ev.size(), hipMemcpyHostToDevice));
+  sur::FeatureArgs f = feature_args(s, *b, d_src_nph);
+  f.first_pair = 0;
+  f.n_pairs = s->P;
+  f.X = s->X;
+  f.XT = s->XT;
+  f.ldxt = R;
+  f.mu_base = s->mu_base;
+  f.nph = s->nph;
+  PP_HIP(ctx, sur::launch_features(f, nullptr));
+  float *lab[4] = {s->k, s->n_t, s->s1, s->s2};
+  for (float *p : lab) PP_HIP(ctx, sur::launch_zero_f32(p, R, nullptr));
+  const float time_per_m = static_cast<float>(static_cast<double>(ctx->ice.n_group) / 0.299792458);
+  PP_HIP(ctx, sur::launch_labels(b->d_hits, b->d_counters + pp::kHitCount, b->hit_cap, d_ev,
+                                 static_cast<uint32_t>(ev.size()), b->d_src, s->doms_by_id, s->n_doms, ctx->radius,
+                                 time_per_m, s->k, s->n_t, s->s1, s->s2, nullptr));
+  PP_HIP(ctx, hipDeviceSynchronize());
+  dfree(d_src_nph);
+  dfree(d_ev);
+  return PP_OK;
+}
+
+pp_status pp_sur_training_size(const pp_surrogate *s, uint64_t *n) {
+  if (!s || !n) return PP_EINVAL;
+  *n = static_cast<uint64_t>(s->P);
+  return PP_OK;
+}
+
+pp_status pp_sur_get_training_rows(pp_surrogate *s, uint64_t first, uint64_t count, float *features, float *mu_base,
+                                   float *k, float *n_t, float *s1, float *s2) {
+  if (!s) return PP_EINVAL;
+  pp_context *ctx = s->ctx;
+  if (first + count > static_cast<uint64_t>(s->P)) return fail(ctx, PP_EINVAL, "rows out of range");
+  PP_HIP(ctx, hipSetDevice(ctx->device));
+  PP_HIP(ctx, hipDeviceSynchronize());
+  if (features) {
+    std::vector<uint16_t> xb(count * sur::kInPad);
+    PP_HIP(ctx, hipMemcpy(xb.data(), s->X + first * sur::kInPad, sizeof(uint16_t) * xb.size(), hipMemcpyDeviceToHost));
+    for (uint64_t r = 0; r < count; ++r)
+      for (int q = 0; q < sur::kInReal; ++q) {
+        const uint32_t u = static_cast<uint32_t>(xb[r * sur::kInPad + q]) << 16;
+        std::memcpy(&features[r * sur::kInReal + q], &u, 4);
+      }
+  }
+  float *dst[5] = {mu_base, k, n_t, s1, s2};
+  float *src[5] = {s->mu_base, s->k, s->n_t, s->s1, s->s2};
+  for (int i = 0; i < 5; ++i)
+    if (dst[i] && count) PP_HIP(ctx, hipMemcpy(dst[i], src[i] + first, sizeof(float) * count, hipMemcpyDeviceToHost));
+  return PP_OK;
+}
+
+pp_status pp_sur_loss_grad(pp_surrogate *s, uint64_t first, uint64_t count, double *loss, float *grad) {
+  if (!s) return PP_EINVAL;
+  pp_status st = need_device(s->ctx);
+  if (st != PP_OK) return st;
+  if ((st = forward_backward(s, static_cast<int64_t>(first), static_cast<int64_t>(count), nullptr)) != PP_OK) return st;
+  PP_HIP(s->ctx, hipDeviceSynchronize());
+  if (loss) {
+    double l = 0;
+    PP_HIP(s->ctx, hipMemcpy(&l, s->d_loss, sizeof(double), hipMemcpyDeviceToHost));
+    *loss = l / static_cast<double>(count);
+  }
+  if (grad) PP_HIP(s->ctx, hipMemcpy(grad, s->grad, sizeof(float) * sur::param_count(), hipMemcpyDeviceToHost));
+  return PP_OK;
+}
+
+pp_status pp_sur_train_step(pp_surrogate *s, uint64_t first, uint64_t count, float lr, double *loss) {
+  if (!s) return PP_EINVAL;
+  pp_status st = need_device(s->ctx);
+  if (st != PP_OK) return st;
+  if ((st = forward_backward(s, static_cast<int64_t>(first), static_cast<int64_t>(count), nullptr)) != PP_OK) return st;
+  if ((st = adam_step(s, lr, nullptr)) != PP_OK) return st;
+  PP_HIP(s->ctx, hipDeviceSynchronize());
+  if (loss) {
+    double l = 0;
+    PP_HIP(s->ctx, hipMemcpy(&l, s->d_loss, sizeof(double), hipMemcpyDeviceToHost));
+    *loss = l / static_cast<double>(count);
+  }
+  return PP_OK;
+}
+
+pp_status pp_sur_train(pp_surrogate *s, uint32_t epochs, uint32_t batch_size, float lr, void *hip_stream,
+                       float *epoch_loss) {
+  if (!s) return PP_EINVAL;
+  pp_context *ctx = s->ctx;
+  pp_status st = need_device(ctx);
+  if (st != PP_OK) return st;
+  if (batch_size == 0 || batch_size % 64 != 0) return fail(ctx, PP_EINVAL, "batch_size must be a positive multiple of 64");
+  if (s->P == 0) return fail(ctx, PP_ESTATE, "no training set");
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  double *d_epoch = nullptr;
+  if ((st = dalloc(ctx, &d_epoch, 1)) != PP_OK) return st;
+  s->epoch_loss = d_epoch;
+  for (uint32_t e = 0; e < epochs; ++e) {
+    PP_HIP(ctx, sur::launch_zero_f64(d_epoch, 1, stream));
+    for (int64_t first = 0; first < s->P; first += batch_size) {
+      const int64_t count = std::min<int64_t>(batch_size, s->P - first);
+      if ((st = forward_backward(s, first, count, stream)) != PP_OK) break;
+      if ((st = adam_step(s, lr, stream)) != PP_OK) break;
+    }
+    if (st != PP_OK) break;
+    if (epoch_loss) {
+      double l = 0;
+      PP_HIP(ctx, hipMemcpyAsync(&l, d_epoch, sizeof(double), hipMemcpyDeviceToHost, stream));
+      PP_HIP(ctx, hipStreamSynchronize(stream));
+      epoch_loss[e] = static_cast<float>(l / static_cast<double>(s->P));
+    }
+  }
+  s->epoch_loss = nullptr;
+  PP_HIP(ctx, hipStreamSynchronize(stream));
+  dfree(d_epoch);
+  return st;
+}
+
+pp_status pp_sur_expected_hits(pp_surrogate *s, uint64_t batch, double *dev_dom_sums, void *hip_stream) {
+  if (!s || !dev_dom_sums) return PP_EINVAL;
+  pp_context *ctx = s->ctx;
+  pp_status st = need_device(ctx);
+  if (st != PP_OK) return st;
+  Batch *b;
+  if ((st = find_batch(ctx, batch, &b)) != PP_OK) return st;
+  if ((st = check_cherenkov(ctx, *b)) != PP_OK) return st;
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  PP_HIP(ctx, sur::launch_zero_f64(dev_dom_sums, s->n_doms, stream));
+  return infer(s, *b, stream, [&](const float *mu, int64_t, int64_t ns) -> pp_status {
+    PP_HIP(ctx, sur::launch_dom_sums(mu, static_cast<int>(ns), s->n_doms, dev_dom_sums, stream));
+    return PP_OK;
+  });
+}
+
+pp_status pp_sur_predict_pairs(pp_surrogate *s, uint64_t batch, float *out, uint64_t n) {
+  if (!s || !out) return PP_EINVAL;
+  pp_context *ctx = s->ctx;
+  pp_status st = need_device(ctx);
+  if (st != PP_OK) return st;
+  Batch *b;
+  if ((st = find_batch(ctx, batch, &b)) != PP_OK) return st;
+  if ((st = check_cherenkov(ctx, *b)) != PP_OK) return st;
+  if (n != b->src.size() * static_cast<uint64_t>(s->n_doms)) return fail(ctx, PP_EINVAL, "output size mismatch");
+  return infer(s, *b, nullptr, [&](const float *mu, int64_t s0, int64_t ns) -> pp_status {
+    PP_HIP(ctx, hipMemcpy(out + s0 * s->n_doms, mu, sizeof(float) * ns * s->n_doms, hipMemcpyDeviceToHost));
+    return PP_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// Internal interface between the surrogate host code (sur_api.cpp) and its
+// gfx950 kernels (sur_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pp_device.h"
+
+namespace sur {
+
+constexpr int kInReal = 16, kInPad = 64, kHidden = 256, kOutPad = 64, kOutReal = 3;
+constexpr int kLayers = 5;
+constexpr int kTile = 64;            // GEMM workgroup tile (rows and columns)
+constexpr float kTau0Ns = 50.0f;     // gamma scale unit of the delay model
+constexpr float kTimeWeight = 0.1f;  // weight of the delay term in the loss
+
+// Layer l maps in_dim(l) -> out_dim(l); weights are stored out x in.
+__host__ __device__ constexpr int in_dim(int l) { return l == 0 ? kInPad : kHidden; }
+__host__ __device__ constexpr int out_dim(int l) { return l == kLayers - 1 ? kOutPad : kHidden; }
+
+// Flat parameter layout (f32): for each layer, W (out x in) then b (out).
+__host__ __device__ constexpr int64_t w_offset(int l) {
+  int64_t o = 0;
+  for (int j = 0; j < l; ++j) o += (int64_t)out_dim(j) * in_dim(j) + out_dim(j);
+  return o;
+}
+__host__ __device__ constexpr int64_t b_offset(int l) { return w_offset(l) + (int64_t)out_dim(l) * in_dim(l); }
+__host__ __device__ constexpr int64_t param_count() { return w_offset(kLayers); }
+// bf16 weight copies: W (out x in) and W^T (in x out), layer after layer.
+__host__ __device__ constexpr int64_t wb_offset(int l) {
+  int64_t o = 0;
+  for (int j = 0; j < l; ++j) o += (int64_t)out_dim(j) * in_dim(j);
+  return o;
+}
+__host__ __device__ constexpr int64_t wb_count() { return wb_offset(kLayers); }
+
+enum Epilogue {
+  kEpiGelu = 0,     // z = acc + bias; store z (f32) unless null, gelu(z) as bf16 and its transpose unless null
+  kEpiGeluBwd = 1,  // dz = acc * gelu'(z_saved); store bf16 and its transpose
+  kEpiAccum = 2,    // out (f32) += acc  (split-K partial sums, atomically)
+  kEpiMu = 3,       // column 0 only: mu = n_photons(row) * mu_base(row) * exp(acc + bias)
+  kEpiLinear = 4,   // out (f32, ld N) = acc + bias
+};
+
+struct GemmArgs {
+  // C[M x N] = A[M x K] * B[N x K]^T ; A, B bf16 with K contiguous
+  const uint16_t *A;
+  int64_t lda;
+  const uint16_t *B;
+  int64_t ldb;
+  int M, N, K;
+  int k_chunk;  // K range per grid.z slice
+  const float *bias;
+  float *Z;          // f32 M x N (ld N)
+  uint16_t *H;       // bf16 M x N (ld N)
+  uint16_t *HT;      // bf16 N x M (ld ldt)
+  int64_t ldt;
+  const float *Zin;  // saved pre-activation for kEpiGeluBwd (ld N)
+  float *out;        // kEpiAccum: f32 M x N (ld N); kEpiMu: f32 per row
+  const float *row_nph;    // kEpiMu: photons of the row's source
+  const float *row_mubase; // kEpiMu: baseline per row
+};
+
+struct FeatureArgs {
+  const pp::DevSource *sources;
+  const float *src_nph;       // photons per source
+  int n_sources_set;          // sources in the pair set (rows = source-major pairs)
+  const float4 *doms;         // module centres, module-id order
+  int n_doms;
+  const pp::DevLayer *layers;
+  int n_layers;
+  float z_lo, inv_dz, radius;
+  int64_t first_pair, n_pairs;  // pairs [first, first + n) of the set
+  uint16_t *X;    // bf16 n x 64 (rows padded to a multiple of 64 with zeros)
+  uint16_t *XT;   // bf16 64 x ldxt (column = pair - first), may be null
+  int64_t ldxt;
+  float *mu_base; // per pair, may be null
+  float *nph;     // photons of the pair's source, may be null
+  float *r_out;   // distance per pair, may be null
+};
+
+struct LossArgs {
+  const float *Y;        // f32 M x 64 (ld 64)
+  const float *mu_base, *nph, *k, *n_t, *s1, *s2;  // per row
+  int M_real, M_pad;
+  float inv_norm;        // 1 / number of pairs averaged over
+  uint16_t *dY;          // bf16 M_pad x 64
+  uint16_t *dYT;         // bf16 64 x M_pad
+  double *loss_sum;
+  double *loss_epoch;    // also accumulated into, if not null
+};
+
+hipError_t launch_gemm(int epi, const GemmArgs &g, int splits, hipStream_t s);
+hipError_t launch_features(const FeatureArgs &f, hipStream_t s);
+hipError_t launch_loss(const LossArgs &l, hipStream_t s);
+hipError_t launch_rowsum(const uint16_t *XT, int64_t ld, int rows, int cols, float *out, hipStream_t s);
+hipError_t launch_adam(float *theta, const float *grad, float *m, float *v, int64_t n, float lr,
+                       float c1, float c2, hipStream_t s);
+hipError_t launch_pack_weights(const float *theta, uint16_t *w_bf16, uint16_t *wt_bf16, hipStream_t s);
+hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s);
+hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
+hipError_t launch_labels(const pp::DevHit *hits, const unsigned long long *hit_count, uint64_t hit_cap,
+                         const int32_t *event_to_source, uint32_t n_events, const pp::DevSource *sources,
+                         const float4 *doms, int n_doms, float radius, float time_per_m,
+                         float *k, float *n_t, float *s1, float *s2, hipStream_t s);
+hipError_t launch_dom_sums(const float *mu, int n_src, int n_doms, double *dom_sums, hipStream_t s);
+
+}  // namespace sur

@@ -1,0 +1,399 @@
+// gfx950 kernels of the learned surrogate: a five-layer GELU perceptron in
+// BF16 with FP32 accumulation on the matrix cores, its backward pass, loss,
+// Adam, and the features / labels / reductions around it.
+//
+// GEMM: C[M x N] = A[M x K] * B[N x K]^T with both operands K-contiguous
+// bf16. A workgroup of four wavefronts computes a 64 x 64 tile; each
+// wavefront a 32 x 32 quarter as 2 x 2 v_mfma_f32_16x16x32_bf16 tiles. The
+// weights (at most 128 KB per layer) stay in L2, so operand fragments are
+// loaded straight into VGPRs, 16 bytes per lane per fragment. Epilogues fuse
+// the bias, GELU and its derivative, the transposed copies the next GEMM
+// needs, split-K accumulation, and the expected-hit output.
+
+#include "sur_device.h"
+
+namespace sur {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t *p) {
+  const uint4 v = *reinterpret_cast<const uint4 *>(p);
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+// GELU(z) = z * Phi(z) with the exact normal CDF.
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// Digamma for x > 0: recurrence psi(x) = psi(x + 1) - 1/x up to x >= 6, then
+// the asymptotic expansion ln x - 1/(2x) - sum B_2n / (2n x^2n)
+// (Abramowitz & Stegun 6.3.18).
+__device__ __forceinline__ float digamma(float x) {
+  float r = 0.0f;
+  while (x < 6.0f) {
+    r -= 1.0f / x;
+    x += 1.0f;
+  }
+  const float f = 1.0f / (x * x);
+  const float t = f * (1.0f / 12 - f * (1.0f / 120 - f * (1.0f / 252 - f * (1.0f / 240 - f * (1.0f / 132)))));
+  return r + logf(x) - 0.5f / x - t;
+}
+
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row0 = blockIdx.y * kTile + (wave >> 1) * 32;
+  const int col0 = blockIdx.x * kTile + (wave & 1) * 32;
+  const int kbeg = blockIdx.z * g.k_chunk;
+  const int kend = min(g.K, kbeg + g.k_chunk);
+  const int lr = lane & 15, lk = (lane >> 4) * 8;
+  f32x4 acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+  const uint16_t *a0 = g.A + (int64_t)(row0 + lr) * g.lda + lk;
+  const uint16_t *a1 = a0 + 16 * g.lda;
+  const uint16_t *b0 = g.B + (int64_t)(col0 + lr) * g.ldb + lk;
+  const uint16_t *b1 = b0 + 16 * g.ldb;
+  for (int k = kbeg; k < kend; k += 32) {
+    const bf16x8 va0 = load8(a0 + k), va1 = load8(a1 + k);
+    const bf16x8 vb0 = load8(b0 + k), vb1 = load8(b1 + k);
+    acc00 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va0, vb0, acc00, 0, 0, 0);
+    acc01 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va0, vb1, acc01, 0, 0, 0);
+    acc10 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va1, vb0, acc10, 0, 0, 0);
+    acc11 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va1, vb1, acc11, 0, 0, 0);
+  }
+  // Output layout of a 16 x 16 tile: lane holds rows 4 (lane / 16) + r,
+  // r = 0..3, of column lane % 16.
+  const f32x4 accs[4] = {acc00, acc01, acc10, acc11};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int i = t >> 1, j = t & 1;
+    const int col = col0 + j * 16 + lr;
+    const int rbase = row0 + i * 16 + (lane >> 4) * 4;
+    const f32x4 v = accs[t];
+    if (EPI == kEpiGelu) {
+      const float b = g.bias[col];
+      uint16_t h[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float z = v[r] + b;
+        const int64_t idx = (int64_t)(rbase + r) * g.N + col;
+        if (g.Z) g.Z[idx] = z;
+        h[r] = f2bf(gelu(z));
+        g.H[idx] = h[r];
+      }
+      if (g.HT) {
+        const uint2 packed = make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
+        *reinterpret_cast<uint2 *>(g.HT + (int64_t)col * g.ldt + rbase) = packed;
+      }
+    } else if (EPI == kEpiGeluBwd) {
+      uint16_t h[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t idx = (int64_t)(rbase + r) * g.N + col;
+        h[r] = f2bf(v[r] * gelu_grad(g.Zin[idx]));
+        g.H[idx] = h[r];
+      }
+      const uint2 packed = make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
+      *reinterpret_cast<uint2 *>(g.HT + (int64_t)col * g.ldt + rbase) = packed;
+    } else if (EPI == kEpiAccum) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) atomicAdd(&g.out[(int64_t)(rbase + r) * g.N + col], v[r]);
+    } else if (EPI == kEpiLinear) {
+      const float b = g.bias[col];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) g.out[(int64_t)(rbase + r) * g.N + col] = v[r] + b;
+    } else {  // kEpiMu
+      if (col == 0) {
+        const float b = g.bias[0];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rbase + r;
+          g.out[row] = g.row_nph[row] * g.row_mubase[row] * expf(v[r] + b);
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ int layer_of(float z, float z_lo, float inv_dz, int n_layers) {
+  const float f = floorf((z - z_lo) * inv_dz);
+  return f >= 0.0f ? (f >= (float)(n_layers - 1) ? n_layers - 1 : (int)f) : 0;
+}
+
+// Features of (source, module) pairs, source-major: pair p is source
+// p / n_doms and module p % n_doms. Rows past n_pairs (padding) are zero.
+__global__ void k_features(const FeatureArgs f, int64_t n_rows) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n_rows) return;
+  float x[kInReal];
+  for (int q = 0; q < kInReal; ++q) x[q] = 0.0f;
+  float mu_base = 0.0f, nph = 0.0f, R = 0.0f;
+  if (t < f.n_pairs) {
+    const int64_t p = f.first_pair + t;
+    const int i = (int)(p / f.n_doms), j = (int)(p % f.n_doms);
+    const pp::DevSource &S = f.sources[i];
+    const float4 m = f.doms[j];
+    const float half = 0.5f * S.dir_len.w;
+    const float cx = S.pos_t0.x + half * S.dir_len.x, cy = S.pos_t0.y + half * S.dir_len.y;
+    const float cz = S.pos_t0.z + half * S.dir_len.z;
+    const float dx = m.x - cx, dy = m.y - cy, dz = m.z - cz;
+    R = fmaxf(sqrtf(dx * dx + dy * dy + dz * dz), 0.5f);
+    const float ux = dx / R, uy = dy / R, uz = dz / R;
+    const float cos_eta = ux * S.dir_len.x + uy * S.dir_len.y + uz * S.dir_len.z;
+    const pp::DevLayer Ls = f.layers[layer_of(cz, f.z_lo, f.inv_dz, f.n_layers)];
+    const pp::DevLayer Ld = f.layers[layer_of(m.z, f.z_lo, f.inv_dz, f.n_layers)];
+    x[0] = ux;
+    x[1] = uy;
+    x[2] = uz;
+    x[3] = R / 100.0f;
+    x[4] = logf(R / 10.0f) / 3.0f;
+    x[5] = cos_eta;
+    x[6] = cos_eta - 0.75470958022277199f;  // cos 41 deg
+    x[7] = S.dir_len.x;
+    x[8] = S.dir_len.y;
+    x[9] = S.dir_len.z;
+    x[10] = cz / 500.0f;
+    x[11] = m.z / 500.0f;
+    x[12] = 100.0f * Ls.coef.x;
+    x[13] = 10.0f * Ls.coef.y;
+    x[14] = 100.0f * Ld.coef.x;
+    x[15] = 10.0f * Ld.coef.y;
+    // diffusion baseline with the two layers' mean absorption and
+    // effective scattering lengths (lambda_e = (1/b) / (1 - g))
+    const float lam_a = 0.5f * (Ls.coef.z + Ld.coef.z);
+    const float lam_e = 0.5f * (Ls.coef.w / Ls.hg.x + Ld.coef.w / Ld.hg.x);
+    const float D = lam_e / 3.0f;
+    const float dl = sqrtf(D * lam_a);
+    mu_base = f.radius * f.radius * expf(-R / dl) / (4.0f * D * R);
+    nph = f.src_nph[i];
+  }
+  uint16_t *row = f.X + t * kInPad;
+  for (int q = 0; q < kInPad; ++q) row[q] = q < kInReal ? f2bf(x[q]) : 0;
+  if (f.XT)
+    for (int q = 0; q < kInPad; ++q) f.XT[(int64_t)q * f.ldxt + t] = q < kInReal ? f2bf(x[q]) : 0;
+  if (f.mu_base) f.mu_base[t] = mu_base;
+  if (f.nph) f.nph[t] = nph;
+  if (f.r_out) f.r_out[t] = R;
+}
+
+// Poisson + gamma negative log-likelihood per row and its gradient with
+// respect to the three outputs (log mu / mu_base, log kappa, log theta/tau0).
+__global__ void __launch_bounds__(256) k_loss(const LossArgs l) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  double part = 0.0;
+  if (m < l.M_pad) {
+    float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+    if (m < l.M_real) {
+      const float *y = l.Y + (int64_t)m * kOutPad;
+      const float y1 = fminf(fmaxf(y[1], -8.0f), 8.0f), y2 = fminf(fmaxf(y[2], -8.0f), 8.0f);
+      const float mu = l.nph[m] * l.mu_base[m] * expf(y[0]);
+      const float kappa = expf(y1), theta = kTau0Ns * expf(y2);
+      const float k = l.k[m], nt = l.n_t[m], s1 = l.s1[m], s2 = l.s2[m];
+      const float log_mu = logf(mu);
+      const float pois = mu - (k > 0.0f ? k * log_mu : 0.0f);
+      const float gam = nt > 0.0f ? nt * (lgammaf(kappa) + kappa * logf(theta)) - (kappa - 1.0f) * s2 + s1 / theta
+                                  : 0.0f;
+      part = (double)pois + (double)kTimeWeight * gam;
+      g0 = (mu - k) * l.inv_norm;
+      if (nt > 0.0f) {
+        g1 = kTimeWeight * kappa * (nt * (digamma(kappa) + logf(theta)) - s2) * l.inv_norm;
+        g2 = kTimeWeight * (nt * kappa - s1 / theta) * l.inv_norm;
+        if (y[1] != y1) g1 = 0.0f;  // clamped: no gradient through the clamp
+        if (y[2] != y2) g2 = 0.0f;
+      }
+    }
+    uint16_t *row = l.dY + (int64_t)m * kOutPad;
+    row[0] = f2bf(g0);
+    row[1] = f2bf(g1);
+    row[2] = f2bf(g2);
+    for (int q = kOutReal; q < kOutPad; ++q) row[q] = 0;
+    l.dYT[m] = f2bf(g0);
+    l.dYT[(int64_t)l.M_pad + m] = f2bf(g1);
+    l.dYT[2 * (int64_t)l.M_pad + m] = f2bf(g2);
+    for (int q = kOutReal; q < kOutPad; ++q) l.dYT[(int64_t)q * l.M_pad + m] = 0;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(l.loss_sum, red[0]);
+    if (l.loss_epoch) atomicAdd(l.loss_epoch, red[0]);
+  }
+}
+
+// out[r] = sum over columns of the bf16 matrix row r (one workgroup per row).
+__global__ void __launch_bounds__(256) k_rowsum(const uint16_t *XT, int64_t ld, int cols, float *out) {
+  const uint16_t *row = XT + blockIdx.x * ld;
+  float s = 0.0f;
+  for (int c = threadIdx.x; c < cols; c += blockDim.x) s += __uint_as_float((uint32_t)row[c] << 16);
+  __shared__ float red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// Adam (Kingma & Ba) with bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t.
+__global__ void k_adam(float *theta, const float *grad, float *m, float *v, int64_t n, float lr, float c1,
+                       float c2) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float g = grad[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * g;
+    const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// bf16 copies of every weight matrix: W (out x in) and W^T (in x out).
+__global__ void k_pack_weights(const float *theta, uint16_t *wb, uint16_t *wt) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= wb_count()) return;
+  int l = 0;
+  while (l + 1 < kLayers && t >= wb_offset(l + 1)) ++l;
+  const int64_t e = t - wb_offset(l);
+  const int n_in = in_dim(l), n_out = out_dim(l);
+  const int o = (int)(e / n_in), i = (int)(e % n_in);
+  const uint16_t h = f2bf(theta[w_offset(l) + e]);
+  wb[t] = h;
+  wt[wb_offset(l) + (int64_t)i * n_out + o] = h;
+}
+
+__global__ void k_zero_f32(float *p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0f;
+}
+
+__global__ void k_zero_f64(double *p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// Training labels from Monte Carlo hits, per (source, module) pair: hit
+// count k, and the count, sum and sum of logs of the delays
+// t - t0 - max(R - L/2 - r, 0) n_g / c (+ 0.01 ns), R the distance from
+// the segment centre to the module centre. The delay is non-negative: no
+// photon reaches the module surface sooner.
+__global__ void k_labels(const pp::DevHit *hits, const unsigned long long *hit_count, uint64_t cap,
+                         const int32_t *event_to_source, uint32_t n_events, const pp::DevSource *sources,
+                         const float4 *doms, int n_doms, float radius, float time_per_m, float *k, float *n_t,
+                         float *s1, float *s2) {
+  uint64_t n = *hit_count;
+  if (n > cap) n = cap;
+  for (uint64_t h = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; h < n; h += (uint64_t)gridDim.x * blockDim.x) {
+    const pp::DevHit hit = hits[h];
+    if (hit.event_id >= n_events || hit.dom_id >= (uint32_t)n_doms) continue;
+    const int i = event_to_source[hit.event_id];
+    if (i < 0) continue;
+    const pp::DevSource &S = sources[i];
+    const float4 m = doms[hit.dom_id];
+    const float half = 0.5f * S.dir_len.w;
+    const float dx = m.x - (S.pos_t0.x + half * S.dir_len.x), dy = m.y - (S.pos_t0.y + half * S.dir_len.y);
+    const float dz = m.z - (S.pos_t0.z + half * S.dir_len.z);
+    const float R = sqrtf(dx * dx + dy * dy + dz * dz);
+    const float delay = fmaxf(hit.time_ns - S.pos_t0.w - fmaxf(R - half - radius, 0.0f) * time_per_m, 0.0f) + 0.01f;
+    const int64_t pair = (int64_t)i * n_doms + hit.dom_id;
+    atomicAdd(&k[pair], 1.0f);
+    atomicAdd(&n_t[pair], 1.0f);
+    atomicAdd(&s1[pair], delay);
+    atomicAdd(&s2[pair], logf(delay));
+  }
+}
+
+// dom_sums[j] += sum_i mu[i * n_doms + j] (one thread per module).
+__global__ void k_dom_sums(const float *mu, int n_src, int n_doms, double *dom_sums) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_doms) return;
+  double s = 0.0;
+  for (int i = 0; i < n_src; ++i) s += (double)mu[(int64_t)i * n_doms + j];
+  dom_sums[j] += s;
+}
+
+int blocks_for(int64_t n, int threads) { return (int)((n + threads - 1) / threads); }
+
+}  // namespace
+
+hipError_t launch_gemm(int epi, const GemmArgs &g, int splits, hipStream_t s) {
+  const dim3 grid(g.N / kTile, g.M / kTile, splits);
+  switch (epi) {
+    case kEpiGelu: hipLaunchKernelGGL(k_gemm<kEpiGelu>, grid, dim3(256), 0, s, g); break;
+    case kEpiGeluBwd: hipLaunchKernelGGL(k_gemm<kEpiGeluBwd>, grid, dim3(256), 0, s, g); break;
+    case kEpiAccum: hipLaunchKernelGGL(k_gemm<kEpiAccum>, grid, dim3(256), 0, s, g); break;
+    case kEpiLinear: hipLaunchKernelGGL(k_gemm<kEpiLinear>, grid, dim3(256), 0, s, g); break;
+    default: hipLaunchKernelGGL(k_gemm<kEpiMu>, grid, dim3(256), 0, s, g); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_features(const FeatureArgs &f, hipStream_t s) {
+  const int64_t rows = (f.n_pairs + kTile - 1) / kTile * kTile;
+  hipLaunchKernelGGL(k_features, dim3(blocks_for(rows, 256)), dim3(256), 0, s, f, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss(const LossArgs &l, hipStream_t s) {
+  hipLaunchKernelGGL(k_loss, dim3(blocks_for(l.M_pad, 256)), dim3(256), 0, s, l);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowsum(const uint16_t *XT, int64_t ld, int rows, int cols, float *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_rowsum, dim3(rows), dim3(256), 0, s, XT, ld, cols, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float *theta, const float *grad, float *m, float *v, int64_t n, float lr, float c1,
+                       float c2, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3(min(blocks_for(n, 256), 1024)), dim3(256), 0, s, theta, grad, m, v, n, lr, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_weights(const float *theta, uint16_t *w_bf16, uint16_t *wt_bf16, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_weights, dim3(blocks_for(wb_count(), 256)), dim3(256), 0, s, theta, w_bf16, wt_bf16);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_f32, dim3(min(blocks_for(n, 256), 4096)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_f64, dim3(min(blocks_for(n, 256), 4096)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_labels(const pp::DevHit *hits, const unsigned long long *hit_count, uint64_t hit_cap,
+                         const int32_t *event_to_source, uint32_t n_events, const pp::DevSource *sources,
+                         const float4 *doms, int n_doms, float radius, float time_per_m, float *k, float *n_t,
+                         float *s1, float *s2, hipStream_t s) {
+  hipLaunchKernelGGL(k_labels, dim3(1024), dim3(256), 0, s, hits, hit_count, hit_cap, event_to_source, n_events,
+                     sources, doms, n_doms, radius, time_per_m, k, n_t, s1, s2);
+  return hipGetLastError();
+}
+
+hipError_t launch_dom_sums(const float *mu, int n_src, int n_doms, double *dom_sums, hipStream_t s) {
+  hipLaunchKernelGGL(k_dom_sums, dim3(blocks_for(n_doms, 256)), dim3(256), 0, s, mu, n_src, n_doms, dom_sums);
+  return hipGetLastError();
+}
+
+}  // namespace sur

@@ -84,6 +84,9 @@ SIGNATURES = {
     "pp_dom_counts": (C.c_int, [_vp, _u64, _vp, _vp]),
     "pp_fetch_records": (C.c_int, [_vp, _u64, _vp, _u64, _u64]),
     "pp_get_stats": (C.c_int, [_vp, _u64, C.POINTER(_Stats)]),
+    "pp_autotune": (C.c_int, [_vp, _u64, _vp, C.POINTER(_LaunchConfig)]),
+    "pp_graph_capture": (C.c_int, [_vp, _u64, _vp]),
+    "pp_graph_launch": (C.c_int, [_vp, _u64, _vp]),
 }
 
 
@@ -255,6 +258,19 @@ class Context:
 
     def _n_photons_hint(self, batch: int) -> int:
         return self.stats(batch)["photons"]
+
+    def autotune(self, batch: int, stream=None) -> dict:
+        """Times the batch under a set of launch configurations and keeps the
+        fastest; returns it."""
+        cfg = _LaunchConfig()
+        self._check(_lib.pp_autotune(self._h, batch, _stream_handle(stream), C.byref(cfg)))
+        return {k: getattr(cfg, k) for k, _ in _LaunchConfig._fields_}
+
+    def graph_capture(self, batch: int, stream):
+        self._check(_lib.pp_graph_capture(self._h, batch, _stream_handle(stream)))
+
+    def graph_launch(self, batch: int, stream=None):
+        self._check(_lib.pp_graph_launch(self._h, batch, _stream_handle(stream)))
 
     def stats(self, batch: int) -> dict:
         s = _Stats()

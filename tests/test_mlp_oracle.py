@@ -1,0 +1,154 @@
+"""Pins of the surrogate's FP64 oracle (oracle/mlp_oracle.py): every
+derivative is checked against central finite differences of the function it
+differentiates, Adam against its closed form for a constant gradient, and
+the features against their geometric meaning."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as M
+from paper_2405_05700_amd import workloads as W
+
+
+def test_gelu_grad_matches_finite_difference():
+    z = np.linspace(-6, 6, 2001)
+    h = 1e-6
+    fd = (M.gelu(z + h) - M.gelu(z - h)) / (2 * h)
+    assert np.allclose(M.gelu_grad(z), fd, atol=1e-8)
+    # limits: gelu(z) -> z for large z, -> 0 for very negative z; gelu(0) = 0
+    assert abs(M.gelu(np.array([8.0]))[0] - 8.0) < 1e-12 and abs(M.gelu(np.array([-8.0]))[0]) < 1e-12
+
+
+def random_labels(rng, P):
+    k = rng.poisson(0.7, P).astype(float)
+    n_t = k.copy()
+    s1 = np.where(n_t > 0, rng.gamma(2.0, 30.0, P) * n_t, 0.0)
+    s2 = np.where(n_t > 0, np.log(rng.gamma(2.0, 30.0, P)) * n_t, 0.0)
+    nph = rng.uniform(1e4, 1e5, P)
+    mub = np.exp(rng.uniform(-14, -8, P))
+    return nph, mub, k, n_t, s1, s2
+
+
+def test_loss_gradient_matches_finite_difference():
+    rng = np.random.default_rng(0)
+    P = 40
+    nph, mub, k, n_t, s1, s2 = random_labels(rng, P)
+    Y = rng.normal(0, 0.5, (P, M.OUT_PAD))
+    _, dY = M.loss_and_grad_out(Y, mub, nph, k, n_t, s1, s2)
+    h = 1e-6
+    for col in range(3):
+        for p in range(0, P, 7):
+            Yp, Ym = Y.copy(), Y.copy()
+            Yp[p, col] += h
+            Ym[p, col] -= h
+            fd = (M.loss_and_grad_out(Yp, mub, nph, k, n_t, s1, s2)[0] -
+                  M.loss_and_grad_out(Ym, mub, nph, k, n_t, s1, s2)[0]) / (2 * h)
+            assert abs(fd - dY[p, col]) <= 1e-5 * max(1.0, abs(fd)), (p, col, fd, dY[p, col])
+    assert (dY[:, 3:] == 0).all()
+
+
+def test_backward_matches_finite_difference():
+    """Chain-rule gradients of a small random network (real shapes) against
+    central differences of the loss on sampled parameters of every layer."""
+    rng = np.random.default_rng(1)
+    params = M.init_params(3)
+    for W_, b in params:  # non-zero biases so every path is exercised
+        b[:] = rng.normal(0, 0.1, b.shape)
+    params[-1][1][M.OUT_REAL:] = 0
+    P = 24
+    X = np.zeros((P, M.IN_PAD))
+    X[:, :M.IN_REAL] = rng.normal(0, 1, (P, M.IN_REAL))
+    labels = random_labels(rng, P)
+
+    def loss_of(ps):
+        Y, _ = M.forward(ps, X)
+        return M.loss_and_grad_out(Y, labels[1], labels[0], *labels[2:])[0]
+
+    Y, cache = M.forward(params, X)
+    _, dY = M.loss_and_grad_out(Y, labels[1], labels[0], *labels[2:])
+    grads = M.backward(params, cache, dY)
+    h = 1e-6
+    for li in range(len(params)):
+        W_, b = params[li]
+        n_out = M.OUT_REAL if li == len(params) - 1 else W_.shape[0]
+        n_in = M.IN_REAL if li == 0 else W_.shape[1]
+        for _ in range(6):
+            o, i = rng.integers(0, n_out), rng.integers(0, n_in)
+            old = W_[o, i]
+            W_[o, i] = old + h
+            lp = loss_of(params)
+            W_[o, i] = old - h
+            lm = loss_of(params)
+            W_[o, i] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - grads[li][0][o, i]) <= 1e-4 * max(1e-3, abs(fd)), (li, o, i)
+        o = rng.integers(0, n_out)
+        old = b[o]
+        b[o] = old + h
+        lp = loss_of(params)
+        b[o] = old - h
+        lm = loss_of(params)
+        b[o] = old
+        assert abs((lp - lm) / (2 * h) - grads[li][1][o]) <= 1e-4 * max(1e-3, abs((lp - lm) / (2 * h)))
+    # padded inputs and outputs receive no gradient
+    assert (grads[0][0][:, M.IN_REAL:] == 0).all()
+    assert (grads[-1][0][M.OUT_REAL:] == 0).all() and (grads[-1][1][M.OUT_REAL:] == 0).all()
+
+
+def test_adam_closed_form_for_constant_gradient():
+    """With a constant gradient g the bias-corrected moments are exactly g
+    and g^2, so every step moves by -lr g / (|g| + eps)."""
+    params = [[np.array([[1.0, -2.0]]), np.array([0.5])]]
+    g = [[np.array([[0.3, -4.0]]), np.array([1e-3])]]
+    opt = M.Adam(params, lr=0.01)
+    for t in range(1, 6):
+        before = [p.copy() for p in params[0]]
+        opt.step(params, g)
+        for j in range(2):
+            step = params[0][j] - before[j]
+            expect = -0.01 * g[0][j] / (np.abs(g[0][j]) + 1e-8)
+            assert np.allclose(step, expect, rtol=1e-9, atol=1e-15)
+
+
+def test_features_geometry():
+    w = W.full_detector(n_sources=3, photons_per_source=10, seed=4)
+    src = np.repeat(np.arange(3), len(w.doms))
+    dom = np.tile(np.arange(len(w.doms)), 3)
+    X, mub, R = M.pair_features(w, src, dom)
+    u = X[:, 0:3]
+    assert np.allclose(np.linalg.norm(u, axis=1), 1.0, atol=1e-12)
+    assert np.allclose(X[:, 3] * 100.0, R) and (R >= 0.5).all()
+    assert (np.abs(X[:, 5]) <= 1 + 1e-12).all()
+    assert np.allclose(X[:, 6], X[:, 5] - math.cos(math.radians(41.0)))
+    assert (X[:, M.IN_REAL:] == 0).all()
+    # module positions recovered from the source centre and the offset
+    s = w.sources
+    d = np.stack([s["dx"], s["dy"], s["dz"]], 1).astype(float)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    c = np.stack([s["x"], s["y"], s["z"]], 1).astype(float) + 5.0 * d
+    m = np.stack([w.doms["x"], w.doms["y"], w.doms["z"]], 1).astype(float)
+    rec = c[src] + R[:, None] * u
+    assert np.allclose(rec, m[dom], atol=1e-9)
+    # the baseline falls with distance at fixed optics and is positive
+    assert (mub > 0).all()
+
+
+def test_baseline_is_the_diffusion_estimate_in_homogeneous_ice():
+    """In one homogeneous layer the baseline reduces to
+    r^2 exp(-R/delta) / (4 D R), D = lambda_e/3, delta = sqrt(D lambda_a),
+    and matches the oracle Monte Carlo's module rate within a factor of 2 in
+    the diffusive range (an estimate, not an exact law)."""
+    from oracle import pyoracle
+    w = W.tiny_point_source(200_000, dom_radius_m=2.0)
+    src = W.cherenkov_segments(1, 200_000, seed=0, length_m=1e-3)
+    src["x"] = src["y"] = src["z"] = 0.0
+    src["cherenkov_deg"] = 90.0  # nearly isotropic in the vertical direction
+    wk = w.with_sources(src)
+    _, mub, R = M.pair_features(wk, np.zeros(60, int), np.arange(60))
+    D = 25.0 / 3
+    expect = 4.0 * np.exp(-R / math.sqrt(D * 100.0)) / (4 * D * R)
+    assert np.allclose(mub, expect, rtol=1e-9)
+    r = pyoracle.run(wk, records=False, dom_mode=1)
+    ratio = r.dom_counts.sum() / (200_000 * mub.sum())
+    assert 0.5 < ratio < 2.0, ratio
