@@ -47,7 +47,8 @@ typedef enum {
   PP_ENOMEM = -2,  /* device or host allocation failed */
   PP_EDEVICE = -3, /* HIP runtime error, or no device on this context */
   PP_ESTATE = -4,  /* call out of order (e.g. submit before loading ice) */
-  PP_ETRUNC = -5   /* output buffer smaller than the result; *n_total set */
+  PP_ETRUNC = -5,  /* output buffer smaller than the result; *n_total set */
+  PP_EBUDGET = -6  /* request larger than the device-memory budget */
 } pp_status;
 
 /* Ice model (Sec. 2: 10 m layers with their own scattering and absorption).

@@ -76,10 +76,15 @@ pp_status pp_sur_loss_grad(pp_surrogate *sur, uint64_t first, uint64_t count, do
 pp_status pp_sur_train_step(pp_surrogate *sur, uint64_t first, uint64_t count, float lr, double *loss);
 
 /* Trains for the given epochs over the whole training set in minibatches of
- * batch_size rows (a multiple of 64) on hip_stream; epoch_loss (may be
- * NULL) receives the mean loss of each epoch. */
-pp_status pp_sur_train(pp_surrogate *sur, uint32_t epochs, uint32_t batch_size, float lr, void *hip_stream,
-                       float *epoch_loss);
+ * batch_size rows (a multiple of 64) on hip_stream. Every epoch visits the
+ * rows in a fresh pseudo-random order (an affine permutation of the row
+ * index modulo the set size, multiplier coprime to it), so each minibatch
+ * mixes pairs of many sources. The Adam learning rate follows a cosine from
+ * lr at the first step to lr_final at the last step of this call (lr_final
+ * = lr: constant). epoch_loss (may be NULL) receives the mean loss of each
+ * epoch. */
+pp_status pp_sur_train(pp_surrogate *sur, uint32_t epochs, uint32_t batch_size, float lr, float lr_final,
+                       void *hip_stream, float *epoch_loss);
 
 /* Expected hits (photons of the source times the predicted probability
  * per photon) of every (source, module) pair of the context's batch,

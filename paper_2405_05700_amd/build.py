@@ -11,16 +11,16 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpp.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("pp_api.cpp", "pp_kernels.hip", "sur_api.cpp",
-                                            "sur_kernels.hip")]
+                                            "sur_kernels.hip", "srv_api.cpp")]
 HEADERS = [os.path.join(CSRC, f) for f in ("pp_device.h", "pp_internal.h", "sur_device.h")] + \
-          [os.path.join(ROOT, "include", f) for f in ("pp.h", "pp_surrogate.h")]
+          [os.path.join(ROOT, "include", f) for f in ("pp.h", "pp_surrogate.h", "pp_server.h")]
 ARCH = "gfx950"
 
 # Packed-FP32 instructions are disabled: hipcc -O3 would otherwise form
 # v_pk_* FP32 ops from scalar code.
 HIPCC_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-               "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result"]
+               "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result", "-pthread"]
 
 
 def build(verbose: bool = False) -> str:

@@ -293,7 +293,7 @@ pp_status prepare(pp_context *ctx, Batch &b, Prepared *out) {
   if (!b.d_counters)
     PP_HIP(ctx, hipMalloc(reinterpret_cast<void **>(&b.d_counters), sizeof(unsigned long long) * pp::kNumCounters));
   if (!b.d_hits) {
-    const uint64_t cap = c.hit_capacity ? c.hit_capacity : std::max<uint64_t>(65536, b.n_photons / 64);
+    const uint64_t cap = c.hit_capacity ? c.hit_capacity : default_hit_capacity(b.n_photons);
     st = alloc_hits(ctx, b, cap);
     if (st != PP_OK) return st;
   }
@@ -410,6 +410,72 @@ pp_status complete_hits(pp_context *ctx, Batch &b, uint64_t *n_total) {
                   cnt[pp::kHitCount], (unsigned long long)need);
   }
   *n_total = cnt[pp::kHitCount];
+  return PP_OK;
+}
+
+}  // namespace ppi
+
+namespace ppi {
+
+// Validates submitted sources and converts them to device records. Pure
+// (touches no context), so the server's client threads can call it.
+pp_status build_sources(const pp_source *src, uint32_t n, std::vector<pp::DevSource> *out, uint64_t *total_out,
+                        std::string *err) {
+  char buf[256];
+  auto bad = [&](const char *fmt, uint32_t i, uint32_t v = 0) {
+    std::snprintf(buf, sizeof buf, fmt, i, v);
+    *err = buf;
+    return PP_EINVAL;
+  };
+  out->assign(n, pp::DevSource{});
+  uint64_t total = 0;
+  std::vector<std::pair<std::pair<uint32_t, uint64_t>, uint64_t>> ranges;
+  for (uint32_t i = 0; i < n; ++i) {
+    const pp_source &s = src[i];
+    if (s.type != PP_SOURCE_POINT && s.type != PP_SOURCE_CHERENKOV)
+      return bad("source %u: unknown type %u", i, s.type);
+    if (!finite(s.x) || !finite(s.y) || !finite(s.z) || !finite(s.t0_ns))
+      return bad("source %u: non-finite position or time", i);
+    if (!finite(s.lambda_min_nm) || !finite(s.lambda_max_nm) || !(s.lambda_min_nm > 0) ||
+        s.lambda_min_nm > s.lambda_max_nm)
+      return bad("source %u: need 0 < lambda_min <= lambda_max", i);
+    if (s.first_photon_index + s.n_photons < s.first_photon_index)
+      return bad("source %u: photon index range overflows", i);
+    if (total + s.n_photons < total) return bad("source %u: photon count overflows", i);
+    pp::DevSource &d = (*out)[i];
+    double dx = 0, dy = 0, dz = 1, len = 0, om = 0;
+    if (s.type == PP_SOURCE_CHERENKOV) {
+      if (!finite(s.dx) || !finite(s.dy) || !finite(s.dz) || !finite(s.length_m) || !(s.length_m >= 0) ||
+          !finite(s.cherenkov_deg) || !(s.cherenkov_deg > 0 && s.cherenkov_deg < 180))
+        return bad("source %u: bad direction, length or Cherenkov angle", i);
+      const double nrm = std::sqrt(static_cast<double>(s.dx) * s.dx + static_cast<double>(s.dy) * s.dy +
+                                   static_cast<double>(s.dz) * s.dz);
+      if (!(std::fabs(nrm - 1.0) <= 1e-3)) return bad("source %u: |direction| not within 1e-3 of 1", i);
+      dx = s.dx / nrm, dy = s.dy / nrm, dz = s.dz / nrm;
+      len = s.length_m;
+      const double half = 0.5 * s.cherenkov_deg * M_PI / 180.0;
+      om = 2.0 * std::sin(half) * std::sin(half);  // 1 - cos(angle) without cancellation
+    }
+    d.pos_t0 = make_float4(s.x, s.y, s.z, s.t0_ns);
+    d.dir_len = make_float4(static_cast<float>(dx), static_cast<float>(dy), static_cast<float>(dz),
+                            static_cast<float>(len));
+    const double inv_min = 1.0 / s.lambda_min_nm, inv_max = 1.0 / s.lambda_max_nm;
+    const bool fixed = s.lambda_min_nm == s.lambda_max_nm;
+    d.emit = make_float4(static_cast<float>(om), fixed ? s.lambda_min_nm : 0.0f,
+                         static_cast<float>(inv_min), fixed ? 0.0f : static_cast<float>(inv_min - inv_max));
+    d.ids = make_uint4(s.type, s.event_id, s.particle_id, 0u);
+    d.first_index = s.first_photon_index;
+    d.seq_base = total;
+    total += s.n_photons;
+    if (s.n_photons > 0) ranges.push_back({{s.event_id, s.first_photon_index}, s.n_photons});
+  }
+  std::sort(ranges.begin(), ranges.end());
+  for (size_t i = 1; i < ranges.size(); ++i) {
+    const auto &p = ranges[i - 1], &q = ranges[i];
+    if (p.first.first == q.first.first && q.first.second < p.first.second + p.second)
+      return bad("overlapping photon-index ranges in event %u", q.first.first);
+  }
+  *total_out = total;
   return PP_OK;
 }
 
@@ -605,54 +671,9 @@ pp_status pp_submit(pp_context *ctx, const pp_source *src, uint32_t n, uint64_t 
   if (!ctx || !batch_out || (n > 0 && !src)) return ctx ? fail(ctx, PP_EINVAL, "null argument") : PP_EINVAL;
   if (!ctx->ice_loaded || !ctx->geo_loaded) return fail(ctx, PP_ESTATE, "load ice and geometry before submitting");
   Batch b;
-  b.src.resize(n);
   uint64_t total = 0;
-  std::vector<std::pair<std::pair<uint32_t, uint64_t>, uint64_t>> ranges;
-  for (uint32_t i = 0; i < n; ++i) {
-    const pp_source &s = src[i];
-    if (s.type != PP_SOURCE_POINT && s.type != PP_SOURCE_CHERENKOV)
-      return fail(ctx, PP_EINVAL, "source %u: unknown type %u", i, s.type);
-    if (!finite(s.x) || !finite(s.y) || !finite(s.z) || !finite(s.t0_ns))
-      return fail(ctx, PP_EINVAL, "source %u: non-finite position or time", i);
-    if (!finite(s.lambda_min_nm) || !finite(s.lambda_max_nm) || !(s.lambda_min_nm > 0) ||
-        s.lambda_min_nm > s.lambda_max_nm)
-      return fail(ctx, PP_EINVAL, "source %u: need 0 < lambda_min <= lambda_max", i);
-    if (s.first_photon_index + s.n_photons < s.first_photon_index)
-      return fail(ctx, PP_EINVAL, "source %u: photon index range overflows", i);
-    if (total + s.n_photons < total) return fail(ctx, PP_EINVAL, "photon count overflows");
-    pp::DevSource &d = b.src[i];
-    double dx = 0, dy = 0, dz = 1, len = 0, om = 0;
-    if (s.type == PP_SOURCE_CHERENKOV) {
-      if (!finite(s.dx) || !finite(s.dy) || !finite(s.dz) || !finite(s.length_m) || !(s.length_m >= 0) ||
-          !finite(s.cherenkov_deg) || !(s.cherenkov_deg > 0 && s.cherenkov_deg < 180))
-        return fail(ctx, PP_EINVAL, "source %u: bad direction, length or Cherenkov angle", i);
-      const double nrm = std::sqrt(static_cast<double>(s.dx) * s.dx + static_cast<double>(s.dy) * s.dy +
-                                   static_cast<double>(s.dz) * s.dz);
-      if (!(std::fabs(nrm - 1.0) <= 1e-3)) return fail(ctx, PP_EINVAL, "source %u: |direction| not within 1e-3 of 1", i);
-      dx = s.dx / nrm, dy = s.dy / nrm, dz = s.dz / nrm;
-      len = s.length_m;
-      const double half = 0.5 * s.cherenkov_deg * M_PI / 180.0;
-      om = 2.0 * std::sin(half) * std::sin(half);  // 1 - cos(angle) without cancellation
-    }
-    d.pos_t0 = make_float4(s.x, s.y, s.z, s.t0_ns);
-    d.dir_len = make_float4(static_cast<float>(dx), static_cast<float>(dy), static_cast<float>(dz),
-                            static_cast<float>(len));
-    const double inv_min = 1.0 / s.lambda_min_nm, inv_max = 1.0 / s.lambda_max_nm;
-    const bool fixed = s.lambda_min_nm == s.lambda_max_nm;
-    d.emit = make_float4(static_cast<float>(om), fixed ? s.lambda_min_nm : 0.0f,
-                         static_cast<float>(inv_min), fixed ? 0.0f : static_cast<float>(inv_min - inv_max));
-    d.ids = make_uint4(s.type, s.event_id, s.particle_id, 0u);
-    d.first_index = s.first_photon_index;
-    d.seq_base = total;
-    total += s.n_photons;
-    if (s.n_photons > 0) ranges.push_back({{s.event_id, s.first_photon_index}, s.n_photons});
-  }
-  std::sort(ranges.begin(), ranges.end());
-  for (size_t i = 1; i < ranges.size(); ++i) {
-    const auto &p = ranges[i - 1], &q = ranges[i];
-    if (p.first.first == q.first.first && q.first.second < p.first.second + p.second)
-      return fail(ctx, PP_EINVAL, "overlapping photon-index ranges in event %u", q.first.first);
-  }
+  std::string err;
+  if (build_sources(src, n, &b.src, &total, &err) != PP_OK) return fail(ctx, PP_EINVAL, "%s", err.c_str());
   b.n_photons = total;
   if (ctx->device >= 0) {
     pp_status st = need_device(ctx);

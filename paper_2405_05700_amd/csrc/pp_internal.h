@@ -75,10 +75,23 @@ struct pp_context {
 
 
 namespace ppi {
+// Default device hit-buffer size (hits) for a batch of n photons.
+inline uint64_t default_hit_capacity(uint64_t n_photons) {
+  return n_photons / 64 > 65536 ? n_photons / 64 : 65536;
+}
+// Upper bound on the device bytes a batch allocates (records off): source
+// records, work-queue chunks of at least `chunk` ids, counters, hit buffer.
+inline uint64_t batch_device_bytes(uint64_t n_sources, uint64_t n_photons, uint64_t chunk,
+                                   uint64_t hit_capacity) {
+  return 80 * n_sources + 16 * (n_sources + n_photons / chunk + 1) + 8 * 16 + 32 * hit_capacity;
+}
 pp_status fail(pp_context *ctx, pp_status st, const char *fmt, ...);
 pp_status need_device(pp_context *ctx);
 pp_status find_batch(pp_context *ctx, uint64_t id, Batch **out);
 pp_status complete_hits(pp_context *ctx, Batch &b, uint64_t *n_total);
+pp_status build_sources(const pp_source *src, uint32_t n, std::vector<pp::DevSource> *out, uint64_t *total,
+                        std::string *err);
+bool finite(float v);
 }  // namespace ppi
 
 #define PP_HIP(ctx, expr)                                                                   \

@@ -36,6 +36,12 @@ struct pp_surrogate {
   uint16_t *dY = nullptr, *dYT = nullptr, *dZ[2] = {}, *dZT = nullptr;
   double *d_loss = nullptr;
   double *epoch_loss = nullptr;  // device accumulator while training, else null
+  // shuffled minibatch staging (capacity Gcap rows) and shuffle state
+  int64_t Gcap = 0;
+  uint16_t *gX = nullptr, *gXT = nullptr;
+  float *g_lab[6] = {};
+  uint64_t shuffle_seed = 0;
+  uint64_t epochs_done = 0;
   // inference buffers (capacity Icap rows)
   int64_t Icap = 0;
   uint16_t *iX = nullptr, *iH[2] = {};
@@ -112,19 +118,38 @@ pp_status ensure_work(pp_surrogate *s, int64_t M) {
   return PP_OK;
 }
 
-// Forward, loss and backward over training rows [first, first + count);
-// leaves the gradient in s->grad and the summed loss in s->d_loss.
-pp_status forward_backward(pp_surrogate *s, int64_t first, int64_t count, hipStream_t st) {
-  pp_context *ctx = s->ctx;
+// One minibatch as the network sees it: features row-major and transposed,
+// and the per-row labels.
+struct Rows {
+  const uint16_t *X, *XT;
+  int64_t ld_XT;
+  const float *mu_base, *nph, *k, *n_t, *s1, *s2;
+};
+
+// Training rows [first, first + count) in stored order.
+Rows slice_rows(const pp_surrogate *s, int64_t first) {
+  return Rows{s->X + first * sur::kInPad, s->XT + first, s->P_pad, s->mu_base + first, s->nph + first,
+              s->k + first, s->n_t + first, s->s1 + first, s->s2 + first};
+}
+
+pp_status check_rows(pp_surrogate *s, int64_t first, int64_t count) {
   if (first % 64 != 0 || count <= 0 || first + count > s->P)
-    return fail(ctx, PP_EINVAL, "rows [%lld, %lld) invalid: start must be a multiple of 64 within %lld pairs",
+    return fail(s->ctx, PP_EINVAL, "rows [%lld, %lld) invalid: start must be a multiple of 64 within %lld pairs",
                 (long long)first, (long long)(first + count), (long long)s->P);
+  return PP_OK;
+}
+
+// Forward, loss and backward over count rows of r (padded to a multiple of
+// 64 with zero rows); leaves the gradient in s->grad and the summed loss in
+// s->d_loss.
+pp_status forward_backward(pp_surrogate *s, const Rows &r, int64_t count, hipStream_t st) {
+  pp_context *ctx = s->ctx;
   const int M = static_cast<int>(round64(count));
   pp_status rc = ensure_work(s, M);
   if (rc != PP_OK) return rc;
   using namespace sur;
-  const uint16_t *X = s->X + first * kInPad;
-  const uint16_t *XT = s->XT + first;  // columns [first, first + M) of 64 x P_pad
+  const uint16_t *X = r.X;
+  const uint16_t *XT = r.XT;
   // forward
   const uint16_t *in = X;
   int64_t ld_in = kInPad;
@@ -142,12 +167,12 @@ pp_status forward_backward(pp_surrogate *s, int64_t first, int64_t count, hipStr
   PP_HIP(ctx, launch_zero_f64(s->d_loss, 1, st));
   LossArgs la{};
   la.Y = s->Y;
-  la.mu_base = s->mu_base + first;
-  la.nph = s->nph + first;
-  la.k = s->k + first;
-  la.n_t = s->n_t + first;
-  la.s1 = s->s1 + first;
-  la.s2 = s->s2 + first;
+  la.mu_base = r.mu_base;
+  la.nph = r.nph;
+  la.k = r.k;
+  la.n_t = r.n_t;
+  la.s1 = r.s1;
+  la.s2 = r.s2;
   la.M_real = static_cast<int>(count);
   la.M_pad = M;
   la.inv_norm = 1.0f / static_cast<float>(count);
@@ -172,7 +197,7 @@ pp_status forward_backward(pp_surrogate *s, int64_t first, int64_t count, hipStr
   for (int l = 3; l >= 0; --l) {
     // dW_l = dZ_l^T . H_{l-1} (X for l = 0), db_l = row sums of dZ_l^T
     const uint16_t *prevT = l > 0 ? s->HT[l - 1] : XT;
-    const int64_t ld_prevT = l > 0 ? M : s->P_pad;
+    const int64_t ld_prevT = l > 0 ? M : r.ld_XT;
     if ((rc = gemm(ctx, kEpiAccum, s->dZT, M, prevT, ld_prevT, kHidden, in_dim(l), M, splits, nullptr, nullptr,
                    nullptr, nullptr, 0, nullptr, s->grad + w_offset(l), nullptr, nullptr, st)) != PP_OK)
       return rc;
@@ -193,6 +218,60 @@ pp_status adam_step(pp_surrogate *s, float lr, hipStream_t st) {
   const float c2 = 1.0f - std::pow(0.999f, static_cast<float>(s->adam_t));
   PP_HIP(s->ctx, sur::launch_adam(s->theta, s->grad, s->adam_m, s->adam_v, sur::param_count(), lr, c1, c2, st));
   PP_HIP(s->ctx, sur::launch_pack_weights(s->theta, s->wb, s->wt, st));
+  return PP_OK;
+}
+
+pp_status ensure_gather(pp_surrogate *s, int64_t M) {
+  if (M <= s->Gcap) return PP_OK;
+  pp_status st;
+  if ((st = dalloc(s->ctx, &s->gX, M * sur::kInPad)) != PP_OK) return st;
+  if ((st = dalloc(s->ctx, &s->gXT, M * sur::kInPad)) != PP_OK) return st;
+  for (auto &p : s->g_lab)
+    if ((st = dalloc(s->ctx, &p, M)) != PP_OK) return st;
+  s->Gcap = M;
+  return PP_OK;
+}
+
+uint64_t gcd64(uint64_t a, uint64_t b) {
+  while (b) {
+    const uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// Gathers rows p(first .. first + count) of the epoch's permutation
+// p(r) = (mul r + add) mod P into the staging buffers.
+pp_status gather_rows(pp_surrogate *s, uint64_t mul, uint64_t add, int64_t first, int64_t count, Rows *out,
+                      hipStream_t st) {
+  const int64_t M = round64(count);
+  pp_status rc = ensure_gather(s, M);
+  if (rc != PP_OK) return rc;
+  sur::GatherArgs g{};
+  g.X = s->X;
+  g.mu_base = s->mu_base;
+  g.nph = s->nph;
+  g.k = s->k;
+  g.n_t = s->n_t;
+  g.s1 = s->s1;
+  g.s2 = s->s2;
+  g.P = static_cast<uint64_t>(s->P);
+  g.mul = mul;
+  g.add = add;
+  g.first = first;
+  g.count = static_cast<int>(count);
+  g.M = static_cast<int>(M);
+  g.gX = s->gX;
+  g.gXT = s->gXT;
+  g.g_mu_base = s->g_lab[0];
+  g.g_nph = s->g_lab[1];
+  g.g_k = s->g_lab[2];
+  g.g_n_t = s->g_lab[3];
+  g.g_s1 = s->g_lab[4];
+  g.g_s2 = s->g_lab[5];
+  PP_HIP(s->ctx, sur::launch_gather(g, st));
+  *out = Rows{s->gX, s->gXT, M, s->g_lab[0], s->g_lab[1], s->g_lab[2], s->g_lab[3], s->g_lab[4], s->g_lab[5]};
   return PP_OK;
 }
 
@@ -348,6 +427,7 @@ pp_status pp_sur_create(pp_context *ctx, uint64_t init_seed, pp_surrogate **out)
     return st;
   }
   (void)hipMemcpy(s->doms_by_id, by_id.data(), sizeof(float4) * by_id.size(), hipMemcpyHostToDevice);
+  s->shuffle_seed = init_seed ^ 0x5DEECE66Dull;
   const std::vector<float> th = init_params(init_seed);
   if ((st = upload_params(s, th.data())) != PP_OK) {
     pp_sur_destroy(s);
@@ -367,6 +447,8 @@ void pp_sur_destroy(pp_surrogate *s) {
   for (int l = 0; l < 4; ++l) dfree(s->Z[l]), dfree(s->H[l]), dfree(s->HT[l]);
   dfree(s->Y), dfree(s->dY), dfree(s->dYT), dfree(s->dZ[0]), dfree(s->dZ[1]), dfree(s->dZT), dfree(s->d_loss);
   dfree(s->iX), dfree(s->iH[0]), dfree(s->iH[1]), dfree(s->i_mu), dfree(s->i_mub), dfree(s->i_nph);
+  dfree(s->gX), dfree(s->gXT);
+  for (auto &p : s->g_lab) dfree(p);
   delete s;
 }
 
@@ -477,7 +559,10 @@ pp_status pp_sur_loss_grad(pp_surrogate *s, uint64_t first, uint64_t count, doub
   if (!s) return PP_EINVAL;
   pp_status st = need_device(s->ctx);
   if (st != PP_OK) return st;
-  if ((st = forward_backward(s, static_cast<int64_t>(first), static_cast<int64_t>(count), nullptr)) != PP_OK) return st;
+  if ((st = check_rows(s, static_cast<int64_t>(first), static_cast<int64_t>(count))) != PP_OK) return st;
+  if ((st = forward_backward(s, slice_rows(s, static_cast<int64_t>(first)), static_cast<int64_t>(count), nullptr)) !=
+      PP_OK)
+    return st;
   PP_HIP(s->ctx, hipDeviceSynchronize());
   if (loss) {
     double l = 0;
@@ -492,7 +577,10 @@ pp_status pp_sur_train_step(pp_surrogate *s, uint64_t first, uint64_t count, flo
   if (!s) return PP_EINVAL;
   pp_status st = need_device(s->ctx);
   if (st != PP_OK) return st;
-  if ((st = forward_backward(s, static_cast<int64_t>(first), static_cast<int64_t>(count), nullptr)) != PP_OK) return st;
+  if ((st = check_rows(s, static_cast<int64_t>(first), static_cast<int64_t>(count))) != PP_OK) return st;
+  if ((st = forward_backward(s, slice_rows(s, static_cast<int64_t>(first)), static_cast<int64_t>(count), nullptr)) !=
+      PP_OK)
+    return st;
   if ((st = adam_step(s, lr, nullptr)) != PP_OK) return st;
   PP_HIP(s->ctx, hipDeviceSynchronize());
   if (loss) {
@@ -503,24 +591,47 @@ pp_status pp_sur_train_step(pp_surrogate *s, uint64_t first, uint64_t count, flo
   return PP_OK;
 }
 
-pp_status pp_sur_train(pp_surrogate *s, uint32_t epochs, uint32_t batch_size, float lr, void *hip_stream,
-                       float *epoch_loss) {
+pp_status pp_sur_train(pp_surrogate *s, uint32_t epochs, uint32_t batch_size, float lr, float lr_final,
+                       void *hip_stream, float *epoch_loss) {
   if (!s) return PP_EINVAL;
   pp_context *ctx = s->ctx;
   pp_status st = need_device(ctx);
   if (st != PP_OK) return st;
   if (batch_size == 0 || batch_size % 64 != 0) return fail(ctx, PP_EINVAL, "batch_size must be a positive multiple of 64");
+  if (!(lr >= 0.0f) || !(lr_final >= 0.0f) || !std::isfinite(lr) || !std::isfinite(lr_final))
+    return fail(ctx, PP_EINVAL, "learning rates must be finite and non-negative");
   if (s->P == 0) return fail(ctx, PP_ESTATE, "no training set");
+  if (static_cast<uint64_t>(s->P) >= (1ull << 32)) return fail(ctx, PP_EINVAL, "training set above 2^32 rows");
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
   double *d_epoch = nullptr;
   if ((st = dalloc(ctx, &d_epoch, 1)) != PP_OK) return st;
   s->epoch_loss = d_epoch;
+  const uint64_t P = static_cast<uint64_t>(s->P);
+  const int64_t steps_per_epoch = (s->P + batch_size - 1) / batch_size;
+  const double total_steps = static_cast<double>(steps_per_epoch) * epochs;
+  int64_t step = 0;
   for (uint32_t e = 0; e < epochs; ++e) {
+    // this epoch's row order: p(r) = (mul r + add) mod P with mul coprime to
+    // P, mul / P stepping through the golden-ratio sequence so consecutive
+    // rows come from sources spread over the whole set
+    std::mt19937_64 rng(s->shuffle_seed + 0x9E3779B97F4A7C15ull * (s->epochs_done + 1));
+    double frac = std::fmod(0.6180339887498949 * static_cast<double>(s->epochs_done + 1), 1.0);
+    if (frac < 0.1 || frac > 0.9) frac = 0.5 * frac + 0.25;
+    uint64_t mul = std::max<uint64_t>(1, static_cast<uint64_t>(frac * static_cast<double>(P))) % P;
+    if (mul == 0) mul = 1;
+    while (gcd64(mul, P) != 1) mul = mul + 1 < P ? mul + 1 : 1;
+    const uint64_t add = rng() % P;
+    s->epochs_done += 1;
     PP_HIP(ctx, sur::launch_zero_f64(d_epoch, 1, stream));
-    for (int64_t first = 0; first < s->P; first += batch_size) {
+    for (int64_t first = 0; first < s->P; first += batch_size, ++step) {
       const int64_t count = std::min<int64_t>(batch_size, s->P - first);
-      if ((st = forward_backward(s, first, count, stream)) != PP_OK) break;
-      if ((st = adam_step(s, lr, stream)) != PP_OK) break;
+      Rows r;
+      if ((st = gather_rows(s, mul, add, first, count, &r, stream)) != PP_OK) break;
+      if ((st = forward_backward(s, r, count, stream)) != PP_OK) break;
+      // cosine decay from lr to lr_final over this call's steps
+      const double c = 0.5 * (1.0 + std::cos(M_PI * static_cast<double>(step) / total_steps));
+      const float lr_t = static_cast<float>(lr_final + (lr - lr_final) * c);
+      if ((st = adam_step(s, lr_t, stream)) != PP_OK) break;
     }
     if (st != PP_OK) break;
     if (epoch_loss) {

@@ -91,7 +91,22 @@ struct LossArgs {
   double *loss_epoch;    // also accumulated into, if not null
 };
 
+// Copies training rows p(r) = (mul * r + add) mod P, r in [first, first + count),
+// into dense minibatch buffers (row i of the batch = row p(first + i)); rows
+// [count, M) of the batch are zero. mul is coprime to P, so p is a permutation.
+struct GatherArgs {
+  const uint16_t *X;                                // bf16 P_pad x 64
+  const float *mu_base, *nph, *k, *n_t, *s1, *s2;   // per training row
+  uint64_t P, mul, add;
+  int64_t first;
+  int count, M;
+  uint16_t *gX;    // bf16 M x 64
+  uint16_t *gXT;   // bf16 64 x M
+  float *g_mu_base, *g_nph, *g_k, *g_n_t, *g_s1, *g_s2;
+};
+
 hipError_t launch_gemm(int epi, const GemmArgs &g, int splits, hipStream_t s);
+hipError_t launch_gather(const GatherArgs &g, hipStream_t s);
 hipError_t launch_features(const FeatureArgs &f, hipStream_t s);
 hipError_t launch_loss(const LossArgs &l, hipStream_t s);
 hipError_t launch_rowsum(const uint16_t *XT, int64_t ld, int rows, int cols, float *out, hipStream_t s);

@@ -354,6 +354,39 @@ hipError_t launch_loss(const LossArgs &l, hipStream_t s) {
   return hipGetLastError();
 }
 
+// One thread per (batch row, feature column); columns 64..69 carry the labels.
+__global__ void __launch_bounds__(256) k_gather(const GatherArgs g) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = t / 72, c = t % 72;
+  if (i >= g.M) return;
+  const bool real = i < g.count;
+  const uint64_t r = (uint64_t)(g.first + i);
+  const uint64_t p = real ? (g.mul * r + g.add) % g.P : 0;
+  if (c < kInPad) {
+    const uint16_t v = real ? g.X[p * kInPad + c] : (uint16_t)0;
+    g.gX[i * kInPad + c] = v;
+    g.gXT[c * (int64_t)g.M + i] = v;
+    return;
+  }
+  const float *src;
+  float *dst;
+  switch (c - kInPad) {
+    case 0: src = g.mu_base, dst = g.g_mu_base; break;
+    case 1: src = g.nph, dst = g.g_nph; break;
+    case 2: src = g.k, dst = g.g_k; break;
+    case 3: src = g.n_t, dst = g.g_n_t; break;
+    case 4: src = g.s1, dst = g.g_s1; break;
+    case 5: src = g.s2, dst = g.g_s2; break;
+    default: return;
+  }
+  dst[i] = real ? src[p] : 0.0f;
+}
+
+hipError_t launch_gather(const GatherArgs &g, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for((int64_t)g.M * 72, 256)), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_rowsum(const uint16_t *XT, int64_t ld, int rows, int cols, float *out, hipStream_t s) {
   hipLaunchKernelGGL(k_rowsum, dim3(rows), dim3(256), 0, s, XT, ld, cols, out);
   return hipGetLastError();

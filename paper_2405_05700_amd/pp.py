@@ -24,9 +24,9 @@ RECORD_DTYPE = np.dtype([("fate", "<u4"), ("dom_id", "<u4"), ("n_iter", "<u4"), 
                         align=True)
 assert HIT_DTYPE.itemsize == 32 and RECORD_DTYPE.itemsize == 48
 
-PP_OK, PP_EINVAL, PP_ENOMEM, PP_EDEVICE, PP_ESTATE, PP_ETRUNC = 0, -1, -2, -3, -4, -5
+PP_OK, PP_EINVAL, PP_ENOMEM, PP_EDEVICE, PP_ESTATE, PP_ETRUNC, PP_EBUDGET = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "PP_OK", -1: "PP_EINVAL", -2: "PP_ENOMEM", -3: "PP_EDEVICE",
-                -4: "PP_ESTATE", -5: "PP_ETRUNC"}
+                -4: "PP_ESTATE", -5: "PP_ETRUNC", -6: "PP_EBUDGET"}
 FATE_ABSORBED, FATE_HIT, FATE_CAPPED, FATE_ESCAPED = 0, 1, 2, 3
 NO_DOM = 0xFFFFFFFF
 

@@ -22,7 +22,7 @@ SIGNATURES = {
     "pp_sur_get_training_rows": (C.c_int, [_vp, _u64, _u64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pp_sur_loss_grad": (C.c_int, [_vp, _u64, _u64, C.POINTER(C.c_double), _vp]),
     "pp_sur_train_step": (C.c_int, [_vp, _u64, _u64, C.c_float, C.POINTER(C.c_double)]),
-    "pp_sur_train": (C.c_int, [_vp, _u32, _u32, C.c_float, _vp, _vp]),
+    "pp_sur_train": (C.c_int, [_vp, _u32, _u32, C.c_float, C.c_float, _vp, _vp]),
     "pp_sur_expected_hits": (C.c_int, [_vp, _u64, _vp, _vp]),
     "pp_sur_predict_pairs": (C.c_int, [_vp, _u64, _vp, _u64]),
 }
@@ -103,10 +103,13 @@ class Surrogate:
         self._check(_lib.pp_sur_train_step(self._h, first, count, lr, C.byref(loss)))
         return loss.value
 
-    def train(self, epochs: int, batch_size: int = 8192, lr: float = 1e-3, stream=None) -> np.ndarray:
+    def train(self, epochs: int, batch_size: int = 8192, lr: float = 1e-3, lr_final: float | None = None,
+              stream=None) -> np.ndarray:
+        """Shuffled minibatch Adam; the learning rate decays along a cosine
+        from lr to lr_final (default: constant lr)."""
         losses = np.zeros(epochs, np.float32)
-        self._check(_lib.pp_sur_train(self._h, epochs, batch_size, lr, pp._stream_handle(stream),
-                                      _p(losses)))
+        self._check(_lib.pp_sur_train(self._h, epochs, batch_size, lr, lr if lr_final is None else lr_final,
+                                      pp._stream_handle(stream), _p(losses)))
         return losses
 
     def expected_hits(self, batch: int, out=None, stream=None):

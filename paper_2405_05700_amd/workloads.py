@@ -215,6 +215,49 @@ def full_detector(n_sources: int = 1000, photons_per_source: int = 100_000,
                     cherenkov_segments(n_sources, photons_per_source, seed))
 
 
+def near_module_segments(w: Workload, n_sources: int, photons_per_source, seed: int = 0,
+                         r_min: float = 3.0, r_max: float = 120.0, targets=None,
+                         length_m: float = 10.0, first_event_id: int = 0) -> np.ndarray:
+    """Cherenkov segments (as in cherenkov_segments) whose centres lie at a
+    log-uniform distance in [r_min, r_max] m from a module, in a uniform
+    direction; the module is drawn uniformly from `targets` (default: all
+    modules of w), cycling through them in order if targets is given.
+    Segments whose centre would fall inside a module are pushed out to
+    r_min. Draw order from numpy default_rng(seed): target (if not given),
+    distance fraction, offset cos(theta), offset azimuth, cos(zenith),
+    direction azimuth."""
+    rng = np.random.default_rng(seed)
+    if targets is None:
+        tgt = rng.integers(0, len(w.doms), n_sources)
+    else:
+        tgt = np.resize(np.asarray(targets), n_sources)
+    r = r_min * (r_max / r_min) ** rng.random(n_sources)
+    ct = rng.uniform(-1.0, 1.0, n_sources)
+    ph = 2.0 * np.pi * rng.random(n_sources)
+    cz = rng.uniform(0.2, 1.0, n_sources)
+    az = 2.0 * np.pi * rng.random(n_sources)
+    st = np.sqrt(1.0 - ct * ct)
+    off = np.stack([st * np.cos(ph), st * np.sin(ph), ct], 1) * r[:, None]
+    m = np.stack([w.doms["x"], w.doms["y"], w.doms["z"]], 1).astype(np.float64)[tgt]
+    centre = m + off
+    sz = np.sqrt(1.0 - cz * cz)
+    d = np.stack([sz * np.cos(az), sz * np.sin(az), -cz], axis=1)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    start = centre - 0.5 * length_m * d
+    s = np.zeros(n_sources, dtype=SOURCE_DTYPE)
+    s["type"] = SOURCE_CHERENKOV
+    s["event_id"] = first_event_id + np.arange(n_sources)
+    s["particle_id"] = np.arange(n_sources)
+    s["x"], s["y"], s["z"] = start[:, 0], start[:, 1], start[:, 2]
+    s["dx"], s["dy"], s["dz"] = d[:, 0], d[:, 1], d[:, 2]
+    s["length_m"] = length_m
+    s["cherenkov_deg"] = 41.0
+    s["lambda_min_nm"] = 300.0
+    s["lambda_max_nm"] = 600.0
+    s["n_photons"] = photons_per_source
+    return s
+
+
 def power_law_energies(n_events: int, seed: int = 0, index: float = 2.7,
                        e_min: float = 1e2, e_max: float = 1e7) -> np.ndarray:
     """Energies (GeV) from a density proportional to E^-index on

@@ -32,13 +32,13 @@ def declared_functions(header=None):
 
 
 def test_every_declared_symbol_is_exported(pp):
-    from paper_2405_05700_amd import surrogate
+    from paper_2405_05700_amd import server, surrogate
     names = declared_functions()
     assert len(names) >= 30
     for n in names:
         assert hasattr(pp._lib, n), n
     assert set(declared_functions(HEADER)) == set(pp.SIGNATURES)
-    assert set(names) == set(pp.SIGNATURES) | set(surrogate.SIGNATURES)
+    assert set(names) == set(pp.SIGNATURES) | set(surrogate.SIGNATURES) | set(server.SIGNATURES)
     out = subprocess.check_output(["nm", "-D", "--defined-only", pp._LIB_PATH], text=True)
     exported = set(re.findall(r" T (pp_[a-z_]+)", out))
     assert set(names) <= exported
@@ -227,3 +227,25 @@ def test_full_detector_geometry_shape(pp):
     assert info["n_doms"] == 5160 and info["n_strings"] == 86
     assert info["grid_nx"] <= 64 and info["grid_ny"] <= 64
     assert abs(info["max_reach_m"] - W.DOM_RADIUS_M) < 1e-3
+
+
+def test_admission_plan_policy(pp):
+    """HBM-budget admission (host logic): arrival order, each request that
+    fits the remaining budget, one request per event id, caps on events and
+    photons per launch."""
+    from paper_2405_05700_amd import server
+    MB = 1 << 20
+    take = server.admit_plan([3 * MB, 4 * MB, 2 * MB, 1 * MB], [1, 2, 3, 4], [10, 10, 10, 10],
+                             bytes_in_use=2 * MB, budget=8 * MB, max_events=10, max_photons=1000)
+    assert take.tolist() == [True, False, True, True]  # 2+3=5, +4 > 8 skip, +2=7, +1=8
+    take = server.admit_plan([MB] * 4, [7, 7, 8, 7], [1] * 4, 0, 100 * MB, 10, 1000)
+    assert take.tolist() == [True, False, True, False]  # event 7 only once per launch
+    take = server.admit_plan([MB] * 5, [1, 2, 3, 4, 5], [1] * 5, 0, 100 * MB, 3, 1000)
+    assert take.sum() == 3 and take[:3].all()
+    take = server.admit_plan([MB] * 4, [1, 2, 3, 4], [600, 600, 600, 1], 0, 100 * MB, 10, 1000)
+    assert take.tolist() == [True, True, False, False]  # closes once 1000 photons are reached
+    take = server.admit_plan([MB], [1], [1], 9 * MB, 8 * MB, 10, 1000)  # over budget already
+    assert not take.any()
+    # the admission cost covers the default hit buffer and grows with photons
+    assert server.request_bytes(1, 1000) >= 32 * 65536
+    assert server.request_bytes(1, 10**9) > server.request_bytes(1, 10**6)
