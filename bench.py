@@ -25,13 +25,13 @@ sys.path.insert(0, ROOT)
 # Algorithmic VALU work in full-rate lane slots: one full-rate VALU op on one
 # lane is 1 slot; a transcendental (log, sin, cos, rcp, sqrt, rsq) or a
 # 32x32->64 multiply-add is 4 slots and a 32-bit mul_hi / mul_lo 2 slots,
-# the issue rates measured on gfx950 relative to v_fma_f32. Frozen counts of
-# the arithmetic each unit needs in the FP32 formulation (derivation table
-# in the design notes):
-SLOTS_PER_STEP = 260        # one propagation step (Philox block 121 of it)
+# the issue rates measured on gfx950 relative to v_fma_f32. Counts of the
+# arithmetic each unit needs in the FP32 formulation, in gfx950 operations
+# (a three-input xor is one v_bitop3_b32):
+SLOTS_PER_STEP = 240        # one propagation step (Philox block 101 of it)
 SLOTS_PER_CROSSING = 28     # each extra layer of the layer walk
 SLOTS_PER_DOM_TEST = 32     # each ray-sphere test
-SLOTS_PER_PHOTON = 205      # emission (Philox block 0, cone rotation, setup)
+SLOTS_PER_PHOTON = 185      # emission pass (Philox block 0, cone rotation, setup)
 FLOPS_PER_STEP = 90         # FP32 FLOPs of a step (FMA = 2), for the FLOP form
 # Peak: MI355X FP32 vector 157.3 TFLOP/s = 256 CUs x 128 FP32 lanes/clock x
 # 2 FLOP per FMA x 2.4 GHz, i.e. 78.65e12 full-rate lane slots/s.
@@ -69,6 +69,7 @@ def parse():
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--chunk-size", type=int, default=0)
     ap.add_argument("--grid-blocks", type=int, default=0)
+    ap.add_argument("--refill-interval", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-photons-per-source", type=int, default=0,
                     help="oracle sample: first N photons of every source (0 = auto, ~15 s)")
@@ -306,7 +307,8 @@ def main():
     n_photons = w.n_photons
     ctx = pp.Context(0, seed=0)
     ctx.load_workload(w)
-    ctx.set_launch_config(args.block_size, args.chunk_size, args.grid_blocks)
+    ctx.set_launch_config(args.block_size, args.chunk_size, args.grid_blocks,
+                          refill_interval=args.refill_interval)
     batch = ctx.submit(w.sources)
     stream = torch.cuda.Stream()
     counts = torch.empty(len(w.doms), dtype=torch.int32, device="cuda:0")
@@ -362,6 +364,7 @@ def main():
                                "photons",
                    "photons_per_step": n_photons, "seed": 0,
                    "block_size": cfg["block_size"], "chunk_size": args.chunk_size or "auto",
+                   "refill_interval": cfg["refill_interval"],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "T lane-slots/s", "frac": achieved / PEAK_SLOTS,

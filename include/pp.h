@@ -157,8 +157,8 @@ typedef struct {
   uint32_t block_size;  /* threads per workgroup, multiple of 64, <= 1024 (default 256) */
   uint32_t chunk_size;  /* photon ids taken per queue grab by one wavefront (default 256) */
   uint32_t grid_blocks; /* workgroups launched (default: enough to fill every CU) */
-  uint32_t refill_interval; /* propagation steps between refills of a wavefront's ended
-                               lanes (default 8) */
+  uint32_t refill_interval; /* passes between refills of a wavefront's ended lanes
+                               (default 4) */
   uint64_t hit_capacity;/* initial device hit-buffer size in hits (default from photons) */
 } pp_launch_config;
 
@@ -276,7 +276,7 @@ pp_status pp_get_stats(pp_context *ctx, uint64_t batch, pp_stats *out);
  * 1e3-photon event share the device without imbalance. */
 
 /* Times the batch under a fixed set of launch configurations (workgroup
- * size 256/512, chunk size 64/256/1024, refill interval 4/8/16), each one
+ * size 256/512, chunk size 64/256/1024, refill interval 2/4/8), each one
  * full propagation on hip_stream, and keeps the fastest as the context's
  * launch configuration (also written to *best if non-NULL). Results do not
  * change; only speed does. Synchronises the stream. */

@@ -81,7 +81,7 @@ pp_status find_batch(pp_context *ctx, uint64_t id, Batch **out) {
 
 uint32_t default_block() { return 256; }
 uint32_t default_chunk() { return 256; }
-uint32_t default_refill_interval() { return 8; }
+uint32_t default_refill_interval() { return 4; }
 
 // Horizontal distance from the rectangle [x0,x1] x [y0,y1] to the point.
 double rect_point_distance(double x0, double x1, double y0, double y1, double px, double py) {
@@ -837,7 +837,7 @@ pp_status pp_autotune(pp_context *ctx, uint64_t batch, void *hip_stream, pp_laun
   float best_ms = -1.0f;
   const uint32_t blocks[] = {256, 512};
   const uint32_t chunks[] = {64, 256, 1024};
-  const uint32_t refills[] = {4, 8, 16};
+  const uint32_t refills[] = {2, 4, 8};
   bool first = true;
   for (uint32_t blk : blocks)
     for (uint32_t chk : chunks)

@@ -12,9 +12,11 @@
 //     lanes whose photon ended are refilled from the chunk in the same pass
 //     (ballot + mbcnt rank), so lanes stay busy despite the long,
 //     geometric tail of steps per photon;
-//   * emission shares the pass with propagation: a new lane draws Philox
-//     block 0 where a running lane draws block 2 + j, and both go through
-//     the same rotation code (emission is a rotation of the source axis);
+//   * emission shares the pass with propagation: a refilled lane draws
+//     Philox block 0 where a running lane draws block 2 + j, and both share
+//     the generator, the logarithm and the rotation (emission is a rotation
+//     of the source axis), so the refill itself is only bookkeeping and can
+//     run every few passes;
 //   * the layer table, the string table and the horizontal search grid are
 //     staged in LDS once per workgroup; module coordinates stay in global
 //     memory (read only when a photon passes within reach of a string);
@@ -31,24 +33,29 @@ namespace pp {
 namespace {
 
 constexpr uint32_t kNoDom = 0xFFFFFFFFu;
-constexpr uint32_t kLive = 0xFFu;
+constexpr uint32_t kLive = 0xFFu;  // fate of a photon still propagating
 constexpr uint32_t kFateAbsorbed = 0, kFateHit = 1, kFateCapped = 2, kFateEscaped = 3;
 constexpr float kNsPerMetreLight = 3.3356409519815204f;  // 1 / c, c = 0.299792458 m/ns
 constexpr float kLn2 = 0.69314718055994531f;
 
 __device__ __forceinline__ float inf_f() { return __builtin_huge_valf(); }
 
+// a ^ b ^ c in one gfx950 instruction (v_bitop3_b32, truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32-10 (Salmon et al., SC'11). The key schedule is wave-uniform, so
 // the compiler keeps it in SGPRs; each round costs two 32x32->64 multiplies
-// per lane.
+// and two three-input xors per lane.
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t k0, uint32_t k1, uint32_t w[4]) {
 #pragma unroll
   for (int round = 0; round < 10; ++round) {
     const unsigned long long p0 = (unsigned long long)0xD2511F53u * c0;
     const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
@@ -100,7 +107,7 @@ __device__ __forceinline__ void test_module(const float4 m, const Segment &s, fl
   const float hx = dx - b * s.vx, hy = dy - b * s.vy, hz = dz - b * s.vz;
   const float disc = r2 - (hx * hx + hy * hy + hz * hz);
   if (disc >= 0.0f && dx * dx + dy * dy + dz * dz >= r2) {
-    const float t = -b - __builtin_sqrtf(disc);
+    const float t = -b - __builtin_amdgcn_sqrtf(disc);
     const uint32_t id = __float_as_uint(m.w);
     if (t >= 0.0f && t <= s.len && (t < best_t || (t == best_t && id < best_id))) {
       best_t = t;
@@ -144,7 +151,7 @@ __device__ __forceinline__ void rotate(float rx, float ry, float rz, float om, f
   const float e1x = __builtin_fmaf(sign * rx * rx, a, 1.0f), e1y = sign * b, e1z = -sign * rx;
   const float e2x = b, e2y = __builtin_fmaf(ry * ry, a, sign), e2z = -ry;
   const float mu = 1.0f - om;
-  const float st = __builtin_sqrtf(om * (2.0f - om));
+  const float st = __builtin_amdgcn_sqrtf(om * (2.0f - om));  // v_sqrt_f32 (1 ulp)
   const float c = __builtin_amdgcn_cosf(phi_turns);  // hardware cos/sin take turns
   const float s = __builtin_amdgcn_sinf(phi_turns);
   const float sc = st * c, ss = st * s;
@@ -180,21 +187,25 @@ k_propagate(const PropagateArgs a) {
   bool more = true;
   uint32_t n_photons = 0, n_hits = 0, n_abs = 0, n_cap = 0, n_esc = 0;
 
-  // lane state: a lane is live (propagating), ended (stopped, output not yet
-  // written) or free
-  bool alive = false, ended = false;
-  uint32_t event = 0, particle = 0, iter = 0, ncross = 0, fate = 0, hit_dom = kNoDom;
+  // Lane state. A lane is free, emitting (photon assigned: position and
+  // direction hold the source's start point and axis), live (propagating)
+  // or ended (stopped, output not yet written).
+  constexpr uint32_t kFree = 0, kEmit = 1, kRun = 2, kEnded = 3;
+  uint32_t phase = kFree;
+  uint32_t event = 0, particle = 0, iter = 0, ncross = 0, fate = 0, hit_dom = kNoDom, src = 0;
   unsigned long long pidx = 0, seq = 0;
   float px = 0, py = 0, pz = 0, vx = 0, vy = 0, vz = 1, t = 0, tau_a = 0, lambda = 0;
+  float elen = 0, eom = 0;  // emission: track length (0: point) and 1 - cos(cone), < 0 for a point source
   int layer = 0;
   uint32_t st_iter = 0, st_cross = 0, st_tests = 0;
 
   for (;;) {
-    // Every refill_interval steps (or when no lane is live): write out the
-    // lanes that ended, then refill free lanes from the wavefront's chunk,
-    // emitting their photons (Philox block 0).
-    if (countdown == 0 || __ballot(alive) == 0) {
+    // Every refill_interval passes (or when no lane is emitting or live):
+    // write out the lanes that ended, then hand free lanes the next photon
+    // ids of the wavefront's chunk.
+    if (countdown == 0 || __ballot(phase == kEmit || phase == kRun) == 0) {
       countdown = a.refill_interval;
+      const bool ended = phase == kEnded;
       const unsigned long long hmask = __ballot(ended && fate == kFateHit);
       if (hmask != 0) {
         unsigned long long base = 0;
@@ -227,9 +238,9 @@ k_propagate(const PropagateArgs a) {
         a.rec.vz[seq] = vz;
         a.rec.wavelength[seq] = lambda;
       }
-      ended = false;
+      if (ended) phase = kFree;
 
-      unsigned long long free_mask = __ballot(!alive);
+      unsigned long long free_mask = __ballot(phase == kFree);
       while (free_mask != 0 && more) {
         if (ch_left == 0) {
           unsigned long long c = 0;
@@ -240,161 +251,190 @@ k_propagate(const PropagateArgs a) {
             break;
           }
           const DevChunk e = a.chunks[c];
-          ch_src = e.src;
-          ch_left = e.count;
-          ch_local = e.local;
+          ch_src = __builtin_amdgcn_readfirstlane(e.src);
+          ch_left = __builtin_amdgcn_readfirstlane(e.count);
+          ch_local = first_lane_u64(e.local);
         }
         const uint32_t take = min((uint32_t)__popcll(free_mask), ch_left);
         const uint32_t rank = lane_rank(free_mask);
         if (((free_mask >> lane) & 1ull) && rank < take) {
-          // Emission from the chunk's source (uniform across the wavefront):
-          // a point source rotates +z by cos(theta) = 2 u0 - 1; a Cherenkov
-          // segment emits from u0 * length along the track, on the cone about
-          // the track axis. Azimuth u1, absorption budget -ln u2.
+          // The chunk's source is uniform across the wavefront. The lane
+          // starts at the source's reference point on its axis; the
+          // emission pass moves it along the track and turns it onto the
+          // emission cone (or the sphere, for a point source).
           const DevSource &S = a.sources[ch_src];
           const unsigned long long local = ch_local + rank;
           pidx = S.first_index + local;
-          if (kRecords) seq = S.seq_base + local;
+          if (kRecords) {
+            seq = S.seq_base + local;
+            src = ch_src;
+          }
           event = S.ids.y;
           particle = S.ids.z;
-          uint32_t w[4];
-          philox4x32_10(0u, event, (uint32_t)pidx, (uint32_t)(pidx >> 32), a.seed_lo, a.seed_hi, w);
-          const float u0 = u01(w[0]);
           const bool point = S.ids.x == 0;
-          const float sdist = point ? 0.0f : u0 * S.dir_len.w;
-          px = __builtin_fmaf(sdist, S.dir_len.x, S.pos_t0.x);
-          py = __builtin_fmaf(sdist, S.dir_len.y, S.pos_t0.y);
-          pz = __builtin_fmaf(sdist, S.dir_len.z, S.pos_t0.z);
-          t = __builtin_fmaf(sdist, kNsPerMetreLight, S.pos_t0.w);
-          const float om = point ? 2.0f * (1.0f - u0) : S.emit.x;
-          rotate(S.dir_len.x, S.dir_len.y, S.dir_len.z, om, u01(w[1]), vx, vy, vz);
-          tau_a = -kLn2 * __builtin_amdgcn_logf(u01(w[2]));
-          if (kRecords)
-            lambda = S.emit.y != 0.0f ? S.emit.y
-                                      : __builtin_amdgcn_rcpf(__builtin_fmaf(-u01(w[3]), S.emit.w, S.emit.z));
-          const float lf = floorf((pz - a.z_lo) * a.inv_dz);
-          layer = lf >= 0.0f ? (lf >= (float)(a.n_layers - 1) ? a.n_layers - 1 : (int)lf) : 0;
+          px = S.pos_t0.x;
+          py = S.pos_t0.y;
+          pz = S.pos_t0.z;
+          t = S.pos_t0.w;
+          vx = S.dir_len.x;
+          vy = S.dir_len.y;
+          vz = S.dir_len.z;
+          elen = point ? 0.0f : S.dir_len.w;
+          eom = point ? -1.0f : S.emit.x;
           iter = 0;
           ncross = 0;
-          alive = a.step_cap != 0;
-          ended = !alive;
           fate = kFateCapped;
           hit_dom = kNoDom;
+          phase = kEmit;
         }
         n_photons += take;
         ch_left -= take;
         ch_local += take;
-        free_mask = __ballot(!alive && !ended);
+        free_mask = __ballot(phase == kFree);
       }
-      if (!more && __ballot(alive || ended) == 0) break;
+      if (!more && __ballot(phase != kFree) == 0) break;
     }
     --countdown;
 
-    if (alive) {
-      // The round keys are recomputed with scalar adds each step rather than
+    if (phase == kEmit || phase == kRun) {
+      const bool emit = phase == kEmit;
+      // The round keys are recomputed with scalar adds each pass rather than
       // held in 20 SGPRs across the loop (which would cap occupancy).
       uint32_t k0 = a.seed_lo, k1 = a.seed_hi;
       asm volatile("" : "+s"(k0), "+s"(k1));
       uint32_t w[4];
-      philox4x32_10(2u + iter, event, (uint32_t)pidx, (uint32_t)(pidx >> 32), k0, k1, w);
-      ++iter;
-      ++st_iter;
-      const float u1 = u01(w[1]), u2 = u01(w[2]);
-      float tau_s = -kLn2 * __builtin_amdgcn_logf(u01(w[0]));
+      philox4x32_10(emit ? 0u : 2u + iter, event, (uint32_t)pidx, (uint32_t)(pidx >> 32), k0, k1, w);
+      // One logarithm per pass: the absorption budget -ln u2 at emission,
+      // the scattering budget -ln u0 on a step.
+      const float budget = -kLn2 * __builtin_amdgcn_logf(u01(emit ? w[2] : w[0]));
+      float om, phi;
+      uint32_t f;
+      bool turn;  // take the rotated direction: emission, or a scatter (also the one that reaches the cap)
+      if (emit) {
+        // Emission (block 0): u0 places a Cherenkov photon along the track
+        // (a point source: cos(theta) = 2 u0 - 1 about +z), u1 is the
+        // azimuth, u2 the absorption budget.
+        const float u0 = u01(w[0]);
+        const float sdist = u0 * elen;
+        px = __builtin_fmaf(sdist, vx, px);
+        py = __builtin_fmaf(sdist, vy, py);
+        pz = __builtin_fmaf(sdist, vz, pz);
+        t = __builtin_fmaf(sdist, kNsPerMetreLight, t);
+        om = eom < 0.0f ? 2.0f * (1.0f - u0) : eom;
+        phi = u01(w[1]);
+        tau_a = budget;
+        if (kRecords) {
+          const DevSource &S = a.sources[src];
+          lambda = S.emit.y != 0.0f ? S.emit.y
+                                    : __builtin_amdgcn_rcpf(__builtin_fmaf(-u01(w[3]), S.emit.w, S.emit.z));
+        }
+        const float lf = floorf((pz - a.z_lo) * a.inv_dz);
+        layer = lf >= 0.0f ? (lf >= (float)(a.n_layers - 1) ? a.n_layers - 1 : (int)lf) : 0;
+        f = a.step_cap != 0 ? kLive : kFateCapped;
+        turn = true;
+      } else {
+        ++iter;
+        ++st_iter;
+        float tau_s = budget;
 
-      // Layer walk: consume both optical-depth budgets layer by layer until
-      // one runs out (ties: absorb <= scatter <= boundary). A zero
-      // coefficient has an infinite reciprocal; fminf turns the 0 * inf of
-      // an exhausted budget there into +inf (an infinite distance), so no
-      // distance is NaN and a crossing always has a finite boundary
-      // distance (the edge layers' boundaries are at infinity).
-      const bool up = vz > 0.0f;
-      const bool flat = vz == 0.0f;
-      const float rvz = __builtin_amdgcn_rcpf(vz);
-      float len = 0.0f, zc = pz;
-      int i = layer;
-      int end;  // 0 absorb, 1 scatter, 2 escape
-      for (;;) {
-        const float4 c = s_layers[i].coef;
-        const float d_abs = fminf(tau_a * c.z, inf_f());
-        const float d_sca = fminf(tau_s * c.w, inf_f());
-        const float zb = s_bounds[up ? i + 1 : i];
-        const float d_bnd = flat ? inf_f() : fmaxf(0.0f, (zb - zc) * rvz);
-        if (d_abs == inf_f() && d_sca == inf_f() && d_bnd == inf_f()) {
+        // Layer walk: consume both optical-depth budgets layer by layer
+        // until one runs out (ties: absorb <= scatter <= boundary). A zero
+        // coefficient has an infinite reciprocal; fminf turns the 0 * inf of
+        // an exhausted budget there into +inf (an infinite distance), so no
+        // distance is NaN and a crossing always has a finite boundary
+        // distance (the edge layers' boundaries are at infinity).
+        const bool up = vz > 0.0f;
+        const bool flat = vz == 0.0f;
+        const float rvz = __builtin_amdgcn_rcpf(vz);
+        const int di = up ? 1 : -1, bofs = up ? 1 : 0;
+        float len = 0.0f, zc = pz, cx, d_abs, d_sca;
+        int i = layer;
+        for (;;) {
+          const float4 c = s_layers[i].coef;
+          cx = c.x;
+          d_abs = fminf(tau_a * c.z, inf_f());
+          d_sca = fminf(tau_s * c.w, inf_f());
+          const float zb = s_bounds[i + bofs];
+          const float d_bnd = flat ? inf_f() : fmaxf(0.0f, (zb - zc) * rvz);
+          if (!(d_bnd < fminf(d_abs, d_sca))) break;
+          len += d_bnd;
+          tau_a = fmaxf(0.0f, tau_a - c.x * d_bnd);
+          tau_s = fmaxf(0.0f, tau_s - c.y * d_bnd);
+          zc = zb;
+          i += di;
+        }
+        const uint32_t crossed = (uint32_t)abs(i - layer);
+        ncross += crossed;
+        st_cross += crossed;
+        int end;  // 0 absorb, 1 scatter, 2 escape (all three distances infinite)
+        if (d_abs == inf_f() && d_sca == inf_f()) {
           len = inf_f();
           end = 2;
-          break;
-        }
-        if (d_abs <= d_sca && d_abs <= d_bnd) {
+        } else if (d_abs <= d_sca) {
           len += d_abs;
           end = 0;
-          break;
-        }
-        if (d_sca <= d_bnd) {
+        } else {
           len += d_sca;
-          tau_a = fmaxf(0.0f, tau_a - c.x * d_sca);
+          tau_a = fmaxf(0.0f, tau_a - cx * d_sca);
           end = 1;
-          break;
         }
-        len += d_bnd;
-        tau_a = fmaxf(0.0f, tau_a - c.x * d_bnd);
-        tau_s = fmaxf(0.0f, tau_s - c.y * d_bnd);
-        zc = zb;
-        i += up ? 1 : -1;
-        ++ncross;
-        ++st_cross;
-      }
 
-      // Nearest module on the segment: the string listed for the grid cell
-      // of the start point, and every other string only when the step is at
-      // least the cell's clearance to them.
-      const Segment seg{px, py, pz, vx, vy, vz, len};
-      float best_t = inf_f();
-      uint32_t best_id = kNoDom;
-      {
-        const float fx = __builtin_amdgcn_fmed3f((px - a.gx0) * a.inv_cell, 0.0f, a.nx_max);
-        const float fy = __builtin_amdgcn_fmed3f((py - a.gy0) * a.inv_cell, 0.0f, a.ny_max);
-        const uint32_t word = s_cells[__umul24((uint32_t)fy, (uint32_t)a.nx) + (uint32_t)fx];
-        const uint32_t s1 = word & 0xFFFFu;
-        const float clearance = __uint_as_float(word & 0xFFFF0000u);
-        if (s1 != 0xFFFFu)
-          test_string(s_strings[s1], a.doms, seg, a.radius, r2, best_t, best_id, st_tests);
-        if (len >= clearance) {
-          for (int s = 0; s < a.n_strings; ++s)
-            if ((uint32_t)s != s1)
-              test_string(s_strings[s], a.doms, seg, a.radius, r2, best_t, best_id, st_tests);
+        // Nearest module on the segment: the string listed for the grid cell
+        // of the start point, and every other string only when the step is
+        // at least the cell's clearance to them.
+        const Segment seg{px, py, pz, vx, vy, vz, len};
+        float best_t = inf_f();
+        uint32_t best_id = kNoDom;
+        {
+          const float fx = __builtin_amdgcn_fmed3f((px - a.gx0) * a.inv_cell, 0.0f, a.nx_max);
+          const float fy = __builtin_amdgcn_fmed3f((py - a.gy0) * a.inv_cell, 0.0f, a.ny_max);
+          const uint32_t word = s_cells[__umul24((uint32_t)fy, (uint32_t)a.nx) + (uint32_t)fx];
+          const uint32_t s1 = word & 0xFFFFu;
+          const float clearance = __uint_as_float(word & 0xFFFF0000u);
+          if (s1 != 0xFFFFu)
+            test_string(s_strings[s1], a.doms, seg, a.radius, r2, best_t, best_id, st_tests);
+          if (len >= clearance) {
+            for (int s = 0; s < a.n_strings; ++s)
+              if ((uint32_t)s != s1)
+                test_string(s_strings[s], a.doms, seg, a.radius, r2, best_t, best_id, st_tests);
+          }
         }
+
+        const bool hit = best_id != kNoDom;
+        const float dmove = hit ? best_t : (end == 2 ? 0.0f : len);
+        px = __builtin_fmaf(dmove, vx, px);
+        py = __builtin_fmaf(dmove, vy, py);
+        pz = __builtin_fmaf(dmove, vz, pz);
+        t = __builtin_fmaf(dmove, a.time_per_m, t);
+        layer = i;
+        hit_dom = best_id;
+        f = hit ? kFateHit : (end == 2 ? kFateEscaped : (end == 0 ? kFateAbsorbed : kLive));
+        turn = f == kLive;
+        if (turn && iter >= a.step_cap) f = kFateCapped;
+
+        // Henyey-Greenstein polar angle in the cancellation-free form
+        // 1 - mu = (1 - g)(1 - u)(s + 1 - g)/w, w = 1 - g + 2 g u,
+        // s = (1 - g^2)/w, with u = u1, and azimuth u2.
+        const float4 hg = s_layers[i].hg;
+        const float u1 = u01(w[1]);
+        const float rw = __builtin_amdgcn_rcpf(__builtin_fmaf(hg.z, u1, hg.x));
+        om = hg.x * (1.0f - u1) * __builtin_fmaf(hg.y, rw, hg.x) * rw;
+        phi = u01(w[2]);
       }
-
-      const bool hit = best_id != kNoDom;
-      const float dmove = hit ? best_t : (end == 2 ? 0.0f : len);
-      px = __builtin_fmaf(dmove, vx, px);
-      py = __builtin_fmaf(dmove, vy, py);
-      pz = __builtin_fmaf(dmove, vz, pz);
-      t = __builtin_fmaf(dmove, a.time_per_m, t);
-      layer = i;
-      uint32_t f = hit ? kFateHit : (end == 2 ? kFateEscaped : (end == 0 ? kFateAbsorbed : kLive));
-
-      // Henyey-Greenstein polar angle in the cancellation-free form
-      // 1 - mu = (1 - g)(1 - u)(s + 1 - g)/w, w = 1 - g + 2 g u,
-      // s = (1 - g^2)/w, and azimuth u2, evaluated by every live lane; it is
-      // kept only by lanes that scatter.
-      const float4 hg = s_layers[i].hg;
-      const float rw = __builtin_amdgcn_rcpf(__builtin_fmaf(hg.z, u1, hg.x));
-      const float om = hg.x * (1.0f - u1) * __builtin_fmaf(hg.y, rw, hg.x) * rw;
+      // One rotation serves both: the emission cone about the source axis
+      // and the scattering angle about the current direction.
       float nx, ny, nz;
-      rotate(vx, vy, vz, om, u2, nx, ny, nz);
-      if (f == kLive) {
+      rotate(vx, vy, vz, om, phi, nx, ny, nz);
+      if (turn) {
         vx = nx;
         vy = ny;
         vz = nz;
-        if (iter >= a.step_cap) f = kFateCapped;
       }
-      if (f != kLive) {
-        alive = false;
-        ended = true;
+      if (f == kLive) {
+        phase = kRun;
+      } else {
+        phase = kEnded;
         fate = f;
-        hit_dom = best_id;
       }
     }
   }

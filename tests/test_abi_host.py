@@ -170,7 +170,7 @@ def test_launch_config_validation(pp):
     assert ctx.launch_config() == {"block_size": 512, "chunk_size": 77, "grid_blocks": 3,
                                    "hit_capacity": 10, "refill_interval": 6}
     ctx.set_launch_config()
-    assert ctx.launch_config()["refill_interval"] == 8
+    assert ctx.launch_config()["refill_interval"] == 4
     expect(pp, pp.PP_EINVAL, ctx.set_step_cap, 2**31 + 1)
     ctx.set_step_cap(0)
 
