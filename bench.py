@@ -76,11 +76,12 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--sur-train-sources", type=int, default=2000)
     ap.add_argument("--sur-train-photons", type=int, default=4_000_000)
-    ap.add_argument("--sur-epochs", type=int, default=8)
-    ap.add_argument("--sur-lr", type=float, default=2e-3)
+    ap.add_argument("--sur-epochs", type=int, default=48)
+    ap.add_argument("--sur-lr", type=float, default=1e-3)
+    ap.add_argument("--sur-lr-final", type=float, default=1e-5)
     ap.add_argument("--sur-infer-sources", type=int, default=100_000)
     ap.add_argument("--sur-eval-targets", type=int, default=40)
-    ap.add_argument("--sur-truth-photons", type=int, default=20_000_000)
+    ap.add_argument("--sur-truth-photons", type=int, default=100_000_000)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
@@ -130,8 +131,8 @@ def surrogate_leg(args):
     """Learned surrogate. Training: Monte Carlo of 2000 segments placed 3-120 m
     from random modules of the full detector (5160 modules each: about 1e7
     (segment, module) pairs). Inference throughput: 1e5 full-detector
-    segments x 5160 modules. Accuracy and speed-up: clusters of held-out
-    segments around target modules; truth = high-statistics Monte Carlo;
+    segments x 5160 modules. Accuracy and speed-up: clusters of four held-out
+    segments 4-20 m from each of 40 target modules; truth = high-statistics Monte Carlo;
     graded modules have >= 1e4 truth hits (<= 1% statistical error). Plain
     Monte Carlo needs enough photons for >= 2500 hits (2%) on every graded
     module; surrogate+MC takes the surrogate's expectation where it is
@@ -155,11 +156,12 @@ def surrogate_leg(args):
     torch.cuda.synchronize()
     n_pairs = sur.training_size()
     t1 = time.perf_counter()
-    losses = sur.train(epochs=args.sur_epochs, batch_size=8192, lr=args.sur_lr)
+    losses = sur.train(epochs=args.sur_epochs, batch_size=8192, lr=args.sur_lr, lr_final=args.sur_lr_final)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     out.update({"train_sources": args.sur_train_sources, "train_photons_per_source": args.sur_train_photons,
                 "train_pairs": n_pairs, "label_mc_and_features_s": t1 - t0, "train_epochs": args.sur_epochs,
+                "train_lr": [args.sur_lr, args.sur_lr_final],
                 "train_s": t2 - t1, "train_pairs_per_s": n_pairs * args.sur_epochs / (t2 - t1),
                 "epoch_loss": [float(x) for x in losses]})
     ctx.release(b_tr)
@@ -182,7 +184,7 @@ def surrogate_leg(args):
     rng = np.random.default_rng(404)
     targets = rng.choice(len(det.doms), args.sur_eval_targets, replace=False)
     ev = W.near_module_segments(det, 4 * args.sur_eval_targets, args.sur_truth_photons, seed=202,
-                                r_min=5.0, r_max=40.0, targets=targets)
+                                r_min=4.0, r_max=20.0, targets=targets)
     b_ev = ctx.submit(ev)
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
