@@ -36,6 +36,11 @@ FLOPS_PER_STEP = 90         # FP32 FLOPs of a step (FMA = 2), for the FLOP form
 # Peak: MI355X FP32 vector 157.3 TFLOP/s = 256 CUs x 128 FP32 lanes/clock x
 # 2 FLOP per FMA x 2.4 GHz, i.e. 78.65e12 full-rate lane slots/s.
 PEAK_FP32_FLOPS = 157.3e12
+# Surrogate inference: a (segment, module) pair needs 2 (16*256 + 3*256*256 +
+# 256*1) FLOPs (16 real inputs, three hidden 256 x 256 layers, one output
+# used), against the dense BF16 matrix-core peak of 2.5 PFLOP/s.
+INFER_FLOP_PER_PAIR = 2 * (16 * 256 + 3 * 256 * 256 + 256)
+PEAK_BF16_FLOPS = 2.5e15
 PEAK_SLOTS = PEAK_FP32_FLOPS / 2
 
 
@@ -101,6 +106,57 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
 
 
+def end_to_end(ctx, w):
+    """Host arrays in, host hits out: submit + propagate + fetch of the whole
+    workload, once (inputs not resident; the timed steps exclude this)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = ctx.submit(w.sources)
+    ctx.propagate(b)
+    hits = ctx.fetch_hits(b)
+    t1 = time.perf_counter()
+    ctx.release(b)
+    return {"end_to_end_ms": 1e3 * (t1 - t0), "end_to_end_photons_per_s": w.n_photons / (t1 - t0),
+            "end_to_end_hits": int(len(hits))}
+
+
+def tiny_rate():
+    """Photons/s on the small parity workload (one point source, 1e5
+    photons, one string): too small to fill the GPU, reported, not graded."""
+    import torch
+    from paper_2405_05700_amd import pp
+    from paper_2405_05700_amd import workloads as W
+    w = W.tiny_point_source(100_000)
+    ctx = pp.Context(0, seed=0)
+    ctx.load_workload(w)
+    b = ctx.submit(w.sources)
+    s = torch.cuda.Stream()
+    ctx.propagate(b, s)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        ctx.propagate(b, s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    med = sorted(ms)[len(ms) // 2]
+    ctx.close()
+    return {"tiny_point_source_kernel_ms_median": med, "tiny_point_source_photons_per_s": 1e5 / (med / 1e3)}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, per_source: int):
     from oracle import pyoracle
     import numpy as np
@@ -121,10 +177,20 @@ def cpu_baseline(w, per_source: int):
     r = pyoracle.run(w, sel_src=sel_src, sel_local=sel_loc, dom_mode=1, threads=threads,
                      records=False, dom_counts=False)
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, over a sixteenth of the sample
+    per1 = max(1, per_source // 16)
+    t2 = time.perf_counter()
+    r1 = pyoracle.run(w, sel_src=np.repeat(np.arange(len(w.sources)), per1),
+                      sel_local=np.tile(np.arange(per1), len(w.sources)), dom_mode=1, threads=1,
+                      records=False, dom_counts=False)
+    dt1 = time.perf_counter() - t2
     return {"value": r.counters["photons"] / dt, "unit": "photons/s", "cores": threads,
             "kind": "oracle",
             "sample": f"first {per_source} photons of each of the {len(w.sources)} sources "
-                      f"({r.counters['photons']} photons, FP64, per-string pre-filter), {dt:.1f} s"}
+                      f"({r.counters['photons']} photons, FP64, per-string pre-filter), {dt:.1f} s",
+            "one_thread_value": r1.counters["photons"] / dt1,
+            "one_thread_sample": f"first {per1} photons of each source, {dt1:.1f} s",
+            "host_cpu": cpu_model(), "host_cpus_visible": len(os.sched_getaffinity(0))}
 
 
 def surrogate_leg(args):
@@ -177,7 +243,10 @@ def surrogate_leg(args):
     t4 = time.perf_counter()
     pairs_inf = args.sur_infer_sources * len(det.doms)
     out.update({"infer_pairs": pairs_inf, "infer_s": t4 - t3, "infer_pairs_per_s": pairs_inf / (t4 - t3),
-                "infer_tflops": pairs_inf * 458752 / (t4 - t3) / 1e12})
+                "infer_roofline": {"bound": "mfma", "kernel": "k_infer_fused",
+                                   "achieved": pairs_inf * INFER_FLOP_PER_PAIR / (t4 - t3) / 1e12,
+                                   "peak": PEAK_BF16_FLOPS / 1e12, "unit": "TFLOP/s",
+                                   "frac": pairs_inf * INFER_FLOP_PER_PAIR / (t4 - t3) / PEAK_BF16_FLOPS}})
     ctx.release(b_inf)
 
     # accuracy and speed-up on held-out clusters around target modules
@@ -377,9 +446,11 @@ def main():
                    "dom_tests": st["dom_tests"], "hits": st["hits"], "absorbed": st["absorbed"],
                    "capped": st["capped"], "escaped": st["escaped"],
                    "iterations_per_photon": st["iterations"] / n_photons,
-                   "kernel_ms": kernel_ms, "lib_kernel_ms_last": st["kernel_ms"],
-                   "hits_fetched_count": n_hits},
+                   "kernel_ms": kernel_ms, "kernel_ms_median": sorted(kernel_ms)[len(kernel_ms) // 2],
+                   "lib_kernel_ms_last": st["kernel_ms"], "hits_fetched_count": n_hits},
     }
+    out["detail"].update(end_to_end(ctx, w))
+    out["detail"].update(tiny_rate())
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_photons_per_source)
     sur_params = None

@@ -44,8 +44,7 @@ struct pp_surrogate {
   uint64_t epochs_done = 0;
   // inference buffers (capacity Icap rows)
   int64_t Icap = 0;
-  uint16_t *iX = nullptr, *iH[2] = {};
-  float *i_mu = nullptr, *i_mub = nullptr, *i_nph = nullptr;
+  float *i_mu = nullptr;
 };
 
 namespace {
@@ -70,7 +69,7 @@ void dfree(T *&p) {
 
 pp_status gemm(pp_context *ctx, int epi, const uint16_t *A, int64_t lda, const uint16_t *B, int64_t ldb, int M,
                int N, int K, int splits, const float *bias, float *Z, uint16_t *H, uint16_t *HT, int64_t ldt,
-               const float *Zin, float *out, const float *nph, const float *mub, hipStream_t st) {
+               const float *Zin, float *out, hipStream_t st) {
   sur::GemmArgs g{};
   g.A = A;
   g.lda = lda;
@@ -89,8 +88,6 @@ pp_status gemm(pp_context *ctx, int epi, const uint16_t *A, int64_t lda, const u
   g.ldt = ldt;
   g.Zin = Zin;
   g.out = out;
-  g.row_nph = nph;
-  g.row_mubase = mub;
   PP_HIP(ctx, sur::launch_gemm(epi, g, splits, st));
   return PP_OK;
 }
@@ -155,13 +152,13 @@ pp_status forward_backward(pp_surrogate *s, const Rows &r, int64_t count, hipStr
   int64_t ld_in = kInPad;
   for (int l = 0; l < 4; ++l) {
     if ((rc = gemm(ctx, kEpiGelu, in, ld_in, wb_ptr(s, l), in_dim(l), M, kHidden, in_dim(l), 1, bias_ptr(s, l),
-                   s->Z[l], s->H[l], s->HT[l], M, nullptr, nullptr, nullptr, nullptr, st)) != PP_OK)
+                   s->Z[l], s->H[l], s->HT[l], M, nullptr, nullptr, st)) != PP_OK)
       return rc;
     in = s->H[l];
     ld_in = kHidden;
   }
   if ((rc = gemm(ctx, kEpiLinear, s->H[3], kHidden, wb_ptr(s, 4), kHidden, M, kOutPad, kHidden, 1, bias_ptr(s, 4),
-                 nullptr, nullptr, nullptr, 0, nullptr, s->Y, nullptr, nullptr, st)) != PP_OK)
+                 nullptr, nullptr, nullptr, 0, nullptr, s->Y, st)) != PP_OK)
     return rc;
   // loss and output gradient
   PP_HIP(ctx, launch_zero_f64(s->d_loss, 1, st));
@@ -186,12 +183,12 @@ pp_status forward_backward(pp_surrogate *s, const Rows &r, int64_t count, hipStr
   const int splits = std::max(1, M / 512);
   // output layer
   if ((rc = gemm(ctx, kEpiAccum, s->dYT, M, s->HT[3], M, kOutPad, kHidden, M, splits, nullptr, nullptr, nullptr,
-                 nullptr, 0, nullptr, s->grad + w_offset(4), nullptr, nullptr, st)) != PP_OK)
+                 nullptr, 0, nullptr, s->grad + w_offset(4), st)) != PP_OK)
     return rc;
   PP_HIP(ctx, launch_rowsum(s->dYT, M, kOutPad, M, s->grad + b_offset(4), st));
   // dZ3 = (dY . W4) * gelu'(Z3)
   if ((rc = gemm(ctx, kEpiGeluBwd, s->dY, kOutPad, wt_ptr(s, 4), kOutPad, M, kHidden, kOutPad, 1, nullptr,
-                 nullptr, s->dZ[1], s->dZT, M, s->Z[3], nullptr, nullptr, nullptr, st)) != PP_OK)
+                 nullptr, s->dZ[1], s->dZT, M, s->Z[3], nullptr, st)) != PP_OK)
     return rc;
   int cur = 1;
   for (int l = 3; l >= 0; --l) {
@@ -199,13 +196,13 @@ pp_status forward_backward(pp_surrogate *s, const Rows &r, int64_t count, hipStr
     const uint16_t *prevT = l > 0 ? s->HT[l - 1] : XT;
     const int64_t ld_prevT = l > 0 ? M : r.ld_XT;
     if ((rc = gemm(ctx, kEpiAccum, s->dZT, M, prevT, ld_prevT, kHidden, in_dim(l), M, splits, nullptr, nullptr,
-                   nullptr, nullptr, 0, nullptr, s->grad + w_offset(l), nullptr, nullptr, st)) != PP_OK)
+                   nullptr, nullptr, 0, nullptr, s->grad + w_offset(l), st)) != PP_OK)
       return rc;
     PP_HIP(ctx, launch_rowsum(s->dZT, M, kHidden, M, s->grad + b_offset(l), st));
     if (l == 0) break;
     // dZ_{l-1} = (dZ_l . W_l) * gelu'(Z_{l-1})
     if ((rc = gemm(ctx, kEpiGeluBwd, s->dZ[cur], kHidden, wt_ptr(s, l), kHidden, M, kHidden, kHidden, 1, nullptr,
-                   nullptr, s->dZ[1 - cur], s->dZT, M, s->Z[l - 1], nullptr, nullptr, nullptr, st)) != PP_OK)
+                   nullptr, s->dZ[1 - cur], s->dZT, M, s->Z[l - 1], nullptr, st)) != PP_OK)
       return rc;
     cur = 1 - cur;
   }
@@ -336,55 +333,50 @@ pp_status check_cherenkov(pp_context *ctx, const Batch &b) {
   return PP_OK;
 }
 
-// Runs the network over every pair of batch b in chunks of whole sources;
-// calls sink(mu, first_source, n_sources) after each chunk.
+// Runs the fused network over every pair of batch b: expected hits are added
+// to dom_sums (if not null) and, if pair_sink is given, produced per pair in
+// chunks of whole sources (pair_sink(mu, first_source, n_sources)).
 template <class Sink>
-pp_status infer(pp_surrogate *s, Batch &b, hipStream_t st, Sink sink) {
+pp_status infer(pp_surrogate *s, Batch &b, hipStream_t st, double *dom_sums, Sink *pair_sink) {
   pp_context *ctx = s->ctx;
   using namespace sur;
   const int64_t n_src = static_cast<int64_t>(b.src.size());
-  const int64_t per_chunk = std::max<int64_t>(1, kInferRows / std::max(s->n_doms, 1));
-  const int64_t rows_cap = round64(per_chunk * s->n_doms);
-  pp_status rc;
-  if (rows_cap > s->Icap) {
-    if ((rc = dalloc(ctx, &s->iX, rows_cap * kInPad)) != PP_OK) return rc;
-    if ((rc = dalloc(ctx, &s->iH[0], rows_cap * kHidden)) != PP_OK) return rc;
-    if ((rc = dalloc(ctx, &s->iH[1], rows_cap * kHidden)) != PP_OK) return rc;
-    if ((rc = dalloc(ctx, &s->i_mu, rows_cap)) != PP_OK) return rc;
-    if ((rc = dalloc(ctx, &s->i_mub, rows_cap)) != PP_OK) return rc;
-    if ((rc = dalloc(ctx, &s->i_nph, rows_cap)) != PP_OK) return rc;
-    s->Icap = rows_cap;
-  }
+  pp_status rc = PP_OK;
   const std::vector<float> nph = source_photons(b);
   float *d_src_nph = nullptr;
   if ((rc = dalloc(ctx, &d_src_nph, static_cast<int64_t>(nph.size()))) != PP_OK) return rc;
   if (!nph.empty()) PP_HIP(ctx, hipMemcpy(d_src_nph, nph.data(), sizeof(float) * nph.size(), hipMemcpyHostToDevice));
-  for (int64_t s0 = 0; s0 < n_src; s0 += per_chunk) {
-    const int64_t ns = std::min(per_chunk, n_src - s0);
-    const int64_t pairs = ns * s->n_doms;
-    const int M = static_cast<int>(round64(pairs));
-    FeatureArgs f = feature_args(s, b, d_src_nph);
-    f.first_pair = s0 * s->n_doms;
-    f.n_pairs = pairs;
-    f.X = s->iX;
-    f.mu_base = s->i_mub;
-    f.nph = s->i_nph;
-    PP_HIP(ctx, launch_features(f, st));
-    const uint16_t *in = s->iX;
-    int64_t ld_in = kInPad;
-    for (int l = 0; l < 4; ++l) {
-      uint16_t *out = s->iH[l & 1];
-      if ((rc = gemm(ctx, kEpiGelu, in, ld_in, wb_ptr(s, l), in_dim(l), M, kHidden, in_dim(l), 1, bias_ptr(s, l),
-                     nullptr, out, nullptr, 0, nullptr, nullptr, nullptr, nullptr, st)) != PP_OK)
-        break;
-      in = out;
-      ld_in = kHidden;
+  FusedArgs a{};
+  a.f = feature_args(s, b, d_src_nph);
+  for (int l = 0; l < kLayers; ++l) {
+    a.w[l] = wb_ptr(s, l);
+    a.b[l] = bias_ptr(s, l);
+  }
+  a.dom_sums = dom_sums;
+  // sources per launch: all of them, or as many as the per-pair buffer holds
+  const int64_t per_launch =
+      pair_sink ? std::max<int64_t>(1, kInferRows / std::max(s->n_doms, 1)) : std::max<int64_t>(n_src, 1);
+  if (pair_sink) {
+    const int64_t cap = per_launch * s->n_doms;
+    if (cap > s->Icap) {
+      if ((rc = dalloc(ctx, &s->i_mu, cap)) != PP_OK) {
+        dfree(d_src_nph);
+        return rc;
+      }
+      s->Icap = cap;
     }
-    if (rc != PP_OK) break;
-    if ((rc = gemm(ctx, kEpiMu, in, kHidden, wb_ptr(s, 4), kHidden, M, kOutPad, kHidden, 1, bias_ptr(s, 4),
-                   nullptr, nullptr, nullptr, 0, nullptr, s->i_mu, s->i_nph, s->i_mub, st)) != PP_OK)
+    a.pair_mu = s->i_mu;
+  }
+  for (int64_t s0 = 0; s0 < n_src && rc == PP_OK; s0 += per_launch) {
+    const int64_t ns = std::min(per_launch, n_src - s0);
+    a.f.first_pair = s0 * s->n_doms;
+    a.f.n_pairs = ns * s->n_doms;
+    const hipError_t e = launch_infer_fused(a, st);
+    if (e != hipSuccess) {
+      rc = fail(ctx, PP_EDEVICE, "fused inference launch: %s", hipGetErrorString(e));
       break;
-    if ((rc = sink(s->i_mu, s0, ns)) != PP_OK) break;
+    }
+    if (pair_sink) rc = (*pair_sink)(s->i_mu, s0, ns);
   }
   (void)hipStreamSynchronize(st);
   dfree(d_src_nph);
@@ -446,7 +438,7 @@ void pp_sur_destroy(pp_surrogate *s) {
   dfree(s->k), dfree(s->n_t), dfree(s->s1), dfree(s->s2);
   for (int l = 0; l < 4; ++l) dfree(s->Z[l]), dfree(s->H[l]), dfree(s->HT[l]);
   dfree(s->Y), dfree(s->dY), dfree(s->dYT), dfree(s->dZ[0]), dfree(s->dZ[1]), dfree(s->dZT), dfree(s->d_loss);
-  dfree(s->iX), dfree(s->iH[0]), dfree(s->iH[1]), dfree(s->i_mu), dfree(s->i_mub), dfree(s->i_nph);
+  dfree(s->i_mu);
   dfree(s->gX), dfree(s->gXT);
   for (auto &p : s->g_lab) dfree(p);
   delete s;
@@ -657,10 +649,8 @@ pp_status pp_sur_expected_hits(pp_surrogate *s, uint64_t batch, double *dev_dom_
   if ((st = check_cherenkov(ctx, *b)) != PP_OK) return st;
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
   PP_HIP(ctx, sur::launch_zero_f64(dev_dom_sums, s->n_doms, stream));
-  return infer(s, *b, stream, [&](const float *mu, int64_t, int64_t ns) -> pp_status {
-    PP_HIP(ctx, sur::launch_dom_sums(mu, static_cast<int>(ns), s->n_doms, dev_dom_sums, stream));
-    return PP_OK;
-  });
+  using NoSink = pp_status (*)(const float *, int64_t, int64_t);
+  return infer<NoSink>(s, *b, stream, dev_dom_sums, nullptr);
 }
 
 pp_status pp_sur_predict_pairs(pp_surrogate *s, uint64_t batch, float *out, uint64_t n) {
@@ -672,10 +662,11 @@ pp_status pp_sur_predict_pairs(pp_surrogate *s, uint64_t batch, float *out, uint
   if ((st = find_batch(ctx, batch, &b)) != PP_OK) return st;
   if ((st = check_cherenkov(ctx, *b)) != PP_OK) return st;
   if (n != b->src.size() * static_cast<uint64_t>(s->n_doms)) return fail(ctx, PP_EINVAL, "output size mismatch");
-  return infer(s, *b, nullptr, [&](const float *mu, int64_t s0, int64_t ns) -> pp_status {
+  auto sink = [&](const float *mu, int64_t s0, int64_t ns) -> pp_status {
     PP_HIP(ctx, hipMemcpy(out + s0 * s->n_doms, mu, sizeof(float) * ns * s->n_doms, hipMemcpyDeviceToHost));
     return PP_OK;
-  });
+  };
+  return infer(s, *b, nullptr, nullptr, &sink);
 }
 
 }  // extern "C"

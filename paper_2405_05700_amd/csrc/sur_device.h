@@ -39,7 +39,6 @@ enum Epilogue {
   kEpiGelu = 0,     // z = acc + bias; store z (f32) unless null, gelu(z) as bf16 and its transpose unless null
   kEpiGeluBwd = 1,  // dz = acc * gelu'(z_saved); store bf16 and its transpose
   kEpiAccum = 2,    // out (f32) += acc  (split-K partial sums, atomically)
-  kEpiMu = 3,       // column 0 only: mu = n_photons(row) * mu_base(row) * exp(acc + bias)
   kEpiLinear = 4,   // out (f32, ld N) = acc + bias
 };
 
@@ -57,9 +56,7 @@ struct GemmArgs {
   uint16_t *HT;      // bf16 N x M (ld ldt)
   int64_t ldt;
   const float *Zin;  // saved pre-activation for kEpiGeluBwd (ld N)
-  float *out;        // kEpiAccum: f32 M x N (ld N); kEpiMu: f32 per row
-  const float *row_nph;    // kEpiMu: photons of the row's source
-  const float *row_mubase; // kEpiMu: baseline per row
+  float *out;        // kEpiAccum: f32 M x N (ld N)
 };
 
 struct FeatureArgs {
@@ -119,6 +116,20 @@ hipError_t launch_labels(const pp::DevHit *hits, const unsigned long long *hit_c
                          const int32_t *event_to_source, uint32_t n_events, const pp::DevSource *sources,
                          const float4 *doms, int n_doms, float radius, float time_per_m,
                          float *k, float *n_t, float *s1, float *s2, hipStream_t s);
-hipError_t launch_dom_sums(const float *mu, int n_src, int n_doms, double *dom_sums, hipStream_t s);
+
+// Fused inference over pairs [f.first_pair, f.first_pair + f.n_pairs):
+// features, the five layers and the expected hits, kFusedRows pairs per
+// workgroup of 256 threads with the activations in LDS.
+constexpr int kFusedRows = 128;
+constexpr int kFusedLd = kHidden + 8;  // LDS row stride of the activations (bf16); the pad spreads rows over banks
+struct FusedArgs {
+  FeatureArgs f;                 // the pair set (its output pointers are unused)
+  const uint16_t *w[kLayers];    // bf16 weights, out x in
+  const float *b[kLayers];       // biases
+  double *dom_sums;              // += expected hits per module, may be null
+  float *pair_mu;                // expected hits of pair first_pair + i at i, may be null
+};
+size_t fused_lds_bytes();
+hipError_t launch_infer_fused(const FusedArgs &a, hipStream_t s);
 
 }  // namespace sur

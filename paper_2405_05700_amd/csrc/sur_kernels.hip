@@ -29,10 +29,33 @@ __device__ __forceinline__ bf16x8 load8(const uint16_t *p) {
   return __builtin_bit_cast(bf16x8, v);
 }
 
-// GELU(z) = z * Phi(z) with the exact normal CDF.
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// Standard normal CDF Phi(z) = erfc(-z / sqrt 2) / 2 from the rational
+// approximation of Abramowitz & Stegun 7.1.26: for x >= 0,
+// erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),
+// t = 1 / (1 + p x), absolute error <= 1.5e-7 (far below the bf16 rounding
+// of every stored activation). Also returns e = exp(-z^2 / 2), which the
+// GELU derivative reuses.
+__device__ __forceinline__ float norm_cdf(float z, float &e) {
+  const float x = fabsf(z) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f, x, 1.0f));
+  float q = __builtin_fmaf(t, 1.061405429f, -1.453152027f);
+  q = __builtin_fmaf(t, q, 1.421413741f);
+  q = __builtin_fmaf(t, q, -0.284496736f);
+  q = __builtin_fmaf(t, q, 0.254829592f);
+  e = __builtin_amdgcn_exp2f(z * z * -0.72134752044448170f);  // exp(-z^2 / 2) = 2^(-z^2 log2(e) / 2)
+  const float lower = 0.5f * t * q * e;                       // Phi(-|z|)
+  return z >= 0.0f ? 1.0f - lower : lower;
+}
+
+// GELU(z) = z Phi(z) and its derivative Phi(z) + z phi(z).
+__device__ __forceinline__ float gelu(float z) {
+  float e;
+  return z * norm_cdf(z, e);
+}
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+  float e;
+  const float cdf = norm_cdf(z, e);
+  return __builtin_fmaf(z * e, 0.39894228040143268f, cdf);
 }
 
 // Digamma for x > 0: recurrence psi(x) = psi(x + 1) - 1/x up to x >= 6, then
@@ -111,15 +134,6 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
       const float b = g.bias[col];
 #pragma unroll
       for (int r = 0; r < 4; ++r) g.out[(int64_t)(rbase + r) * g.N + col] = v[r] + b;
-    } else {  // kEpiMu
-      if (col == 0) {
-        const float b = g.bias[0];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = rbase + r;
-          g.out[row] = g.row_nph[row] * g.row_mubase[row] * expf(v[r] + b);
-        }
-      }
     }
   }
 }
@@ -129,53 +143,59 @@ __device__ __forceinline__ int layer_of(float z, float z_lo, float inv_dz, int n
   return f >= 0.0f ? (f >= (float)(n_layers - 1) ? n_layers - 1 : (int)f) : 0;
 }
 
-// Features of (source, module) pairs, source-major: pair p is source
-// p / n_doms and module p % n_doms. Rows past n_pairs (padding) are zero.
+// Features of pair p of the set (source-major: source p / n_doms, module
+// p % n_doms) and its diffusion baseline.
+__device__ __forceinline__ void pair_features(const FeatureArgs &f, int64_t p, float x[kInReal],
+                                              float &mu_base, float &nph, float &R, int &dom) {
+  const int i = (int)(p / f.n_doms), j = (int)(p % f.n_doms);
+  const pp::DevSource &S = f.sources[i];
+  const float4 m = f.doms[j];
+  const float half = 0.5f * S.dir_len.w;
+  const float cx = S.pos_t0.x + half * S.dir_len.x, cy = S.pos_t0.y + half * S.dir_len.y;
+  const float cz = S.pos_t0.z + half * S.dir_len.z;
+  const float dx = m.x - cx, dy = m.y - cy, dz = m.z - cz;
+  R = fmaxf(sqrtf(dx * dx + dy * dy + dz * dz), 0.5f);
+  const float ux = dx / R, uy = dy / R, uz = dz / R;
+  const float cos_eta = ux * S.dir_len.x + uy * S.dir_len.y + uz * S.dir_len.z;
+  const pp::DevLayer Ls = f.layers[layer_of(cz, f.z_lo, f.inv_dz, f.n_layers)];
+  const pp::DevLayer Ld = f.layers[layer_of(m.z, f.z_lo, f.inv_dz, f.n_layers)];
+  x[0] = ux;
+  x[1] = uy;
+  x[2] = uz;
+  x[3] = R / 100.0f;
+  x[4] = logf(R / 10.0f) / 3.0f;
+  x[5] = cos_eta;
+  x[6] = cos_eta - 0.75470958022277199f;  // cos 41 deg
+  x[7] = S.dir_len.x;
+  x[8] = S.dir_len.y;
+  x[9] = S.dir_len.z;
+  x[10] = cz / 500.0f;
+  x[11] = m.z / 500.0f;
+  x[12] = 100.0f * Ls.coef.x;
+  x[13] = 10.0f * Ls.coef.y;
+  x[14] = 100.0f * Ld.coef.x;
+  x[15] = 10.0f * Ld.coef.y;
+  // diffusion baseline with the two layers' mean absorption and
+  // effective scattering lengths (lambda_e = (1/b) / (1 - g))
+  const float lam_a = 0.5f * (Ls.coef.z + Ld.coef.z);
+  const float lam_e = 0.5f * (Ls.coef.w / Ls.hg.x + Ld.coef.w / Ld.hg.x);
+  const float D = lam_e / 3.0f;
+  const float dl = sqrtf(D * lam_a);
+  mu_base = f.radius * f.radius * expf(-R / dl) / (4.0f * D * R);
+  nph = f.src_nph[i];
+  dom = j;
+}
+
+// Feature rows of pairs [first_pair, first_pair + n_pairs); rows past
+// n_pairs (padding) are zero.
 __global__ void k_features(const FeatureArgs f, int64_t n_rows) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n_rows) return;
   float x[kInReal];
   for (int q = 0; q < kInReal; ++q) x[q] = 0.0f;
   float mu_base = 0.0f, nph = 0.0f, R = 0.0f;
-  if (t < f.n_pairs) {
-    const int64_t p = f.first_pair + t;
-    const int i = (int)(p / f.n_doms), j = (int)(p % f.n_doms);
-    const pp::DevSource &S = f.sources[i];
-    const float4 m = f.doms[j];
-    const float half = 0.5f * S.dir_len.w;
-    const float cx = S.pos_t0.x + half * S.dir_len.x, cy = S.pos_t0.y + half * S.dir_len.y;
-    const float cz = S.pos_t0.z + half * S.dir_len.z;
-    const float dx = m.x - cx, dy = m.y - cy, dz = m.z - cz;
-    R = fmaxf(sqrtf(dx * dx + dy * dy + dz * dz), 0.5f);
-    const float ux = dx / R, uy = dy / R, uz = dz / R;
-    const float cos_eta = ux * S.dir_len.x + uy * S.dir_len.y + uz * S.dir_len.z;
-    const pp::DevLayer Ls = f.layers[layer_of(cz, f.z_lo, f.inv_dz, f.n_layers)];
-    const pp::DevLayer Ld = f.layers[layer_of(m.z, f.z_lo, f.inv_dz, f.n_layers)];
-    x[0] = ux;
-    x[1] = uy;
-    x[2] = uz;
-    x[3] = R / 100.0f;
-    x[4] = logf(R / 10.0f) / 3.0f;
-    x[5] = cos_eta;
-    x[6] = cos_eta - 0.75470958022277199f;  // cos 41 deg
-    x[7] = S.dir_len.x;
-    x[8] = S.dir_len.y;
-    x[9] = S.dir_len.z;
-    x[10] = cz / 500.0f;
-    x[11] = m.z / 500.0f;
-    x[12] = 100.0f * Ls.coef.x;
-    x[13] = 10.0f * Ls.coef.y;
-    x[14] = 100.0f * Ld.coef.x;
-    x[15] = 10.0f * Ld.coef.y;
-    // diffusion baseline with the two layers' mean absorption and
-    // effective scattering lengths (lambda_e = (1/b) / (1 - g))
-    const float lam_a = 0.5f * (Ls.coef.z + Ld.coef.z);
-    const float lam_e = 0.5f * (Ls.coef.w / Ls.hg.x + Ld.coef.w / Ld.hg.x);
-    const float D = lam_e / 3.0f;
-    const float dl = sqrtf(D * lam_a);
-    mu_base = f.radius * f.radius * expf(-R / dl) / (4.0f * D * R);
-    nph = f.src_nph[i];
-  }
+  int dom = 0;
+  if (t < f.n_pairs) pair_features(f, f.first_pair + t, x, mu_base, nph, R, dom);
   uint16_t *row = f.X + t * kInPad;
   for (int q = 0; q < kInPad; ++q) row[q] = q < kInReal ? f2bf(x[q]) : 0;
   if (f.XT)
@@ -318,13 +338,128 @@ __global__ void k_labels(const pp::DevHit *hits, const unsigned long long *hit_c
   }
 }
 
-// dom_sums[j] += sum_i mu[i * n_doms + j] (one thread per module).
-__global__ void k_dom_sums(const float *mu, int n_src, int n_doms, double *dom_sums) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_doms) return;
-  double s = 0.0;
-  for (int i = 0; i < n_src; ++i) s += (double)mu[(int64_t)i * n_doms + j];
-  dom_sums[j] += s;
+// ---------------------------------------------------------------------------
+// Fused inference. A workgroup of four wavefronts owns kFusedRows = 128 pairs:
+// it computes their features into LDS, then runs every layer as
+// H_out^T = W H_in^T on the matrix cores (W from L2 as the A operand, the
+// activations from LDS as the B operand), so a lane's accumulator holds four
+// consecutive output features of one pair and is written back to the pair's
+// LDS row as one 8-byte store. Wavefront w computes features 64 w .. + 64 of
+// all 128 pairs: 4 x 8 tiles of 16 x 16. Layers overwrite their input in
+// place, so a barrier separates the reads of a layer from its writes. The
+// 68 KB of LDS per workgroup let two workgroups share a CU, so one runs its
+// matrix products while the other runs its GELU epilogue. The last layer's
+// first output gives the expected hits, which go to the per-module sums with
+// one atomic per pair.
+
+__device__ __forceinline__ bf16x8 lds_load8(const uint16_t *p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(p));
+}
+
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  const f32x2 v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));  // v_cvt_pk_bf16_f32, round to nearest even
+}
+
+template <int K, int LDW>
+__device__ __forceinline__ void fused_hidden_layer(uint16_t *lds_h, const uint16_t *__restrict__ w,
+                                                   const float *__restrict__ bias, int lane, int wave) {
+  const int fg = wave;
+  const int l16 = lane & 15, kq = (lane >> 4) * 8;
+  const uint16_t *wrow = w + (int64_t)(fg * 64 + l16) * LDW + kq;
+  const uint16_t *hrow = lds_h + l16 * kFusedLd + kq;
+  f32x4 acc[4][8];
+#pragma unroll
+  for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+    for (int pt = 0; pt < 8; ++pt) acc[ft][pt] = f32x4{0, 0, 0, 0};
+#pragma unroll 2  // two K steps in flight fit the 256-register budget of 2 waves per SIMD without spills
+  for (int k = 0; k < K; k += 32) {
+    bf16x8 wa[4], hb[8];
+#pragma unroll
+    for (int ft = 0; ft < 4; ++ft) wa[ft] = load8(wrow + ft * 16 * LDW + k);
+#pragma unroll
+    for (int pt = 0; pt < 8; ++pt) hb[pt] = lds_load8(hrow + pt * 16 * kFusedLd + k);
+#pragma unroll
+    for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+      for (int pt = 0; pt < 8; ++pt)
+        acc[ft][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[ft], hb[pt], acc[ft][pt], 0, 0, 0);
+  }
+  __syncthreads();  // every wavefront has read the layer's input
+#pragma unroll
+  for (int ft = 0; ft < 4; ++ft) {
+    const int f0 = fg * 64 + ft * 16 + 4 * (lane >> 4);
+    const float b0 = bias[f0], b1 = bias[f0 + 1], b2 = bias[f0 + 2], b3 = bias[f0 + 3];
+#pragma unroll
+    for (int pt = 0; pt < 8; ++pt) {
+      const f32x4 v = acc[ft][pt];
+      const uint2 h = make_uint2(pack_bf16(gelu(v[0] + b0), gelu(v[1] + b1)),
+                                 pack_bf16(gelu(v[2] + b2), gelu(v[3] + b3)));
+      *reinterpret_cast<uint2 *>(lds_h + (pt * 16 + l16) * kFusedLd + f0) = h;
+    }
+  }
+  __syncthreads();  // the layer's output is complete
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_infer_fused(const FusedArgs a) {
+  extern __shared__ __align__(16) uint16_t lds_h[];  // kFusedRows x kFusedLd bf16, then scale and module id
+  float *s_scale = reinterpret_cast<float *>(lds_h + kFusedRows * kFusedLd);
+  int *s_dom = reinterpret_cast<int *>(s_scale + kFusedRows);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t q0 = (int64_t)blockIdx.x * kFusedRows;
+
+  // features: one pair per thread of the first half; input columns 16..31 are zero
+  if (tid < kFusedRows) {
+    float x[kInReal];
+#pragma unroll
+    for (int q = 0; q < kInReal; ++q) x[q] = 0.0f;
+    float mub = 0.0f, nph = 0.0f, R = 0.0f;
+    int dom = -1;
+    if (q0 + tid < a.f.n_pairs) pair_features(a.f, a.f.first_pair + q0 + tid, x, mub, nph, R, dom);
+    uint4 *row = reinterpret_cast<uint4 *>(lds_h + tid * kFusedLd);
+    row[0] = make_uint4(pack_bf16(x[0], x[1]), pack_bf16(x[2], x[3]), pack_bf16(x[4], x[5]), pack_bf16(x[6], x[7]));
+    row[1] = make_uint4(pack_bf16(x[8], x[9]), pack_bf16(x[10], x[11]), pack_bf16(x[12], x[13]),
+                        pack_bf16(x[14], x[15]));
+    row[2] = make_uint4(0, 0, 0, 0);
+    row[3] = make_uint4(0, 0, 0, 0);
+    s_scale[tid] = nph * mub;
+    s_dom[tid] = dom;
+  }
+  __syncthreads();
+
+  fused_hidden_layer<32, kInPad>(lds_h, a.w[0], a.b[0], lane, wave);  // 16 real inputs: one K step of 32
+  fused_hidden_layer<kHidden, kHidden>(lds_h, a.w[1], a.b[1], lane, wave);
+  fused_hidden_layer<kHidden, kHidden>(lds_h, a.w[2], a.b[2], lane, wave);
+  fused_hidden_layer<kHidden, kHidden>(lds_h, a.w[3], a.b[3], lane, wave);
+
+  // output layer, first output only: W4 rows 0..15 against pair tiles 2w and 2w + 1
+  const int l16 = lane & 15, kq = (lane >> 4) * 8;
+  const uint16_t *wrow = a.w[4] + (int64_t)l16 * kHidden + kq;
+  const uint16_t *h0 = lds_h + (2 * wave * 16 + l16) * kFusedLd + kq;
+  const uint16_t *h1 = h0 + 16 * kFusedLd;
+  f32x4 o0 = {0, 0, 0, 0}, o1 = o0;
+#pragma unroll
+  for (int k = 0; k < kHidden; k += 32) {
+    const bf16x8 wa = load8(wrow + k);
+    o0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, lds_load8(h0 + k), o0, 0, 0, 0);
+    o1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, lds_load8(h1 + k), o1, 0, 0, 0);
+  }
+  if (lane < 16) {  // row 0 of the output tile (feature 0) lives in lanes 0..15, element 0
+    const float b = a.b[4][0];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int pr = (2 * wave + j) * 16 + lane;
+      const int d = s_dom[pr];
+      if (d >= 0) {
+        const float mu = s_scale[pr] * expf((j ? o1[0] : o0[0]) + b);
+        if (a.dom_sums) atomicAdd(&a.dom_sums[d], (double)mu);
+        if (a.pair_mu) a.pair_mu[q0 + pr] = mu;
+      }
+    }
+  }
 }
 
 int blocks_for(int64_t n, int threads) { return (int)((n + threads - 1) / threads); }
@@ -338,8 +473,20 @@ hipError_t launch_gemm(int epi, const GemmArgs &g, int splits, hipStream_t s) {
     case kEpiGeluBwd: hipLaunchKernelGGL(k_gemm<kEpiGeluBwd>, grid, dim3(256), 0, s, g); break;
     case kEpiAccum: hipLaunchKernelGGL(k_gemm<kEpiAccum>, grid, dim3(256), 0, s, g); break;
     case kEpiLinear: hipLaunchKernelGGL(k_gemm<kEpiLinear>, grid, dim3(256), 0, s, g); break;
-    default: hipLaunchKernelGGL(k_gemm<kEpiMu>, grid, dim3(256), 0, s, g); break;
   }
+  return hipGetLastError();
+}
+
+size_t fused_lds_bytes() { return sizeof(uint16_t) * kFusedRows * kFusedLd + 2 * sizeof(float) * kFusedRows; }
+
+hipError_t launch_infer_fused(const FusedArgs &a, hipStream_t s) {
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_infer_fused),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     static_cast<int>(fused_lds_bytes()));
+  if (attr != hipSuccess) return attr;
+  if (a.f.n_pairs <= 0) return hipSuccess;
+  const int64_t blocks = (a.f.n_pairs + kFusedRows - 1) / kFusedRows;
+  hipLaunchKernelGGL(k_infer_fused, dim3(static_cast<uint32_t>(blocks)), dim3(256), fused_lds_bytes(), s, a);
   return hipGetLastError();
 }
 
@@ -424,9 +571,5 @@ hipError_t launch_labels(const pp::DevHit *hits, const unsigned long long *hit_c
   return hipGetLastError();
 }
 
-hipError_t launch_dom_sums(const float *mu, int n_src, int n_doms, double *dom_sums, hipStream_t s) {
-  hipLaunchKernelGGL(k_dom_sums, dim3(blocks_for(n_doms, 256)), dim3(256), 0, s, mu, n_src, n_doms, dom_sums);
-  return hipGetLastError();
-}
 
 }  // namespace sur

@@ -156,6 +156,27 @@ def test_forward_and_gradients_match_oracle(mods, small_set):
             assert err < 0.06 and cos > 0.998, (li, part, err, cos)
 
 
+def test_fused_expected_hits_equal_pair_sums(mods):
+    """The fused inference kernel adds every pair's expectation to its
+    module's sum: 37 sources x 5160 modules is 746 full tiles of 256 pairs
+    and a ragged last one."""
+    pp, surrogate, M = mods
+    import torch
+    w = W.full_detector(n_sources=37, photons_per_source=1000, seed=31)
+    ctx = pp.Context(0, seed=0)
+    ctx.load_workload(w)
+    b = ctx.submit(w.sources)
+    sur = surrogate.Surrogate(ctx, seed=6)
+    per_pair = sur.predict_pairs(b, len(w.sources)).astype(np.float64)
+    sums = sur.expected_hits(b).cpu().numpy()
+    torch.cuda.synchronize()
+    assert (37 * len(w.doms)) % 256 != 0
+    ref = per_pair.sum(0)
+    say("fused sums vs pair sums: max rel", np.max(np.abs(sums - ref) / np.maximum(ref, 1e-300)))
+    assert np.allclose(sums, ref, rtol=1e-6, atol=1e-300)
+    assert np.isfinite(per_pair).all() and (per_pair >= 0).all()
+
+
 def test_adam_step_matches_definition(mods, small_set):
     pp, surrogate, M = mods
     w, ctx, b, sur = small_set
@@ -206,7 +227,7 @@ def test_training_beats_the_untrained_baseline(mods):
     sur.set_params(zero)
     l_tr0, _ = sur.loss_grad(0, n_tr)
     sur.set_params(init)
-    losses = sur.train(epochs=6, batch_size=4096, lr=2e-3)
+    losses = sur.train(epochs=12, batch_size=4096, lr=2e-3, lr_final=2e-5)
     say("epoch losses", losses)
     l_tr1, _ = sur.loss_grad(0, n_tr)
     say("training-set loss before", l_tr0, "after", l_tr1)
