@@ -36,10 +36,10 @@ FLOPS_PER_STEP = 90         # FP32 FLOPs of a step (FMA = 2), for the FLOP form
 # Peak: MI355X FP32 vector 157.3 TFLOP/s = 256 CUs x 128 FP32 lanes/clock x
 # 2 FLOP per FMA x 2.4 GHz, i.e. 78.65e12 full-rate lane slots/s.
 PEAK_FP32_FLOPS = 157.3e12
-# Surrogate inference: a (segment, module) pair needs 2 (16*256 + 3*256*256 +
-# 256*1) FLOPs (16 real inputs, three hidden 256 x 256 layers, one output
+# Surrogate inference: a (segment, module) pair needs 2 (21*256 + 3*256*256 +
+# 256*1) FLOPs (21 real inputs, three hidden 256 x 256 layers, one output
 # used), against the dense BF16 matrix-core peak of 2.5 PFLOP/s.
-INFER_FLOP_PER_PAIR = 2 * (16 * 256 + 3 * 256 * 256 + 256)
+INFER_FLOP_PER_PAIR = 2 * (21 * 256 + 3 * 256 * 256 + 256)
 PEAK_BF16_FLOPS = 2.5e15
 PEAK_SLOTS = PEAK_FP32_FLOPS / 2
 

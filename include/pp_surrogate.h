@@ -11,8 +11,9 @@
  * evaluation instead of many propagated photons. The Monte Carlo stays the
  * judge of its error and the fallback where the error check fails.
  *
- * Model (fixed shape): features of a (source, module) pair -> five affine
- * layers 64 -> 256 -> 256 -> 256 -> 256 -> 64 with GELU between them; BF16
+ * Model (fixed shape): 21 features of a (source, module) pair, padded to
+ * 64 -> five affine layers 64 -> 256 -> 256 -> 256 -> 256 -> 64 with GELU
+ * between them; BF16
  * weights and activations, FP32 accumulation on the matrix cores, FP32
  * master weights and Adam state. Output 0 is log(mu / mu_base), where
  * mu_base is a diffusion estimate of the hit probability per photon;
@@ -61,9 +62,15 @@ pp_status pp_sur_set_training_set(pp_surrogate *sur, uint64_t batch);
 /* Number of pairs in the training set. */
 pp_status pp_sur_training_size(const pp_surrogate *sur, uint64_t *n_pairs);
 
-/* Copies training-set rows [first, first + count) to host memory: 16
- * features per row, mu_base, and labels (k, n_t, sum of delays, sum of log
- * delays). Any output pointer may be NULL. */
+/* Number of real input features per (segment, module) pair (21): the pair
+ * geometry up to a rotation about the vertical, the segment's extent, and
+ * the optics of the layers at the segment centre and at the module. */
+uint32_t pp_sur_feature_count(void);
+
+/* Copies training-set rows [first, first + count) to host memory:
+ * pp_sur_feature_count() features per row (bf16 values widened to float),
+ * mu_base, and labels (k, n_t, sum of delays, sum of log delays). Any output
+ * pointer may be NULL. */
 pp_status pp_sur_get_training_rows(pp_surrogate *sur, uint64_t first, uint64_t count, float *features,
                                    float *mu_base, float *k, float *n_t, float *s1, float *s2);
 

@@ -2,12 +2,13 @@
 
 The surrogate predicts, for a light source and an optical module, the
 expected number of hits per emitted photon and gamma parameters of the hit
-delay. It is a multilayer perceptron: five affine layers (16 features + 48 zero columns)
+delay. It is a multilayer perceptron: five affine layers (21 features + 43 zero columns)
 -> 256 -> 256 -> 256 -> 256 -> 64, three outputs used) with GELU between
 them (GELU(z) = z Phi(z), Phi the standard normal CDF). Everything here is
 the plain definition, in float64:
 
-* features: geometry of the (source, module) pair and the optical
+* features: geometry of the (source, module) pair up to a rotation about
+  the vertical (the ice is layered in depth only) and the optical
   properties of the layers holding the source centre and the module;
 * baseline: the diffusion estimate of the hit probability,
   mu_base = r^2 exp(-R/delta) / (4 D R), D = lambda_e/3,
@@ -32,7 +33,8 @@ import numpy as np
 from scipy import special
 
 C_LIGHT = 0.299792458
-IN_REAL, IN_PAD, HIDDEN, OUT_PAD, OUT_REAL = 16, 64, 256, 64, 3
+IN_REAL, IN_PAD, HIDDEN, OUT_PAD, OUT_REAL = 21, 64, 256, 64, 3
+TAN_CHERENKOV = math.tan(math.radians(41.0))
 LAYER_SHAPES = [(HIDDEN, IN_PAD), (HIDDEN, HIDDEN), (HIDDEN, HIDDEN), (HIDDEN, HIDDEN),
                 (OUT_PAD, HIDDEN)]  # (out, in): weight matrices are out x in
 TAU0_NS = 50.0
@@ -78,19 +80,44 @@ def pair_features(w, src_idx, dom_idx):
     a_s, a_d = a_all[ls], a_all[ld]
     b_s = 1.0 / (le_all[ls] * (1.0 - g_all[ls]))
     b_d = 1.0 / (le_all[ld] * (1.0 - g_all[ld]))
+    # Geometry up to a rotation about the vertical (the ice is layered in
+    # depth only): vertical parts of the two unit vectors, horizontal and
+    # vertical offsets, distance, the angle to the track and the relative
+    # azimuth of the two horizontal projections.
+    rho = np.hypot(delta[:, 0], delta[:, 1])
+    h = dirv[:, 0] * u[:, 0] + dirv[:, 1] * u[:, 1]        # horizontal part of cos(eta)
+    hh = np.sqrt((dirv[:, 0] ** 2 + dirv[:, 1] ** 2) * (u[:, 0] ** 2 + u[:, 1] ** 2))
     X = np.zeros((len(R), IN_PAD))
-    X[:, 0:3] = u
+    X[:, 0] = u[:, 2]
+    X[:, 1] = rho / 100.0
+    X[:, 2] = delta[:, 2] / 100.0
     X[:, 3] = R / 100.0
     X[:, 4] = np.log(R / 10.0) / 3.0
     X[:, 5] = cos_eta
     X[:, 6] = cos_eta - math.cos(math.radians(41.0))
-    X[:, 7:10] = dirv
+    X[:, 7] = dirv[:, 2]
+    X[:, 8] = h
+    X[:, 9] = np.where(hh > 1e-9, np.clip(h / np.maximum(hh, 1e-9), -1.0, 1.0), 0.0)  # cos(relative azimuth)
     X[:, 10] = c[:, 2] / 500.0
     X[:, 11] = m[:, 2] / 500.0
     X[:, 12] = 100.0 * a_s
     X[:, 13] = 10.0 * b_s
     X[:, 14] = 100.0 * a_d
     X[:, 15] = 10.0 * b_d
+    # The segment's extent: impact parameter of the track line, along-track
+    # offset of the closest approach from the centre, where on the segment
+    # (in lengths, capped to [-1, 2]) direct Cherenkov light at 41 degrees
+    # would leave for the module, and the distances to both ends.
+    L = np.maximum(s["length_m"].astype(np.float64), 1e-3)
+    p0 = np.stack([s["x"], s["y"], s["z"]], 1).astype(np.float64)
+    v = m - p0
+    along = (v * dirv).sum(1)
+    b = np.linalg.norm(v - along[:, None] * dirv, axis=1)
+    X[:, 16] = b / 100.0
+    X[:, 17] = (along - 0.5 * L) / 100.0
+    X[:, 18] = np.clip((along - b / TAN_CHERENKOV) / L, -1.0, 2.0)
+    X[:, 19] = np.linalg.norm(v, axis=1) / 100.0
+    X[:, 20] = np.linalg.norm(v - L[:, None] * dirv, axis=1) / 100.0
     # diffusion baseline with the two layers' mean lengths
     lam_a = 0.5 * (1.0 / a_s + 1.0 / a_d)
     lam_e = 0.5 * (le_all[ls] + le_all[ld])

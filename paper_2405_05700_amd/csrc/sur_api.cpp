@@ -389,6 +389,8 @@ extern "C" {
 
 uint64_t pp_sur_param_count(void) { return static_cast<uint64_t>(sur::param_count()); }
 
+uint32_t pp_sur_feature_count(void) { return static_cast<uint32_t>(sur::kInReal); }
+
 pp_status pp_sur_create(pp_context *ctx, uint64_t init_seed, pp_surrogate **out) {
   if (!ctx || !out) return PP_EINVAL;
   *out = nullptr;

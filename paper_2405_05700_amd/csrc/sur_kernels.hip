@@ -159,22 +159,42 @@ __device__ __forceinline__ void pair_features(const FeatureArgs &f, int64_t p, f
   const float cos_eta = ux * S.dir_len.x + uy * S.dir_len.y + uz * S.dir_len.z;
   const pp::DevLayer Ls = f.layers[layer_of(cz, f.z_lo, f.inv_dz, f.n_layers)];
   const pp::DevLayer Ld = f.layers[layer_of(m.z, f.z_lo, f.inv_dz, f.n_layers)];
-  x[0] = ux;
-  x[1] = uy;
-  x[2] = uz;
+  // Geometry up to a rotation about the vertical (the ice is layered in
+  // depth only): vertical parts, horizontal and vertical offsets, distance,
+  // angle to the track and the relative azimuth of the horizontal parts.
+  const float h = S.dir_len.x * ux + S.dir_len.y * uy;
+  const float hh = sqrtf((S.dir_len.x * S.dir_len.x + S.dir_len.y * S.dir_len.y) * (ux * ux + uy * uy));
+  x[0] = uz;
+  x[1] = sqrtf(dx * dx + dy * dy) / 100.0f;
+  x[2] = dz / 100.0f;
   x[3] = R / 100.0f;
   x[4] = logf(R / 10.0f) / 3.0f;
   x[5] = cos_eta;
   x[6] = cos_eta - 0.75470958022277199f;  // cos 41 deg
-  x[7] = S.dir_len.x;
-  x[8] = S.dir_len.y;
-  x[9] = S.dir_len.z;
+  x[7] = S.dir_len.z;
+  x[8] = h;
+  x[9] = hh > 1e-9f ? fminf(fmaxf(h / hh, -1.0f), 1.0f) : 0.0f;
   x[10] = cz / 500.0f;
   x[11] = m.z / 500.0f;
   x[12] = 100.0f * Ls.coef.x;
   x[13] = 10.0f * Ls.coef.y;
   x[14] = 100.0f * Ld.coef.x;
   x[15] = 10.0f * Ld.coef.y;
+  // The segment's extent: impact parameter of the track line, along-track
+  // offset of the closest approach from the centre, where on the segment (in
+  // lengths, capped to [-1, 2]) direct Cherenkov light at 41 degrees would
+  // leave for the module, and the distances to both ends.
+  const float L = fmaxf(S.dir_len.w, 1e-3f);
+  const float vx = m.x - S.pos_t0.x, vy = m.y - S.pos_t0.y, vz = m.z - S.pos_t0.z;
+  const float along = vx * S.dir_len.x + vy * S.dir_len.y + vz * S.dir_len.z;
+  const float px = vx - along * S.dir_len.x, py = vy - along * S.dir_len.y, pz = vz - along * S.dir_len.z;
+  const float bimp = sqrtf(px * px + py * py + pz * pz);
+  const float ex = vx - L * S.dir_len.x, ey = vy - L * S.dir_len.y, ez = vz - L * S.dir_len.z;
+  x[16] = bimp / 100.0f;
+  x[17] = (along - 0.5f * L) / 100.0f;
+  x[18] = fminf(fmaxf((along - bimp / kTanCherenkov) / L, -1.0f), 2.0f);
+  x[19] = sqrtf(vx * vx + vy * vy + vz * vz) / 100.0f;
+  x[20] = sqrtf(ex * ex + ey * ey + ez * ez) / 100.0f;
   // diffusion baseline with the two layers' mean absorption and
   // effective scattering lengths (lambda_e = (1/b) / (1 - g))
   const float lam_a = 0.5f * (Ls.coef.z + Ld.coef.z);
@@ -411,7 +431,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t q0 = (int64_t)blockIdx.x * kFusedRows;
 
-  // features: one pair per thread of the first half; input columns 16..31 are zero
+  // features: one pair per thread of the first half; input columns kInReal..31 are zero
   if (tid < kFusedRows) {
     float x[kInReal];
 #pragma unroll
@@ -419,18 +439,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     float mub = 0.0f, nph = 0.0f, R = 0.0f;
     int dom = -1;
     if (q0 + tid < a.f.n_pairs) pair_features(a.f, a.f.first_pair + q0 + tid, x, mub, nph, R, dom);
+    static_assert(kInReal <= 32, "the first layer reads one K step of 32 inputs");
+    uint32_t w[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      w[q] = pack_bf16(2 * q < kInReal ? x[2 * q] : 0.0f, 2 * q + 1 < kInReal ? x[2 * q + 1] : 0.0f);
     uint4 *row = reinterpret_cast<uint4 *>(lds_h + tid * kFusedLd);
-    row[0] = make_uint4(pack_bf16(x[0], x[1]), pack_bf16(x[2], x[3]), pack_bf16(x[4], x[5]), pack_bf16(x[6], x[7]));
-    row[1] = make_uint4(pack_bf16(x[8], x[9]), pack_bf16(x[10], x[11]), pack_bf16(x[12], x[13]),
-                        pack_bf16(x[14], x[15]));
-    row[2] = make_uint4(0, 0, 0, 0);
-    row[3] = make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) row[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
     s_scale[tid] = nph * mub;
     s_dom[tid] = dom;
   }
   __syncthreads();
 
-  fused_hidden_layer<32, kInPad>(lds_h, a.w[0], a.b[0], lane, wave);  // 16 real inputs: one K step of 32
+  fused_hidden_layer<32, kInPad>(lds_h, a.w[0], a.b[0], lane, wave);  // kInReal real inputs: one K step of 32
   fused_hidden_layer<kHidden, kHidden>(lds_h, a.w[1], a.b[1], lane, wave);
   fused_hidden_layer<kHidden, kHidden>(lds_h, a.w[2], a.b[2], lane, wave);
   fused_hidden_layer<kHidden, kHidden>(lds_h, a.w[3], a.b[3], lane, wave);

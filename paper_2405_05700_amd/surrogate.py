@@ -22,6 +22,7 @@ SIGNATURES = {
     "pp_sur_get_training_rows": (C.c_int, [_vp, _u64, _u64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pp_sur_loss_grad": (C.c_int, [_vp, _u64, _u64, C.POINTER(C.c_double), _vp]),
     "pp_sur_train_step": (C.c_int, [_vp, _u64, _u64, C.c_float, C.POINTER(C.c_double)]),
+    "pp_sur_feature_count": (C.c_uint32, []),
     "pp_sur_train": (C.c_int, [_vp, _u32, _u32, C.c_float, C.c_float, _vp, _vp]),
     "pp_sur_expected_hits": (C.c_int, [_vp, _u64, _vp, _vp]),
     "pp_sur_predict_pairs": (C.c_int, [_vp, _u64, _vp, _u64]),
@@ -84,7 +85,7 @@ class Surrogate:
         return n.value
 
     def training_rows(self, first: int, count: int) -> dict:
-        out = {"features": np.empty((count, 16), np.float32)}
+        out = {"features": np.empty((count, _lib.pp_sur_feature_count()), np.float32)}
         for k in ("mu_base", "k", "n_t", "s1", "s2"):
             out[k] = np.empty(count, np.float32)
         self._check(_lib.pp_sur_get_training_rows(

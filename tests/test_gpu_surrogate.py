@@ -76,11 +76,12 @@ def test_features_and_labels(mods, small_set):
     P = sur.training_size()
     assert P == 4 * n_dom
     rows = sur.training_rows(0, P)
+    assert rows["features"].shape[1] == M.IN_REAL
     src = np.repeat(np.arange(4), n_dom)
     dom = np.tile(np.arange(n_dom), 4)
     X, mub, R = M.pair_features(w, src, dom)
-    diff = np.abs(rows["features"] - X[:, :16])
-    ok = (diff <= 0.008 * np.abs(X[:, :16]) + 2e-3).all(1)
+    diff = np.abs(rows["features"] - X[:, :M.IN_REAL])
+    ok = (diff <= 0.008 * np.abs(X[:, :M.IN_REAL]) + 2e-3).all(1)
     say("feature rows within bf16 tolerance", ok.mean())
     assert ok.mean() >= 0.999
     assert np.allclose(rows["mu_base"], mub, rtol=2e-3, atol=1e-30)
@@ -106,7 +107,7 @@ def test_features_and_labels(mods, small_set):
 
 def oracle_on_gpu_inputs(M, rows, theta, first, count):
     X = np.zeros((count, M.IN_PAD))
-    X[:, :16] = rows["features"][first:first + count]
+    X[:, :M.IN_REAL] = rows["features"][first:first + count]
     params = unflatten(M, theta)
     for p in params:
         p[0] = bf16_round(p[0])

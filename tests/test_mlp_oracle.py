@@ -2,6 +2,7 @@
 derivative is checked against central finite differences of the function it
 differentiates, Adam against its closed form for a constant gradient, and
 the features against their geometric meaning."""
+import dataclasses
 import math
 
 import numpy as np
@@ -116,22 +117,63 @@ def test_features_geometry():
     src = np.repeat(np.arange(3), len(w.doms))
     dom = np.tile(np.arange(len(w.doms)), 3)
     X, mub, R = M.pair_features(w, src, dom)
-    u = X[:, 0:3]
-    assert np.allclose(np.linalg.norm(u, axis=1), 1.0, atol=1e-12)
     assert np.allclose(X[:, 3] * 100.0, R) and (R >= 0.5).all()
-    assert (np.abs(X[:, 5]) <= 1 + 1e-12).all()
+    assert (np.abs(X[:, 5]) <= 1 + 1e-12).all() and (np.abs(X[:, 9]) <= 1).all()
     assert np.allclose(X[:, 6], X[:, 5] - math.cos(math.radians(41.0)))
     assert (X[:, M.IN_REAL:] == 0).all()
-    # module positions recovered from the source centre and the offset
+    # offsets recovered directly from the source centre and the module
     s = w.sources
     d = np.stack([s["dx"], s["dy"], s["dz"]], 1).astype(float)
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     c = np.stack([s["x"], s["y"], s["z"]], 1).astype(float) + 5.0 * d
     m = np.stack([w.doms["x"], w.doms["y"], w.doms["z"]], 1).astype(float)
-    rec = c[src] + R[:, None] * u
-    assert np.allclose(rec, m[dom], atol=1e-9)
+    off = m[dom] - c[src]
+    assert np.allclose(X[:, 1] * 100.0, np.hypot(off[:, 0], off[:, 1]), atol=1e-9)
+    assert np.allclose(X[:, 2] * 100.0, off[:, 2], atol=1e-9)
+    assert np.allclose(X[:, 0], off[:, 2] / R) and np.allclose(X[:, 7], d[src, 2])
+    assert np.allclose(np.hypot(X[:, 1], X[:, 2]) * 100.0, R)
+    # cos(eta) = dz uz + |d_h| |u_h| cos(relative azimuth)
+    hh = np.sqrt((1 - X[:, 7] ** 2) * (1 - X[:, 0] ** 2))
+    assert np.allclose(X[:, 8], X[:, 5] - X[:, 7] * X[:, 0])
+    assert np.allclose(X[:, 9] * hh, X[:, 8], atol=1e-9)
+    # segment extent: both end distances from the impact parameter and the
+    # along-track offset (Pythagoras), and direct Cherenkov light leaving
+    # the segment exactly where the cone through the module meets the track
+    b, along = X[:, 16] * 100.0, X[:, 17] * 100.0 + 5.0
+    assert np.allclose((X[:, 19] * 100.0) ** 2, b ** 2 + along ** 2)
+    assert np.allclose((X[:, 20] * 100.0) ** 2, b ** 2 + (along - 10.0) ** 2)
+    inside = (X[:, 18] > 0) & (X[:, 18] < 1)
+    q = c[src] - 5.0 * d[src] + (X[:, 18] * 10.0)[:, None] * d[src]   # emission point on the track
+    to_m = m[dom] - q
+    cos_c = (to_m * d[src]).sum(1) / np.linalg.norm(to_m, axis=1)
+    assert inside.any() and np.allclose(cos_c[inside], math.cos(math.radians(41.0)))
     # the baseline falls with distance at fixed optics and is positive
     assert (mub > 0).all()
+
+
+def test_features_do_not_depend_on_azimuth():
+    """Turning sources and modules together about the vertical axis (the
+    ice is layered in depth only) leaves every feature and the baseline
+    unchanged; a mirror image in a vertical plane too."""
+    w = W.full_detector(n_sources=4, photons_per_source=10, seed=9)
+    src = np.repeat(np.arange(4), len(w.doms))
+    dom = np.tile(np.arange(len(w.doms)), 4)
+    X0, mub0, _ = M.pair_features(w, src, dom)
+    for phi, mirror in ((0.7, False), (2.9, True)):
+        cs, sn = math.cos(phi), math.sin(phi)
+        sgn = -1.0 if mirror else 1.0
+
+        def turn(x, y):
+            return cs * x - sn * sgn * y, sn * x + cs * sgn * y
+        s2 = w.sources.copy()
+        d2 = w.doms.copy()
+        s2["x"], s2["y"] = turn(s2["x"].astype(float), s2["y"].astype(float))
+        s2["dx"], s2["dy"] = turn(s2["dx"].astype(float), s2["dy"].astype(float))
+        d2["x"], d2["y"] = turn(d2["x"].astype(float), d2["y"].astype(float))
+        X1, mub1, _ = M.pair_features(dataclasses.replace(w, sources=s2, doms=d2), src, dom)
+        # inputs are stored in float32, so the turned geometry differs by rounding
+        assert np.allclose(X1, X0, atol=2e-5), np.abs(X1 - X0).max()
+        assert np.allclose(mub1, mub0, rtol=1e-4)
 
 
 def test_baseline_is_the_diffusion_estimate_in_homogeneous_ice():
