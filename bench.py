@@ -83,6 +83,7 @@ def parse():
     ap.add_argument("--sur-train-photons", type=int, default=2_000_000)
     ap.add_argument("--sur-train-rmax", type=float, default=25.0)
     ap.add_argument("--sur-epochs", type=int, default=48)
+    ap.add_argument("--sur-ensemble", type=int, default=3)
     ap.add_argument("--sur-lr", type=float, default=1e-3)
     ap.add_argument("--sur-lr-final", type=float, default=1e-5)
     ap.add_argument("--sur-infer-sources", type=int, default=100_000)
@@ -195,9 +196,10 @@ def cpu_baseline(w, per_source: int):
 
 
 def surrogate_leg(args):
-    """Learned surrogate. Training: Monte Carlo of 6000 segments placed 3-25 m
-    from random modules of the full detector (5160 modules each: about 3e7
-    (segment, module) pairs at all distances). Inference throughput: 1e5 full-detector
+    """Learned surrogate: an ensemble of three networks trained on the same
+    labels from different initial weights. Training: Monte Carlo of 6000
+    segments placed 3-25 m from random modules of the full detector (5160
+    modules each: about 3e7 (segment, module) pairs at all distances). Inference throughput: 1e5 full-detector
     segments x 5160 modules. Accuracy and speed-up: clusters of four held-out
     segments 4-20 m from each of 40 target modules; truth = high-statistics Monte Carlo;
     graded modules have >= 1e4 truth hits (<= 1% statistical error). Plain
@@ -219,19 +221,29 @@ def surrogate_leg(args):
     b_tr = ctx.submit(tr)
     t0 = time.perf_counter()
     ctx.propagate(b_tr)
-    sur = surrogate.Surrogate(ctx, seed=1)
-    sur.set_training_set(b_tr)
     torch.cuda.synchronize()
-    n_pairs = sur.training_size()
     t1 = time.perf_counter()
-    losses = sur.train(epochs=args.sur_epochs, batch_size=8192, lr=args.sur_lr, lr_final=args.sur_lr_final)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    # an ensemble of independently initialised networks on the same labels;
+    # its expectation is the mean of theirs
+    members, losses, t_train = [], [], 0.0
+    for seed in range(1, args.sur_ensemble + 1):
+        m = surrogate.Surrogate(ctx, seed=seed)
+        m.set_training_set(b_tr)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        losses.append([float(x) for x in m.train(epochs=args.sur_epochs, batch_size=8192, lr=args.sur_lr,
+                                                 lr_final=args.sur_lr_final)])
+        torch.cuda.synchronize()
+        t_train += time.perf_counter() - t2
+        members.append(m)
+    sur = members[0]
+    n_pairs = sur.training_size()
     out.update({"train_sources": args.sur_train_sources, "train_photons_per_source": args.sur_train_photons,
-                "train_pairs": n_pairs, "label_mc_and_features_s": t1 - t0, "train_epochs": args.sur_epochs,
-                "train_lr": [args.sur_lr, args.sur_lr_final],
-                "train_s": t2 - t1, "train_pairs_per_s": n_pairs * args.sur_epochs / (t2 - t1),
-                "epoch_loss": [float(x) for x in losses]})
+                "train_pairs": n_pairs, "label_mc_s": t1 - t0, "ensemble": args.sur_ensemble,
+                "train_epochs": args.sur_epochs, "train_lr": [args.sur_lr, args.sur_lr_final],
+                "train_s": t_train,
+                "train_pairs_per_s": n_pairs * args.sur_epochs * args.sur_ensemble / t_train,
+                "epoch_loss_last": [l[-1] for l in losses]})
     ctx.release(b_tr)
 
     # inference throughput at 1e5 full-detector segments x all modules
@@ -266,13 +278,16 @@ def surrogate_leg(args):
     torch.cuda.synchronize()
     n_truth = int(ev["n_photons"].sum())
     mc_rate = n_truth / (e0.elapsed_time(e1) / 1e3)
-    sur.expected_hits(b_ev)
+    def ensemble_expectation():
+        return (sum(m.expected_hits(b_ev) for m in members) / len(members)).cpu().numpy()
+
+    ensemble_expectation()  # warm-up, including torch's first use of the tensor ops
     torch.cuda.synchronize()
     t5 = time.perf_counter()
-    pred = sur.expected_hits(b_ev).cpu().numpy()
+    pred = ensemble_expectation()
     torch.cuda.synchronize()
     t_sur = time.perf_counter() - t5
-    per_pair = sur.predict_pairs(b_ev, len(ev)).astype(np.float64)  # (segment, module) expectations
+    per_pair = sum(m.predict_pairs(b_ev, len(ev)).astype(np.float64) for m in members) / len(members)
     graded = np.nonzero(truth >= 10_000)[0]
     rel = np.abs(pred[graded] - truth[graded]) / truth[graded]
     within = rel <= 0.02
@@ -309,7 +324,8 @@ def surrogate_leg(args):
                     "speedup_at_2pct_global": t_glob / t_glob_h})
     out.update(res)
     params = sur.get_params()
-    sur.close()
+    for m in members:
+        m.close()
     return out, params
 
 
