@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--grid-blocks", type=int, default=0)
     ap.add_argument("--refill-interval", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the end-to-end and small-workload rates (profiling runs)")
     ap.add_argument("--cpu-photons-per-source", type=int, default=0,
                     help="oracle sample: first N photons of every source (0 = auto, ~15 s)")
     ap.add_argument("--no-surrogate", action="store_true")
@@ -484,8 +486,9 @@ def main():
                    "kernel_ms": kernel_ms, "kernel_ms_median": sorted(kernel_ms)[len(kernel_ms) // 2],
                    "lib_kernel_ms_last": st["kernel_ms"], "hits_fetched_count": n_hits},
     }
-    out["detail"].update(end_to_end(ctx, w))
-    out["detail"].update(tiny_rate())
+    if not args.no_extras:
+        out["detail"].update(end_to_end(ctx, w))
+        out["detail"].update(tiny_rate())
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_photons_per_source)
     sur_params = None

@@ -227,6 +227,42 @@ pp_status pp_submit(pp_context *ctx, const pp_source *sources, uint32_t n_source
 /* Frees a batch's device memory. */
 pp_status pp_release(pp_context *ctx, uint64_t batch);
 
+/* Wavelength dependence of the ice (Sec. 2, photon-propagation paragraph:
+ * every 10 m layer has its own scattering and absorption coefficients; the
+ * paper states no law for their change with wavelength). With this set, the
+ * loaded layer table holds the coefficients at lambda_ref_nm and a photon
+ * of wavelength l sees a (l / lambda_ref)^-kappa_abs and
+ * b (l / lambda_ref)^-kappa_scat; g is unchanged. The photon's wavelength is
+ * drawn at emission (fixed, or 1/l^2 on [lambda_min, lambda_max]). NULL
+ * restores wavelength-independent optics (the default). Applies to later
+ * pp_propagate calls and graph captures. PP_EINVAL unless lambda_ref_nm > 0
+ * and |kappa| <= 10. */
+typedef struct {
+  float lambda_ref_nm;  /* wavelength of the loaded coefficients */
+  float kappa_abs;      /* absorption exponent */
+  float kappa_scat;     /* scattering exponent */
+  float reserved;
+} pp_chromatic;
+pp_status pp_set_chromatic(pp_context *ctx, const pp_chromatic *c);
+
+/* Hit weight (Sec. 2: a photon that meets a module makes a photoelectron
+ * with a probability that depends on its position, direction, time and
+ * wavelength; the paper gives no formula). With this set, each hit's weight
+ * is A(l) P(c): A linear between table[k] at lambda0_nm + k dlambda_nm
+ * (held constant beyond the ends), P(c) = sum_k poly[k] c^k, and c the
+ * cosine of the angle between the photon's direction and the inward surface
+ * normal where it meets the module (0..1). Deterministic: no random draws.
+ * NULL restores weight 1 (the default). The arrays are copied. PP_EINVAL
+ * unless 1 <= n_table <= 256 with finite values >= 0, dlambda_nm > 0 when
+ * n_table > 1, and 1 <= n_poly <= 8 finite coefficients. */
+typedef struct {
+  float lambda0_nm, dlambda_nm;
+  uint32_t n_table, n_poly;
+  const float *table;
+  const float *poly;
+} pp_acceptance;
+pp_status pp_set_acceptance(pp_context *ctx, const pp_acceptance *acc);
+
 /* Turns per-photon terminal records on or off for later pp_propagate calls
  * (48 bytes of device memory per photon). */
 pp_status pp_set_debug_records(pp_context *ctx, int on);

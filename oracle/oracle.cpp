@@ -146,6 +146,19 @@ struct Ice {
   int n_layers = 0;
   double n_group = 1.35;
   std::vector<double> abs_coef, scat_coef, g;  // a = 1/lambda_a, b = 1/(lambda_e (1 - g))
+  // Wavelength dependence of the coefficients (the table holds them at
+  // lambda_ref): a(l) = a (l / lambda_ref)^-kappa_abs, b(l) likewise with
+  // kappa_scat; lambda_ref = 0 means none.
+  double lambda_ref = 0, kappa_abs = 0, kappa_scat = 0;
+};
+
+// Hit weight: acceptance A(lambda), linear between table values at
+// l0 + k dl (held constant beyond the ends), times a polynomial P(c) in the
+// cosine c of the angle between the photon's direction and the inward
+// surface normal where it meets the module. An empty table means weight 1.
+struct Acceptance {
+  std::vector<double> table, poly;
+  double l0 = 0, dl = 1;
 };
 
 struct Source {
@@ -173,7 +186,7 @@ struct Photon {
 
 struct Record {
   uint32_t fate, dom, n_iter, n_cross;
-  double t, x, y, z, vx, vy, vz, lambda;
+  double t, x, y, z, vx, vy, vz, lambda, weight;
 };
 
 // Layer i covers [z_lo + i dz, z_lo + (i+1) dz); the edge layers extend to
@@ -273,13 +286,34 @@ struct Counters {
 // Propagates one photon to its end. The loop follows the paper's order:
 // distance to the next scatter, move (absorbed or hitting a module on the
 // way ends the photon), new direction, repeat.
-Record propagate(const Ice &ice, const Doms &doms, const Source &src, uint64_t seed,
-                 uint64_t photon_index, uint64_t step_cap, int mode, Counters *cnt) {
+double hit_weight(const Acceptance &acc, const Doms &doms, uint32_t dom, const Photon &ph) {
+  if (acc.table.empty()) return 1.0;
+  double A = acc.table[0];
+  if (acc.table.size() > 1) {
+    const double x = std::min(std::max((ph.lambda - acc.l0) / acc.dl, 0.0),
+                              static_cast<double>(acc.table.size() - 1));
+    const size_t k = std::min(static_cast<size_t>(x), acc.table.size() - 2);
+    const double f = x - static_cast<double>(k);
+    A = acc.table[k] * (1.0 - f) + acc.table[k + 1] * f;
+  }
+  const Vec n = (1.0 / doms.r) * (ph.p - doms.c[dom]);  // outward unit normal at the hit point
+  const double c = std::min(std::max(-dot(ph.v, n), 0.0), 1.0);
+  double P = 0.0;
+  for (size_t k = acc.poly.size(); k-- > 0;) P = P * c + acc.poly[k];
+  return A * P;
+}
+
+Record propagate(const Ice &ice, const Doms &doms, const Acceptance &acc, const Source &src,
+                 uint64_t seed, uint64_t photon_index, uint64_t step_cap, int mode, Counters *cnt) {
   Photon ph = emit(ice, src, seed, photon_index);
   const double time_per_m = ice.n_group / kLightSpeed;
+  // the photon's coefficients are the table's scaled to its wavelength
+  const double sa = ice.lambda_ref > 0 ? std::pow(ph.lambda / ice.lambda_ref, -ice.kappa_abs) : 1.0;
+  const double sb = ice.lambda_ref > 0 ? std::pow(ph.lambda / ice.lambda_ref, -ice.kappa_scat) : 1.0;
   Record rec{};
   rec.dom = kNoDom;
   rec.lambda = ph.lambda;
+  rec.weight = 1.0;
   uint32_t fate = kCapped;
   uint64_t iter = 0;
   uint32_t n_cross = 0;
@@ -297,7 +331,7 @@ Record propagate(const Ice &ice, const Doms &doms, const Source &src, uint64_t s
     enum { kStepAbsorb, kStepScatter, kStepEscape } step_end;
     const int dir = ph.v.z > 0.0 ? 1 : (ph.v.z < 0.0 ? -1 : 0);
     for (;;) {
-      const double a = ice.abs_coef[i], b = ice.scat_coef[i];
+      const double a = ice.abs_coef[i] * sa, b = ice.scat_coef[i] * sb;
       const double d_abs = a > 0.0 ? ph.tau_a / a : kInf;
       const double d_sca = b > 0.0 ? tau_s / b : kInf;
       double d_bnd = kInf;
@@ -341,6 +375,7 @@ Record propagate(const Ice &ice, const Doms &doms, const Source &src, uint64_t s
       ph.t += h.best_t * time_per_m;
       fate = kHit;
       rec.dom = h.best_id;
+      rec.weight = hit_weight(acc, doms, h.best_id, ph);
       break;
     }
     if (step_end == kStepEscape) {
@@ -456,9 +491,26 @@ struct OrcInputs {
   const uint32_t *src_event, *src_particle;
   const double *src_f;
   const uint64_t *src_n, *src_first;
+  // wavelength dependence: lambda_ref (0: none), kappa_abs, kappa_scat
+  double lambda_ref, kappa_abs, kappa_scat;
+  // hit acceptance: n_acc table values at acc_l0 + k acc_dl (0: weight 1)
+  // and n_poly coefficients of P(c), lowest order first
+  uint32_t n_acc, n_poly;
+  double acc_l0, acc_dl;
+  const double *acc, *poly;
 };
 
-static void build_model(const OrcInputs *in, Ice *ice, Doms *doms, std::vector<Source> *src) {
+static void build_model(const OrcInputs *in, Ice *ice, Doms *doms, std::vector<Source> *src,
+                        Acceptance *acc = nullptr) {
+  ice->lambda_ref = in->lambda_ref;
+  ice->kappa_abs = in->kappa_abs;
+  ice->kappa_scat = in->kappa_scat;
+  if (acc && in->n_acc > 0) {
+    acc->table.assign(in->acc, in->acc + in->n_acc);
+    acc->poly.assign(in->poly, in->poly + in->n_poly);
+    acc->l0 = in->acc_l0;
+    acc->dl = in->acc_dl;
+  }
   ice->z_lo = in->z_lo;
   ice->dz = in->dz;
   ice->n_layers = in->n_layers;
@@ -543,7 +595,7 @@ int orc_emit(const OrcInputs *in, uint64_t seed, uint64_t n_sel, const uint64_t 
 //     (needs dom_string).
 //   outputs (each may be NULL):
 //     rec_u n x 4 (fate, dom id, iterations, layer crossings),
-//     rec_f n x 8 (t, x, y, z, vx, vy, vz, lambda),
+//     rec_f n x 9 (t, x, y, z, vx, vy, vz, lambda, hit weight (1 unless hit)),
 //     dom_counts n_dom (hits per module),
 //     counters 8 (photons, iterations, crossings, dom tests, hits, absorbed,
 //       capped, escaped).
@@ -554,8 +606,9 @@ int orc_run(const OrcInputs *in, uint64_t seed, uint64_t step_cap, int32_t dom_m
             uint64_t *counters) {
   Ice ice;
   Doms doms;
+  Acceptance acc;
   std::vector<Source> src;
-  build_model(in, &ice, &doms, &src);
+  build_model(in, &ice, &doms, &src, &acc);
   if (dom_mode == 1 && !in->dom_string) return -1;
 
   // The work list: (source, local photon number) per output slot.
@@ -582,16 +635,16 @@ int orc_run(const OrcInputs *in, uint64_t seed, uint64_t step_cap, int32_t dom_m
         s = std::upper_bound(prefix.begin(), prefix.end(), i) - prefix.begin() - 1;
         local = i - prefix[s];
       }
-      const Record r = propagate(ice, doms, src[s], seed, src[s].first_index + local, step_cap,
+      const Record r = propagate(ice, doms, acc, src[s], seed, src[s].first_index + local, step_cap,
                                  dom_mode, &cnt[tid]);
       if (rec_u) {
         rec_u[4 * i] = r.fate, rec_u[4 * i + 1] = r.dom;
         rec_u[4 * i + 2] = r.n_iter, rec_u[4 * i + 3] = r.n_cross;
       }
       if (rec_f) {
-        double *o = rec_f + 8 * i;
+        double *o = rec_f + 9 * i;
         o[0] = r.t, o[1] = r.x, o[2] = r.y, o[3] = r.z;
-        o[4] = r.vx, o[5] = r.vy, o[6] = r.vz, o[7] = r.lambda;
+        o[4] = r.vx, o[5] = r.vy, o[6] = r.vz, o[7] = r.lambda, o[8] = r.weight;
       }
       if (dom_counts && r.fate == kHit) counts[tid][r.dom]++;
     }

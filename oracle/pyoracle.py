@@ -41,6 +41,9 @@ class _Inputs(C.Structure):
         ("n_src", C.c_uint32), ("src_type", C.c_void_p), ("src_event", C.c_void_p),
         ("src_particle", C.c_void_p), ("src_f", C.c_void_p), ("src_n", C.c_void_p),
         ("src_first", C.c_void_p),
+        ("lambda_ref", C.c_double), ("kappa_abs", C.c_double), ("kappa_scat", C.c_double),
+        ("n_acc", C.c_uint32), ("n_poly", C.c_uint32), ("acc_l0", C.c_double), ("acc_dl", C.c_double),
+        ("acc", C.c_void_p), ("poly", C.c_void_p),
     ]
 
 
@@ -146,12 +149,20 @@ class _Packed:
         self.src_f = np.ascontiguousarray(np.stack([s[n] for n in names], 1), np.float64)
         self.src_n = np.ascontiguousarray(s["n_photons"], np.uint64)
         self.src_first = np.ascontiguousarray(s["first_photon_index"], np.uint64)
+        ch = w.chromatic or (0.0, 0.0, 0.0)
+        acc = w.acceptance
+        self.acc = np.ascontiguousarray(acc["table"], np.float64) if acc else None
+        self.poly = np.ascontiguousarray(acc["poly"], np.float64) if acc else None
         self.struct = _Inputs(
             float(w.z_lo_m), float(w.dz_m), len(L), float(w.n_group),
             _p(self.abs_len), _p(self.eff), _p(self.g),
             len(d), _p(self.dom_xyz), _p(self.dom_string), float(w.dom_radius_m),
             len(s), _p(self.src_type), _p(self.src_event), _p(self.src_particle),
-            _p(self.src_f), _p(self.src_n), _p(self.src_first))
+            _p(self.src_f), _p(self.src_n), _p(self.src_first),
+            float(ch[0]), float(ch[1]), float(ch[2]),
+            len(self.acc) if acc else 0, len(self.poly) if acc else 0,
+            float(acc["l0"]) if acc else 0.0, float(acc["dl"]) if acc else 1.0,
+            _p(self.acc), _p(self.poly))
 
 
 def emit(w, seed: int, sel_src, sel_local):
@@ -206,6 +217,10 @@ class Result:
     def wavelength(self):
         return self.rec_f[:, 7]
 
+    @property
+    def weight(self):
+        return self.rec_f[:, 8]
+
 
 def run(w, seed: int = 0, step_cap: int = 100_000, dom_mode: int = 0, threads: int | None = None,
         sel_src=None, sel_local=None, records: bool = True, dom_counts: bool = True) -> Result:
@@ -222,7 +237,7 @@ def run(w, seed: int = 0, step_cap: int = 100_000, dom_mode: int = 0, threads: i
     if threads is None:
         threads = max(1, min(16, os.cpu_count() or 1))
     rec_u = np.empty((n, 4), np.uint32) if records else None
-    rec_f = np.empty((n, 8), np.float64) if records else None
+    rec_f = np.empty((n, 9), np.float64) if records else None
     counts = np.zeros(len(w.doms), np.uint64) if dom_counts else None
     counters = np.zeros(8, np.uint64)
     rc = lib().orc_run(C.byref(pk.struct), seed, step_cap, dom_mode, threads, n_sel, _p(ss), _p(sl),

@@ -274,7 +274,10 @@ pp_status prepare(pp_context *ctx, Batch &b, Prepared *out) {
   uint32_t grid = c.grid_blocks;
   if (grid == 0) {
     int per_cu = 0;
-    PP_HIP(ctx, pp::propagate_occupancy(ctx->records, static_cast<int>(block), lds, &per_cu));
+    const bool wave = (ctx->chroma.lambda_ref_nm > 0 &&
+                       (ctx->chroma.kappa_abs != 0.0f || ctx->chroma.kappa_scat != 0.0f)) ||
+                      !ctx->acc_table.empty();
+    PP_HIP(ctx, pp::propagate_occupancy(ctx->records, wave, static_cast<int>(block), lds, &per_cu));
     grid = static_cast<uint32_t>(std::max(per_cu, 1) * std::max(ctx->n_cu, 1));
   }
   // Default chunk: 256 ids (measured best on the full detector), smaller
@@ -335,6 +338,18 @@ pp_status prepare(pp_context *ctx, Batch &b, Prepared *out) {
   a.hits = b.d_hits;
   a.hit_capacity = b.hit_cap;
   if (ctx->records) a.rec = b.rec;
+  const bool chroma = ctx->chroma.lambda_ref_nm > 0;
+  a.inv_lambda_ref = chroma ? 1.0f / ctx->chroma.lambda_ref_nm : 1.0f;
+  a.kappa_abs = chroma ? ctx->chroma.kappa_abs : 0.0f;
+  a.kappa_scat = chroma ? ctx->chroma.kappa_scat : 0.0f;
+  a.n_acc = static_cast<uint32_t>(ctx->acc_table.size());
+  a.acc = ctx->d_acc;
+  a.acc_l0 = ctx->acc_l0;
+  a.inv_acc_dl = 1.0f / ctx->acc_dl;
+  a.n_poly = static_cast<uint32_t>(ctx->acc_poly.size());
+  for (uint32_t k = 0; k < a.n_poly; ++k) a.poly[k] = ctx->acc_poly[k];
+  a.doms_by_id = ctx->d_doms_by_id;
+  a.inv_radius = 1.0f / ctx->radius;
 
   out->args = a;
   out->grid = grid;
@@ -529,6 +544,8 @@ void pp_destroy(pp_context *ctx) {
     (void)hipFree(ctx->d_strings);
     (void)hipFree(ctx->d_cells);
     (void)hipFree(ctx->d_doms);
+    (void)hipFree(ctx->d_doms_by_id);
+    (void)hipFree(ctx->d_acc);
   }
   delete ctx;
 }
@@ -558,6 +575,50 @@ pp_status pp_set_step_cap(pp_context *ctx, uint64_t step_cap) {
   if (!ctx) return PP_EINVAL;
   if (step_cap > (1ull << 31)) return fail(ctx, PP_EINVAL, "step_cap above 2^31");
   ctx->step_cap = step_cap;
+  return PP_OK;
+}
+
+pp_status pp_set_chromatic(pp_context *ctx, const pp_chromatic *c) {
+  if (!ctx) return PP_EINVAL;
+  if (!c) {
+    ctx->chroma = pp_chromatic{};
+    return PP_OK;
+  }
+  if (!finite(c->lambda_ref_nm) || !(c->lambda_ref_nm > 0) || !finite(c->kappa_abs) || !finite(c->kappa_scat) ||
+      std::fabs(c->kappa_abs) > 10.0f || std::fabs(c->kappa_scat) > 10.0f)
+    return fail(ctx, PP_EINVAL, "lambda_ref_nm must be finite and > 0, exponents finite with |kappa| <= 10");
+  ctx->chroma = *c;
+  return PP_OK;
+}
+
+pp_status pp_set_acceptance(pp_context *ctx, const pp_acceptance *acc) {
+  if (!ctx) return PP_EINVAL;
+  if (!acc) {
+    ctx->acc_table.clear();
+    ctx->acc_poly.clear();
+    return PP_OK;
+  }
+  if (acc->n_table < 1 || acc->n_table > static_cast<uint32_t>(pp::kMaxAcceptance) || !acc->table)
+    return fail(ctx, PP_EINVAL, "n_table must be 1..%d with a table", pp::kMaxAcceptance);
+  if (acc->n_poly < 1 || acc->n_poly > static_cast<uint32_t>(pp::kMaxPoly) || !acc->poly)
+    return fail(ctx, PP_EINVAL, "n_poly must be 1..%d with coefficients", pp::kMaxPoly);
+  if (!finite(acc->lambda0_nm) || !finite(acc->dlambda_nm) || (acc->n_table > 1 && !(acc->dlambda_nm > 0)))
+    return fail(ctx, PP_EINVAL, "lambda0_nm must be finite and dlambda_nm finite and > 0");
+  for (uint32_t k = 0; k < acc->n_table; ++k)
+    if (!finite(acc->table[k]) || acc->table[k] < 0)
+      return fail(ctx, PP_EINVAL, "acceptance %u must be finite and >= 0", k);
+  for (uint32_t k = 0; k < acc->n_poly; ++k)
+    if (!finite(acc->poly[k])) return fail(ctx, PP_EINVAL, "coefficient %u is not finite", k);
+  std::vector<float> table(acc->table, acc->table + acc->n_table);
+  if (ctx->device >= 0) {
+    pp_status st = need_device(ctx);
+    if (st != PP_OK) return st;
+    if ((st = upload(ctx, &ctx->d_acc, table)) != PP_OK) return st;
+  }
+  ctx->acc_table = std::move(table);
+  ctx->acc_poly.assign(acc->poly, acc->poly + acc->n_poly);
+  ctx->acc_l0 = acc->lambda0_nm;
+  ctx->acc_dl = acc->n_table > 1 ? acc->dlambda_nm : 1.0f;
   return PP_OK;
 }
 
@@ -641,6 +702,9 @@ pp_status pp_load_geometry(pp_context *ctx, const pp_dom *doms, uint32_t n, floa
     if ((st = upload(ctx, &ctx->d_strings, ctx->strings)) != PP_OK) return st;
     if ((st = upload(ctx, &ctx->d_cells, ctx->cells)) != PP_OK) return st;
     if ((st = upload(ctx, &ctx->d_doms, ctx->doms_sorted)) != PP_OK) return st;
+    std::vector<float4> by_id(n);
+    for (uint32_t k = 0; k < n; ++k) by_id[k] = make_float4(doms[k].x, doms[k].y, doms[k].z, 0.0f);
+    if ((st = upload(ctx, &ctx->d_doms_by_id, by_id)) != PP_OK) return st;
   }
   ctx->geo_loaded = true;
   return PP_OK;

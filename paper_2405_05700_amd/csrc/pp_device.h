@@ -71,6 +71,9 @@ struct Records {  // terminal records, structure of arrays (null if off)
   float *t, *x, *y, *z, *vx, *vy, *vz, *wavelength;
 };
 
+constexpr int kMaxPoly = 8;          // coefficients of the angular acceptance polynomial
+constexpr int kMaxAcceptance = 256;  // points of the wavelength acceptance table
+
 struct PropagateArgs {
   // ice: layer table and the n_layers + 1 boundary heights (first -inf,
   // last +inf, so the edge layers extend to infinity)
@@ -95,6 +98,17 @@ struct PropagateArgs {
   uint32_t seed_lo, seed_hi;
   uint32_t step_cap;
   uint32_t refill_interval;
+  // wavelength dependence: a photon of wavelength l sees the layer
+  // coefficients scaled by (l * inv_lambda_ref)^-kappa (kappas 0: none)
+  float inv_lambda_ref, kappa_abs, kappa_scat;
+  // hit acceptance (n_acc 0: weight 1): table at acc_l0 + k / inv_acc_dl,
+  // linear between points, times sum_k poly[k] c^k, c = cosine of incidence
+  const float *acc;
+  uint32_t n_acc, n_poly;
+  float acc_l0, inv_acc_dl;
+  float poly[kMaxPoly];
+  const float4 *doms_by_id;  // module centres by module id
+  float inv_radius;
   // outputs
   unsigned long long *counters;
   DevHit *hits;
@@ -107,7 +121,9 @@ size_t propagate_lds_bytes(int n_layers, int n_strings, int n_cells);
 
 hipError_t launch_reset(unsigned long long *counters, int n, hipStream_t stream);
 hipError_t launch_propagate(const PropagateArgs &args, int grid, int block, hipStream_t stream);
-hipError_t propagate_occupancy(bool records, int block, size_t lds_bytes, int *blocks_per_cu);
+// records: debug records on; wave: wavelength-dependent optics or hit
+// acceptance (the kernel variant that draws wavelengths).
+hipError_t propagate_occupancy(bool records, bool wave, int block, size_t lds_bytes, int *blocks_per_cu);
 hipError_t launch_dom_histogram(const DevHit *hits, const unsigned long long *hit_count,
                                 unsigned long long hit_capacity, uint32_t *counts, uint32_t n_doms,
                                 hipStream_t stream);

@@ -68,6 +68,12 @@ struct pp_context {
   pp::DevString *d_strings = nullptr;
   uint32_t *d_cells = nullptr;
   float4 *d_doms = nullptr;
+  float4 *d_doms_by_id = nullptr;  // module centres in module-id order
+  // wavelength dependence and hit acceptance
+  pp_chromatic chroma{};           // lambda_ref_nm 0: none
+  std::vector<float> acc_table, acc_poly;
+  float acc_l0 = 0, acc_dl = 1;
+  float *d_acc = nullptr;
   // batches
   std::map<uint64_t, ppi::Batch> batches;
   uint64_t next_batch = 1;

@@ -164,9 +164,34 @@ __device__ __forceinline__ void rotate(float rx, float ry, float rz, float om, f
   vz = z * inv;
 }
 
-template <bool kRecords>
+// Weight of a hit (the chance that it makes a photoelectron): acceptance
+// table at the wavelength, linear between points and held beyond the ends,
+// times the angular polynomial in the cosine of incidence c = -v . n, n the
+// outward surface normal where the photon meets the module.
+__device__ __forceinline__ float hit_weight(const PropagateArgs &a, uint32_t dom, float px, float py, float pz,
+                                         float vx, float vy, float vz, float lambda) {
+  float A = a.acc[0];
+  if (a.n_acc > 1) {
+    const float x = fminf(fmaxf((lambda - a.acc_l0) * a.inv_acc_dl, 0.0f), (float)(a.n_acc - 1));
+    const uint32_t k = min((uint32_t)x, a.n_acc - 2);
+    const float f = x - (float)k;
+    A = __builtin_fmaf(a.acc[k + 1] - a.acc[k], f, a.acc[k]);
+  }
+  const float4 m = a.doms_by_id[dom];
+  const float c = -((px - m.x) * vx + (py - m.y) * vy + (pz - m.z) * vz) * a.inv_radius;
+  const float cc = fminf(fmaxf(c, 0.0f), 1.0f);
+  float P = 0.0f;
+  for (int k = (int)a.n_poly - 1; k >= 0; --k) P = __builtin_fmaf(P, cc, a.poly[k]);
+  return A * P;
+}
+
+// kWave: the photon's wavelength matters (wavelength-dependent optics, hit
+// acceptance or debug records). Without it the kernel draws no wavelength
+// and scales nothing, and every hit weighs 1.
+template <bool kRecords, bool kWave>
 __global__ void __launch_bounds__(1024)
 k_propagate(const PropagateArgs a) {
+  static_assert(kWave || !kRecords, "records carry the wavelength");
   extern __shared__ __align__(16) unsigned char lds_raw[];
   DevLayer *s_layers = reinterpret_cast<DevLayer *>(lds_raw);
   DevString *s_strings = reinterpret_cast<DevString *>(s_layers + a.n_layers);
@@ -196,6 +221,7 @@ k_propagate(const PropagateArgs a) {
   unsigned long long pidx = 0, seq = 0;
   float px = 0, py = 0, pz = 0, vx = 0, vy = 0, vz = 1, t = 0, tau_a = 0, lambda = 0;
   float elen = 0, eom = 0;  // emission: track length (0: point) and 1 - cos(cone), < 0 for a point source
+  float inv_sb = 1.0f;      // 1 / scattering-coefficient scale at the photon's wavelength
   int layer = 0;
   uint32_t st_iter = 0, st_cross = 0, st_tests = 0;
 
@@ -214,9 +240,11 @@ k_propagate(const PropagateArgs a) {
         if (ended && fate == kFateHit) {
           const unsigned long long slot = base + lane_rank(hmask);
           if (slot < a.hit_capacity) {
+            const float weight =
+                kWave && a.n_acc ? hit_weight(a, hit_dom, px, py, pz, vx, vy, vz, lambda) : 1.0f;
             uint4 *out = reinterpret_cast<uint4 *>(a.hits + slot);
             out[0] = make_uint4((uint32_t)pidx, (uint32_t)(pidx >> 32), event, particle);
-            out[1] = make_uint4(hit_dom, __float_as_uint(t), __float_as_uint(1.0f), 0u);
+            out[1] = make_uint4(hit_dom, __float_as_uint(t), __float_as_uint(weight), 0u);
           }
         }
       }
@@ -265,10 +293,8 @@ k_propagate(const PropagateArgs a) {
           const DevSource &S = a.sources[ch_src];
           const unsigned long long local = ch_local + rank;
           pidx = S.first_index + local;
-          if (kRecords) {
-            seq = S.seq_base + local;
-            src = ch_src;
-          }
+          if (kWave) src = ch_src;
+          if (kRecords) seq = S.seq_base + local;
           event = S.ids.y;
           particle = S.ids.z;
           const bool point = S.ids.x == 0;
@@ -323,10 +349,17 @@ k_propagate(const PropagateArgs a) {
         om = eom < 0.0f ? 2.0f * (1.0f - u0) : eom;
         phi = u01(w[1]);
         tau_a = budget;
-        if (kRecords) {
-          const DevSource &S = a.sources[src];
-          lambda = S.emit.y != 0.0f ? S.emit.y
-                                    : __builtin_amdgcn_rcpf(__builtin_fmaf(-u01(w[3]), S.emit.w, S.emit.z));
+        if (kWave) {
+          // wavelength: fixed, or u3 through the inverse CDF of a 1/l^2 density
+          const float4 em = a.sources[src].emit;
+          lambda = em.y != 0.0f ? em.y : __builtin_amdgcn_rcpf(__builtin_fmaf(-u01(w[3]), em.w, em.z));
+          // Coefficients scaled by s = (l / l_ref)^-kappa are the same as the
+          // table's coefficients with every optical-depth budget divided by
+          // s: the absorption budget once here, the scattering budget each
+          // step. Exponents 0 give factors of exactly 1.
+          const float lr = __builtin_amdgcn_logf(lambda * a.inv_lambda_ref);
+          tau_a = budget * __builtin_amdgcn_exp2f(a.kappa_abs * lr);
+          inv_sb = __builtin_amdgcn_exp2f(a.kappa_scat * lr);
         }
         const float lf = floorf((pz - a.z_lo) * a.inv_dz);
         layer = lf >= 0.0f ? (lf >= (float)(a.n_layers - 1) ? a.n_layers - 1 : (int)lf) : 0;
@@ -335,7 +368,7 @@ k_propagate(const PropagateArgs a) {
       } else {
         ++iter;
         ++st_iter;
-        float tau_s = budget;
+        float tau_s = kWave ? budget * inv_sb : budget;
 
         // Layer walk: consume both optical-depth budgets layer by layer
         // until one runs out (ties: absorb <= scatter <= boundary). A zero
@@ -504,20 +537,25 @@ hipError_t launch_reset(unsigned long long *counters, int n, hipStream_t stream)
   return hipGetLastError();
 }
 
+bool needs_wave(const PropagateArgs &a) { return a.kappa_abs != 0.0f || a.kappa_scat != 0.0f || a.n_acc != 0; }
+
 hipError_t launch_propagate(const PropagateArgs &args, int grid, int block, hipStream_t stream) {
   const size_t lds = propagate_lds_bytes(args.n_layers, args.n_strings, args.nx * args.ny);
   if (args.rec.fate != nullptr)
-    hipLaunchKernelGGL(k_propagate<true>, dim3(grid), dim3(block), lds, stream, args);
+    hipLaunchKernelGGL((k_propagate<true, true>), dim3(grid), dim3(block), lds, stream, args);
+  else if (needs_wave(args))
+    hipLaunchKernelGGL((k_propagate<false, true>), dim3(grid), dim3(block), lds, stream, args);
   else
-    hipLaunchKernelGGL(k_propagate<false>, dim3(grid), dim3(block), lds, stream, args);
+    hipLaunchKernelGGL((k_propagate<false, false>), dim3(grid), dim3(block), lds, stream, args);
   return hipGetLastError();
 }
 
-hipError_t propagate_occupancy(bool records, int block, size_t lds_bytes, int *blocks_per_cu) {
-  return records ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_propagate<true>, block,
-                                                                lds_bytes)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_propagate<false>, block,
-                                                                lds_bytes);
+hipError_t propagate_occupancy(bool records, bool wave, int block, size_t lds_bytes, int *blocks_per_cu) {
+  if (records)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_propagate<true, true>, block, lds_bytes);
+  if (wave)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_propagate<false, true>, block, lds_bytes);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_propagate<false, false>, block, lds_bytes);
 }
 
 hipError_t launch_dom_histogram(const DevHit *hits, const unsigned long long *hit_count,

@@ -60,6 +60,16 @@ class _GeometryInfo(C.Structure):
                 ("cell_m", C.c_float), ("max_reach_m", C.c_float)]
 
 
+class _Chromatic(C.Structure):
+    _fields_ = [("lambda_ref_nm", C.c_float), ("kappa_abs", C.c_float), ("kappa_scat", C.c_float),
+                ("reserved", C.c_float)]
+
+
+class _Acceptance(C.Structure):
+    _fields_ = [("lambda0_nm", C.c_float), ("dlambda_nm", C.c_float), ("n_table", C.c_uint32),
+                ("n_poly", C.c_uint32), ("table", C.c_void_p), ("poly", C.c_void_p)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/pp.h
 _vp, _u64, _u32 = C.c_void_p, C.c_uint64, C.c_uint32
 SIGNATURES = {
@@ -87,6 +97,8 @@ SIGNATURES = {
     "pp_autotune": (C.c_int, [_vp, _u64, _vp, C.POINTER(_LaunchConfig)]),
     "pp_graph_capture": (C.c_int, [_vp, _u64, _vp]),
     "pp_graph_launch": (C.c_int, [_vp, _u64, _vp]),
+    "pp_set_chromatic": (C.c_int, [_vp, C.POINTER(_Chromatic)]),
+    "pp_set_acceptance": (C.c_int, [_vp, C.POINTER(_Acceptance)]),
 }
 
 
@@ -186,6 +198,32 @@ class Context:
     def load_workload(self, w: "W.Workload"):
         self.load_ice(w.z_lo_m, w.dz_m, w.n_group, w.layers)
         self.load_geometry(w.doms, w.dom_radius_m)
+        self.set_chromatic(*(w.chromatic or ()))
+        a = w.acceptance
+        if a:
+            self.set_acceptance(a["l0"], a["dl"], a["table"], a["poly"])
+        else:
+            self.set_acceptance()
+
+    def set_chromatic(self, lambda_ref_nm=None, kappa_abs=0.0, kappa_scat=0.0):
+        """Coefficients scale as (lambda / lambda_ref)^-kappa; no argument:
+        wavelength-independent optics."""
+        if lambda_ref_nm is None:
+            self._check(_lib.pp_set_chromatic(self._h, None))
+            return
+        c = _Chromatic(lambda_ref_nm, kappa_abs, kappa_scat, 0.0)
+        self._check(_lib.pp_set_chromatic(self._h, C.byref(c)))
+
+    def set_acceptance(self, lambda0_nm=None, dlambda_nm=1.0, table=(), poly=(1.0,)):
+        """Hit weight = table(lambda) x poly(cos incidence); no argument:
+        weight 1."""
+        if lambda0_nm is None:
+            self._check(_lib.pp_set_acceptance(self._h, None))
+            return
+        t = np.ascontiguousarray(table, np.float32)
+        p = np.ascontiguousarray(poly, np.float32)
+        a = _Acceptance(lambda0_nm, dlambda_nm, len(t), len(p), t.ctypes.data, p.ctypes.data)
+        self._check(_lib.pp_set_acceptance(self._h, C.byref(a)))
 
     def geometry_info(self) -> dict:
         gi = _GeometryInfo()

@@ -65,6 +65,14 @@ class Workload:
     doms: np.ndarray        # DOM_DTYPE; the module id is the row index
     dom_radius_m: float
     sources: np.ndarray     # SOURCE_DTYPE
+    # optional wavelength dependence of the layer coefficients:
+    # (lambda_ref_nm, kappa_abs, kappa_scat), coefficients scale as
+    # (lambda / lambda_ref)^-kappa; None: independent of wavelength
+    chromatic: tuple | None = None
+    # optional hit acceptance: {"l0": nm, "dl": nm, "table": [...],
+    # "poly": [...]} (weight = table interpolated at the photon's
+    # wavelength x polynomial in the cosine of incidence); None: weight 1
+    acceptance: dict | None = None
 
     @property
     def n_photons(self) -> int:

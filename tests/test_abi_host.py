@@ -3,6 +3,7 @@ input validation, call-order errors and the search grid's conservativeness.
 No device compute: contexts here are host-only (device -1)."""
 import glob
 import math
+import ctypes as C
 import os
 import re
 import subprocess
@@ -51,9 +52,10 @@ def test_struct_layouts_match_bindings(tmp_path, pp):
 #include <stdio.h>
 #include "pp.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(pp_source), sizeof(pp_hit),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(pp_source), sizeof(pp_hit),
          sizeof(pp_photon_record), sizeof(pp_dom), sizeof(pp_ice_layer), sizeof(pp_ice_header),
-         offsetof(pp_source, n_photons), offsetof(pp_hit, time_ns));
+         offsetof(pp_source, n_photons), offsetof(pp_hit, time_ns), sizeof(pp_chromatic),
+         sizeof(pp_acceptance), offsetof(pp_acceptance, poly));
   return 0;
 }''')
     exe = tmp_path / "layout"
@@ -61,7 +63,26 @@ int main(void) {
     got = [int(x) for x in subprocess.check_output([str(exe)], text=True).split()]
     assert got == [W.SOURCE_DTYPE.itemsize, pp.HIT_DTYPE.itemsize, pp.RECORD_DTYPE.itemsize,
                    W.DOM_DTYPE.itemsize, W.ICE_LAYER_DTYPE.itemsize, 16,
-                   W.SOURCE_DTYPE.fields["n_photons"][1], pp.HIT_DTYPE.fields["time_ns"][1]]
+                   W.SOURCE_DTYPE.fields["n_photons"][1], pp.HIT_DTYPE.fields["time_ns"][1],
+                   C.sizeof(pp._Chromatic), C.sizeof(pp._Acceptance), pp._Acceptance.poly.offset]
+
+
+def test_chromatic_and_acceptance_validation(pp):
+    ctx = host_ctx(pp)
+    for bad in ((0.0, 1.0, 1.0), (-400.0, 0.0, 0.0), (400.0, 11.0, 0.0), (400.0, 0.0, float("nan"))):
+        expect(pp, pp.PP_EINVAL, ctx.set_chromatic, *bad)
+    ctx.set_chromatic(400.0, 1.0, 0.5)
+    ctx.set_chromatic()
+    expect(pp, pp.PP_EINVAL, ctx.set_acceptance, 300.0, 10.0, [], [1.0])
+    expect(pp, pp.PP_EINVAL, ctx.set_acceptance, 300.0, 10.0, [1.0] * 257, [1.0])
+    expect(pp, pp.PP_EINVAL, ctx.set_acceptance, 300.0, 10.0, [1.0, -0.5], [1.0])
+    expect(pp, pp.PP_EINVAL, ctx.set_acceptance, 300.0, 0.0, [1.0, 2.0], [1.0])
+    expect(pp, pp.PP_EINVAL, ctx.set_acceptance, 300.0, 10.0, [1.0], [])
+    expect(pp, pp.PP_EINVAL, ctx.set_acceptance, 300.0, 10.0, [1.0], [1.0] * 9)
+    expect(pp, pp.PP_EINVAL, ctx.set_acceptance, 300.0, 10.0, [1.0], [float("inf")])
+    ctx.set_acceptance(300.0, 0.0, [0.8], [0.0, 1.0])  # one point: dlambda unused
+    ctx.set_acceptance()
+    ctx.close()
 
 
 def host_ctx(pp, w=None):

@@ -271,3 +271,75 @@ def test_statistical_consistency_independent_seeds(pp, oracle):
         p = stats.chi2.sf(chi2, dof)
         say("chi2", n, r, chi2, dof, p, c0.sum(), c1.sum())
         assert p > 0.01
+
+
+def chromatic_tiny(n, radius=W.DOM_RADIUS_M):
+    """The tiny configuration with 300-600 nm photons (1/l^2), coefficients
+    scaled from 400 nm with exponents 1.5 (absorption) and 0.9
+    (scattering), and an acceptance table x angular polynomial."""
+    w = W.tiny_point_source(n, dom_radius_m=radius)
+    src = w.sources.copy()
+    src["lambda_min_nm"], src["lambda_max_nm"] = 300.0, 600.0
+    return W.dataclasses.replace(w.with_sources(src), chromatic=(400.0, 1.5, 0.9),
+                                 acceptance={"l0": 300.0, "dl": 150.0, "table": [0.5, 1.5, 1.0],
+                                             "poly": [0.2, 0.8]})
+
+
+def test_chromatic_optics_per_photon(pp, oracle):
+    """Wavelength-dependent coefficients: every photon follows its FP64
+    twin (same wavelength, same fate, module and step count)."""
+    w = chromatic_tiny(100_000)
+    g = gpu_run(pp, w)
+    ref = oracle.run(w, dom_mode=1, threads=THREADS)
+    frac, ok = agreement(g["rec"], ref)
+    lam_ok = np.abs(g["rec"]["wavelength_nm"] - ref.wavelength) <= 1e-5 * ref.wavelength
+    say("chromatic per-photon agreement", frac, "wavelengths", lam_ok.mean())
+    assert frac >= MIN_AGREE and lam_ok.mean() >= MIN_AGREE
+    # the optics really changed: over this spectrum the mean path to
+    # absorption is (l / 400)^1.5 averaged with density 1/l^2 on
+    # [300, 600] nm: 0.075 * 2 (sqrt(600) - sqrt(300)) = 1.076 times the grey one
+    grey = oracle.run(W.dataclasses.replace(w, chromatic=None), dom_mode=1, threads=THREADS)
+    ratio = ref.t.mean() / grey.t.mean()
+    say("mean time chromatic / grey", ratio)
+    assert abs(ratio - 1.076) < 0.02
+    check_conservation(g["stats"], w.n_photons)
+
+
+def test_hit_weights_match_oracle(pp, oracle):
+    """Hit weights (acceptance at the wavelength x polynomial in the cosine
+    of incidence) agree with the oracle's for the same photons."""
+    w = chromatic_tiny(100_000, radius=2.0)
+    g = gpu_run(pp, w, records=False)
+    ref = oracle.run(w, dom_mode=1, threads=THREADS)
+    hits = g["hits"]
+    assert len(hits) > 500
+    rw = ref.weight[hits["photon_index"].astype(np.int64)]
+    same = ref.fate[hits["photon_index"].astype(np.int64)] == oracle.FATE_HIT
+    # The cosine of incidence is sqrt(r^2 - h^2) / r (h: the ray's distance
+    # from the module centre); FP32 rounding of h^2 (~ 2^-22 |d|^2 for a step
+    # starting |d| ~ 10 m away) moves it by ~ 5e-6 / c, so grazing hits
+    # (small c) lose relative precision: most weights agree to 1e-4, all to
+    # 2e-3 (c >= 0.0025 for all but ~6e-6 of Lambert-distributed hits).
+    dw = np.abs(hits["weight"] - rw)[same]
+    tight = dw <= 1e-4 * np.abs(rw[same]) + 1e-6
+    say("hit weights: hits", len(hits), "same photon hits in oracle", same.mean(), "within 1e-4", tight.mean(),
+        "max abs diff", dw.max())
+    assert same.mean() >= MIN_AGREE and tight.mean() >= 0.98 and (dw <= 2e-3).mean() >= MIN_AGREE
+    assert (hits["weight"] >= 0).all() and hits["weight"].std() > 0.05
+
+
+def test_default_optics_and_weights_unchanged(pp, oracle):
+    """Exponents 0 and no acceptance: bit-identical records to a context
+    that never set them, and every weight is exactly 1."""
+    w = W.tiny_point_source(20_000)
+    a = gpu_run(pp, w)
+    ctx = pp.Context(0, seed=0)
+    ctx.load_workload(w)
+    ctx.set_debug_records(True)
+    ctx.set_chromatic(400.0, 0.0, 0.0)
+    ctx.set_acceptance(300.0, 10.0, [1.0], [1.0])
+    b = ctx.submit(w.sources)
+    ctx.propagate(b)
+    rec = ctx.fetch_records(b, 0, w.n_photons)
+    assert (rec == a["rec"]).all()
+    assert (a["hits"]["weight"] == 1.0).all() and (ctx.fetch_hits(b)["weight"] == 1.0).all()
