@@ -94,6 +94,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-saturation-seconds", type=float, default=5.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter scaling)")
     return ap.parse_args()
@@ -333,11 +334,15 @@ def surrogate_leg(args):
 
 def serving_leg(args, sur_params=None):
     """Serving loop: 16 client threads submit events (one Cherenkov segment
-    each, N = round(10 E) photons, E ~ E^-2.7 on [1e2, 1e7] GeV) as Poisson
-    streams totalling 200 events/s to the photon server (continuous
-    batching, 200 GB HBM budget, surrogate expectations attached), for a
-    fixed duration; reports throughput and p50/p99 event latency from the
-    server's own submit/done stamps."""
+    each, N = round(10 E) photons, E ~ E^-2.7 on [1e2, 1e7] GeV) to the
+    photon server (continuous batching, 200 GB HBM budget, surrogate
+    expectations attached).
+    * offered load: Poisson streams totalling 200 events/s for a fixed
+      duration; throughput and p50/p99 event latency from the server's own
+      submit/done stamps;
+    * saturation: each client keeps 32 requests outstanding (a closed loop)
+      for a fixed duration; sustained events/s and photons/s through the
+      server, with the same latency figures."""
     import threading
     import numpy as np
     import torch
@@ -351,51 +356,66 @@ def serving_leg(args, sur_params=None):
     if sur_params is not None:
         sur = surrogate.Surrogate(ctx, seed=0)
         sur.set_params(sur_params)
-    srv = server.Server(ctx, max_inflight=4, hbm_budget_bytes=200_000_000_000, surrogate=sur)
-    n_clients, rate, duration = 16, args.serve_rate, args.serve_seconds
-    infos, lock = [], threading.Lock()
+    n_clients = 16
 
-    def client(c):
-        rng = np.random.default_rng(1000 + c)
-        energies = W.power_law_energies(int(rate * duration / n_clients * 3) + 16, seed=2000 + c)
-        segs = W.cherenkov_segments(len(energies), 1, seed=3000 + c)
+    def events_of(c, n):
+        energies = W.power_law_energies(n, seed=2000 + c)
+        segs = W.cherenkov_segments(n, 1, seed=3000 + c)
         segs["n_photons"] = np.rint(10.0 * energies).astype(np.uint64)
-        segs["event_id"] = c * 1_000_000 + np.arange(len(segs))
-        tickets = []
-        t_end = time.perf_counter() + duration
-        k = 0
-        while True:
-            time.sleep(rng.exponential(n_clients / rate))
-            if time.perf_counter() >= t_end or k >= len(segs):
-                break
-            tickets.append(srv.submit(segs[k:k + 1]))
-            k += 1
-        for t in tickets:
-            _, info, _ = srv.wait(t, expected=sur is not None)
-            with lock:
-                infos.append(info)
+        segs["event_id"] = c * 10_000_000 + np.arange(n)
+        return segs
 
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    th = [threading.Thread(target=client, args=(c,)) for c in range(n_clients)]
-    for t in th:
-        t.start()
-    for t in th:
-        t.join()
-    wall = time.perf_counter() - t0
-    st = srv.stats()
-    srv.close()
-    lat = np.array([i["t_done_s"] - i["t_submit_s"] for i in infos])
-    photons = sum(i["photons"] for i in infos)
-    span = max(i["t_done_s"] for i in infos) - min(i["t_submit_s"] for i in infos)
-    return {"clients": n_clients, "offered_events_per_s": rate, "duration_s": duration,
-            "events": len(infos), "events_per_s": len(infos) / span, "photons_per_s": photons / span,
-            "latency_p50_ms": 1e3 * float(np.percentile(lat, 50)),
-            "latency_p99_ms": 1e3 * float(np.percentile(lat, 99)),
-            "latency_max_ms": 1e3 * float(lat.max()),
-            "launches": st["launches"], "events_per_launch": st["completed"] / max(st["launches"], 1),
-            "peak_device_bytes": st["peak_bytes_in_use"], "surrogate_attached": sur is not None,
-            "wall_s": wall}
+    def run(mode, duration):
+        srv = server.Server(ctx, max_inflight=4, hbm_budget_bytes=200_000_000_000, surrogate=sur)
+        infos, lock = [], threading.Lock()
+
+        def client(c):
+            rng = np.random.default_rng(1000 + c)
+            n_max = int(args.serve_rate * duration / n_clients * 3) + 16 if mode == "poisson" else 400_000
+            segs = events_of(c, n_max)
+            tickets, mine = [], []
+            t_end = time.perf_counter() + duration
+            k = 0
+            while k < len(segs):
+                if mode == "poisson":
+                    time.sleep(rng.exponential(n_clients / args.serve_rate))
+                elif len(tickets) >= 32:
+                    mine.append(srv.wait(tickets.pop(0), expected=sur is not None)[1])
+                if time.perf_counter() >= t_end:
+                    break
+                tickets.append(srv.submit(segs[k:k + 1]))
+                k += 1
+            for t in tickets:
+                mine.append(srv.wait(t, expected=sur is not None)[1])
+            with lock:
+                infos.extend(mine)
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        th = [threading.Thread(target=client, args=(c,)) for c in range(n_clients)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat = np.array([i["t_done_s"] - i["t_submit_s"] for i in infos])
+        photons = sum(i["photons"] for i in infos)
+        span = max(i["t_done_s"] for i in infos) - min(i["t_submit_s"] for i in infos)
+        return {"duration_s": duration, "events": len(infos), "events_per_s": len(infos) / span,
+                "photons_per_s": photons / span,
+                "latency_p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                "latency_p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                "latency_max_ms": 1e3 * float(lat.max()),
+                "launches": st["launches"], "events_per_launch": st["completed"] / max(st["launches"], 1),
+                "peak_device_bytes": st["peak_bytes_in_use"], "wall_s": wall}
+
+    out = {"clients": n_clients, "offered_events_per_s": args.serve_rate, "surrogate_attached": sur is not None}
+    out.update(run("poisson", args.serve_seconds))
+    out["saturation"] = run("closed", args.serve_saturation_seconds)
+    out["saturation"]["outstanding_per_client"] = 32
+    return out
 
 
 def main():

@@ -54,21 +54,101 @@ pp_status upload(pp_context *ctx, T **dptr, const std::vector<T> &host) {
   return PP_OK;
 }
 
+constexpr size_t kPoolMinBlock = 4096;
+constexpr size_t kPoolMaxBlock = size_t(256) << 20;
+constexpr size_t kPoolCacheBytes = size_t(8) << 30;
+
+// Device memory for a batch buffer: a cached block of the request's
+// power-of-two size class if one is free, else a new one. Requests above
+// kPoolMaxBlock get their own allocation.
+pp_status pool_alloc(pp_context *ctx, void **out, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 1);
+  size_t cls = bytes;
+  if (bytes <= kPoolMaxBlock) {
+    cls = kPoolMinBlock;
+    while (cls < bytes) cls <<= 1;
+    auto it = ctx->pool_free.find(cls);
+    if (it != ctx->pool_free.end() && !it->second.empty()) {
+      *out = it->second.back();
+      it->second.pop_back();
+      ctx->pool_cached -= cls;
+      ctx->pool_live[*out] = cls;
+      return PP_OK;
+    }
+  }
+  hipError_t e = hipMalloc(out, cls);
+  if (e != hipSuccess && ctx->pool_cached > 0) {  // give the cache back and try once more
+    for (auto &kv : ctx->pool_free)
+      for (void *p : kv.second) (void)hipFree(p);
+    ctx->pool_free.clear();
+    ctx->pool_cached = 0;
+    e = hipMalloc(out, cls);
+  }
+  if (e != hipSuccess) {
+    *out = nullptr;
+    return fail(ctx, PP_ENOMEM, "device allocation of %zu bytes: %s", cls, hipGetErrorString(e));
+  }
+  ctx->pool_live[*out] = cls;
+  return PP_OK;
+}
+
+// Returns a block to the cache (or frees it). The caller guarantees that no
+// enqueued work still uses it.
+void pool_free(pp_context *ctx, void *p) {
+  if (!p) return;
+  auto it = ctx->pool_live.find(p);
+  if (it == ctx->pool_live.end()) {
+    (void)hipFree(p);
+    return;
+  }
+  const size_t cls = it->second;
+  ctx->pool_live.erase(it);
+  if (cls > kPoolMaxBlock || ctx->pool_cached + cls > kPoolCacheBytes) {
+    (void)hipFree(p);
+    return;
+  }
+  ctx->pool_free[cls].push_back(p);
+  ctx->pool_cached += cls;
+}
+
+template <class T>
+pp_status pool_upload(pp_context *ctx, T **dptr, const std::vector<T> &host) {
+  pool_free(ctx, *dptr);
+  *dptr = nullptr;
+  if (host.empty()) return PP_OK;
+  void *p = nullptr;
+  pp_status st = pool_alloc(ctx, &p, sizeof(T) * host.size());
+  if (st != PP_OK) return st;
+  *dptr = static_cast<T *>(p);
+  PP_HIP(ctx, hipMemcpy(*dptr, host.data(), sizeof(T) * host.size(), hipMemcpyHostToDevice));
+  return PP_OK;
+}
+
+// Records that work enqueued on stream reads the batch's buffers, so that
+// releasing the batch waits for it.
+pp_status note_use(pp_context *ctx, Batch &b, hipStream_t stream) {
+  if (!b.ev_use) PP_HIP(ctx, hipEventCreateWithFlags(&b.ev_use, hipEventDisableTiming));
+  PP_HIP(ctx, hipEventRecord(b.ev_use, stream));
+  return PP_OK;
+}
+
 void drop_graph(Batch &b) {
   if (b.graph) (void)hipGraphExecDestroy(b.graph);
   b.graph = nullptr;
 }
 
-void free_batch(Batch &b) {
+void free_batch(pp_context *ctx, Batch &b) {
   if (b.ev1) (void)hipEventSynchronize(b.ev1);
+  if (b.ev_use) (void)hipEventSynchronize(b.ev_use);
   drop_graph(b);
-  (void)hipFree(b.d_src);
-  (void)hipFree(b.d_chunks);
-  (void)hipFree(b.d_counters);
-  (void)hipFree(b.d_hits);
-  (void)hipFree(b.d_rec);
+  pool_free(ctx, b.d_src);
+  pool_free(ctx, b.d_chunks);
+  pool_free(ctx, b.d_counters);
+  pool_free(ctx, b.d_hits);
+  pool_free(ctx, b.d_rec);
   if (b.ev0) (void)hipEventDestroy(b.ev0);
   if (b.ev1) (void)hipEventDestroy(b.ev1);
+  if (b.ev_use) (void)hipEventDestroy(b.ev_use);
   b = Batch{};
 }
 
@@ -228,7 +308,7 @@ pp_status build_chunks(pp_context *ctx, Batch &b, uint32_t chunk) {
   }
   if (ch.size() >= 0xFFFFFFFFull) return fail(ctx, PP_EINVAL, "too many work chunks; raise chunk_size");
   drop_graph(b);
-  pp_status st = upload(ctx, &b.d_chunks, ch);
+  pp_status st = pool_upload(ctx, &b.d_chunks, ch);
   if (st != PP_OK) return st;
   b.n_chunks = static_cast<uint32_t>(ch.size());
   b.chunk_size = chunk;
@@ -237,10 +317,13 @@ pp_status build_chunks(pp_context *ctx, Batch &b, uint32_t chunk) {
 
 pp_status alloc_hits(pp_context *ctx, Batch &b, uint64_t cap) {
   drop_graph(b);
-  (void)hipFree(b.d_hits);
+  pool_free(ctx, b.d_hits);
   b.d_hits = nullptr;
   b.hit_cap = 0;
-  PP_HIP(ctx, hipMalloc(reinterpret_cast<void **>(&b.d_hits), sizeof(pp::DevHit) * std::max<uint64_t>(cap, 1)));
+  void *p = nullptr;
+  pp_status st = pool_alloc(ctx, &p, sizeof(pp::DevHit) * std::max<uint64_t>(cap, 1));
+  if (st != PP_OK) return st;
+  b.d_hits = static_cast<pp::DevHit *>(p);
   b.hit_cap = cap;
   return PP_OK;
 }
@@ -248,7 +331,8 @@ pp_status alloc_hits(pp_context *ctx, Batch &b, uint64_t cap) {
 pp_status alloc_records(pp_context *ctx, Batch &b) {
   if (b.d_rec) return PP_OK;
   const uint64_t n = std::max<uint64_t>(b.n_photons, 1);
-  PP_HIP(ctx, hipMalloc(&b.d_rec, 48 * n));
+  pp_status st = pool_alloc(ctx, &b.d_rec, 48 * n);
+  if (st != PP_OK) return st;
   char *base = static_cast<char *>(b.d_rec);
   uint32_t **u[] = {&b.rec.fate, &b.rec.dom, &b.rec.n_iter, &b.rec.n_cross};
   float **f[] = {&b.rec.t, &b.rec.x, &b.rec.y, &b.rec.z, &b.rec.vx, &b.rec.vy, &b.rec.vz, &b.rec.wavelength};
@@ -293,8 +377,11 @@ pp_status prepare(pp_context *ctx, Batch &b, Prepared *out) {
   // no more workgroups than there are chunks to share among their wavefronts
   grid = static_cast<uint32_t>(std::min<uint64_t>(
       grid, std::max<uint64_t>(1, (static_cast<uint64_t>(b.n_chunks) * 64 + block - 1) / block)));
-  if (!b.d_counters)
-    PP_HIP(ctx, hipMalloc(reinterpret_cast<void **>(&b.d_counters), sizeof(unsigned long long) * pp::kNumCounters));
+  if (!b.d_counters) {
+    void *p = nullptr;
+    if ((st = pool_alloc(ctx, &p, sizeof(unsigned long long) * pp::kNumCounters)) != PP_OK) return st;
+    b.d_counters = static_cast<unsigned long long *>(p);
+  }
   if (!b.d_hits) {
     const uint64_t cap = c.hit_capacity ? c.hit_capacity : default_hit_capacity(b.n_photons);
     st = alloc_hits(ctx, b, cap);
@@ -538,7 +625,9 @@ void pp_destroy(pp_context *ctx) {
   if (!ctx) return;
   if (ctx->device >= 0) {
     (void)hipSetDevice(ctx->device);
-    for (auto &kv : ctx->batches) free_batch(kv.second);
+    for (auto &kv : ctx->batches) free_batch(ctx, kv.second);
+    for (auto &kv : ctx->pool_free)
+      for (void *p : kv.second) (void)hipFree(p);
     (void)hipFree(ctx->d_layers);
     (void)hipFree(ctx->d_bounds);
     (void)hipFree(ctx->d_strings);
@@ -742,9 +831,9 @@ pp_status pp_submit(pp_context *ctx, const pp_source *src, uint32_t n, uint64_t 
   if (ctx->device >= 0) {
     pp_status st = need_device(ctx);
     if (st != PP_OK) return st;
-    st = upload(ctx, &b.d_src, b.src);
+    st = pool_upload(ctx, &b.d_src, b.src);
     if (st != PP_OK) {
-      free_batch(b);
+      free_batch(ctx, b);
       return st;
     }
   }
@@ -760,7 +849,7 @@ pp_status pp_release(pp_context *ctx, uint64_t batch) {
   pp_status st = find_batch(ctx, batch, &b);
   if (st != PP_OK) return st;
   if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
-  free_batch(*b);
+  free_batch(ctx, *b);
   ctx->batches.erase(batch);
   return PP_OK;
 }
@@ -810,9 +899,11 @@ pp_status pp_fetch_hits_device(pp_context *ctx, uint64_t batch, void *dev_out, u
   if ((st = complete_hits(ctx, *b, &n)) != PP_OK) return st;
   *n_total = n;
   const uint64_t m = std::min(n, cap);
-  if (m > 0)
+  if (m > 0) {
     PP_HIP(ctx, hipMemcpyAsync(dev_out, b->d_hits, sizeof(pp_hit) * m, hipMemcpyDeviceToDevice,
                                static_cast<hipStream_t>(hip_stream)));
+    if ((st = note_use(ctx, *b, static_cast<hipStream_t>(hip_stream))) != PP_OK) return st;
+  }
   return n > cap ? fail(ctx, PP_ETRUNC, "%llu hits, buffer holds %llu", (unsigned long long)n,
                         (unsigned long long)cap)
                  : PP_OK;
@@ -827,7 +918,7 @@ pp_status pp_dom_counts(pp_context *ctx, uint64_t batch, uint32_t *dev_counts, v
   if (!b->propagated) return fail(ctx, PP_ESTATE, "batch not propagated");
   PP_HIP(ctx, pp::launch_dom_histogram(b->d_hits, b->d_counters + pp::kHitCount, b->hit_cap, dev_counts,
                                        ctx->n_doms, static_cast<hipStream_t>(hip_stream)));
-  return PP_OK;
+  return note_use(ctx, *b, static_cast<hipStream_t>(hip_stream));
 }
 
 pp_status pp_fetch_records(pp_context *ctx, uint64_t batch, pp_photon_record *out, uint64_t first,

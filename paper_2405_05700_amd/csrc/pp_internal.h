@@ -34,6 +34,7 @@ struct Batch {
   bool propagated = false, rec_valid = false;
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev_use = nullptr;  // after the last other enqueued work that reads the batch's buffers
   pp_launch_config used{};
   hipGraphExec_t graph = nullptr;  // captured reset + propagation, if any
   pp_launch_config graph_cfg{};
@@ -74,6 +75,12 @@ struct pp_context {
   std::vector<float> acc_table, acc_poly;
   float acc_l0 = 0, acc_dl = 1;
   float *d_acc = nullptr;
+  // caching allocator of batch buffers: blocks up to kPoolMaxBlock bytes in
+  // power-of-two size classes, reused instead of freed (hipFree waits for
+  // the whole device), up to kPoolCacheBytes cached
+  std::map<size_t, std::vector<void *>> pool_free;
+  std::map<void *, size_t> pool_live;
+  size_t pool_cached = 0;
   // batches
   std::map<uint64_t, ppi::Batch> batches;
   uint64_t next_batch = 1;

@@ -42,8 +42,10 @@ struct pp_surrogate {
   float *g_lab[6] = {};
   uint64_t shuffle_seed = 0;
   uint64_t epochs_done = 0;
-  // inference buffers (capacity Icap rows)
-  int64_t Icap = 0;
+  // inference buffers (capacity Icap rows; photons per source, capacity
+  // NScap, kept between calls so inference allocates nothing once warm)
+  int64_t Icap = 0, NScap = 0;
+  float *i_src_nph = nullptr;
   float *i_mu = nullptr;
 };
 
@@ -343,9 +345,13 @@ pp_status infer(pp_surrogate *s, Batch &b, hipStream_t st, double *dom_sums, Sin
   const int64_t n_src = static_cast<int64_t>(b.src.size());
   pp_status rc = PP_OK;
   const std::vector<float> nph = source_photons(b);
-  float *d_src_nph = nullptr;
-  if ((rc = dalloc(ctx, &d_src_nph, static_cast<int64_t>(nph.size()))) != PP_OK) return rc;
-  if (!nph.empty()) PP_HIP(ctx, hipMemcpy(d_src_nph, nph.data(), sizeof(float) * nph.size(), hipMemcpyHostToDevice));
+  if (static_cast<int64_t>(nph.size()) > s->NScap) {
+    if ((rc = dalloc(ctx, &s->i_src_nph, static_cast<int64_t>(nph.size()))) != PP_OK) return rc;
+    s->NScap = static_cast<int64_t>(nph.size());
+  }
+  float *d_src_nph = s->i_src_nph;
+  if (!nph.empty())
+    PP_HIP(ctx, hipMemcpyAsync(d_src_nph, nph.data(), sizeof(float) * nph.size(), hipMemcpyHostToDevice, st));
   FusedArgs a{};
   a.f = feature_args(s, b, d_src_nph);
   for (int l = 0; l < kLayers; ++l) {
@@ -359,10 +365,7 @@ pp_status infer(pp_surrogate *s, Batch &b, hipStream_t st, double *dom_sums, Sin
   if (pair_sink) {
     const int64_t cap = per_launch * s->n_doms;
     if (cap > s->Icap) {
-      if ((rc = dalloc(ctx, &s->i_mu, cap)) != PP_OK) {
-        dfree(d_src_nph);
-        return rc;
-      }
+      if ((rc = dalloc(ctx, &s->i_mu, cap)) != PP_OK) return rc;
       s->Icap = cap;
     }
     a.pair_mu = s->i_mu;
@@ -378,8 +381,7 @@ pp_status infer(pp_surrogate *s, Batch &b, hipStream_t st, double *dom_sums, Sin
     }
     if (pair_sink) rc = (*pair_sink)(s->i_mu, s0, ns);
   }
-  (void)hipStreamSynchronize(st);
-  dfree(d_src_nph);
+  (void)hipStreamSynchronize(st);  // also keeps nph alive until its copy has run
   return rc;
 }
 
@@ -440,7 +442,7 @@ void pp_sur_destroy(pp_surrogate *s) {
   dfree(s->k), dfree(s->n_t), dfree(s->s1), dfree(s->s2);
   for (int l = 0; l < 4; ++l) dfree(s->Z[l]), dfree(s->H[l]), dfree(s->HT[l]);
   dfree(s->Y), dfree(s->dY), dfree(s->dYT), dfree(s->dZ[0]), dfree(s->dZ[1]), dfree(s->dZT), dfree(s->d_loss);
-  dfree(s->i_mu);
+  dfree(s->i_mu), dfree(s->i_src_nph);
   dfree(s->gX), dfree(s->gXT);
   for (auto &p : s->g_lab) dfree(p);
   delete s;

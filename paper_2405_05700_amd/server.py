@@ -72,6 +72,7 @@ class Server:
         self._h = h
         self.ctx = ctx
         self.n_doms = ctx.n_doms
+        self.has_surrogate = surrogate is not None
 
     def close(self):
         if self._h:
@@ -95,13 +96,14 @@ class Server:
         self._check(_lib.pp_server_submit(self._h, sources.ctypes.data, len(sources), C.byref(t)))
         return t.value
 
-    def wait(self, ticket: int, cap: int = 1 << 16, expected: bool = False):
+    def wait(self, ticket: int, cap: int = 256, expected: bool = False):
         """Blocks until the request is done; returns (hits, info dict,
-        per-module expected hits or None)."""
+        per-module expected hits or None). A request with more than cap hits
+        is fetched again with a buffer of its exact size."""
         while True:
-            out = np.zeros(cap, pp.HIT_DTYPE)
+            out = np.empty(cap, pp.HIT_DTYPE)
             info = RequestInfo()
-            dom = np.zeros(self.n_doms, np.float32) if expected else None
+            dom = np.empty(self.n_doms, np.float32) if expected and self.has_surrogate else None
             st = _lib.pp_server_wait(self._h, ticket, out.ctypes.data, cap,
                                      dom.ctypes.data if dom is not None else None, C.byref(info))
             if st == pp.PP_ETRUNC:
