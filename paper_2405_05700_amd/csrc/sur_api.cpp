@@ -71,7 +71,7 @@ void dfree(T *&p) {
 
 pp_status gemm(pp_context *ctx, int epi, const uint16_t *A, int64_t lda, const uint16_t *B, int64_t ldb, int M,
                int N, int K, int splits, const float *bias, float *Z, uint16_t *H, uint16_t *HT, int64_t ldt,
-               const float *Zin, float *out, hipStream_t st) {
+               const float *Zin, float *out, hipStream_t st, float *col_sums = nullptr) {
   sur::GemmArgs g{};
   g.A = A;
   g.lda = lda;
@@ -90,6 +90,7 @@ pp_status gemm(pp_context *ctx, int epi, const uint16_t *A, int64_t lda, const u
   g.ldt = ldt;
   g.Zin = Zin;
   g.out = out;
+  g.col_sums = col_sums;
   PP_HIP(ctx, sur::launch_gemm(epi, g, splits, st));
   return PP_OK;
 }
@@ -164,6 +165,7 @@ pp_status forward_backward(pp_surrogate *s, const Rows &r, int64_t count, hipStr
     return rc;
   // loss and output gradient
   PP_HIP(ctx, launch_zero_f64(s->d_loss, 1, st));
+  PP_HIP(ctx, launch_zero_f32(s->grad, param_count(), st));  // the loss and GELU-backward kernels add bias gradients
   LossArgs la{};
   la.Y = s->Y;
   la.mu_base = r.mu_base;
@@ -179,32 +181,31 @@ pp_status forward_backward(pp_surrogate *s, const Rows &r, int64_t count, hipStr
   la.dYT = s->dYT;
   la.loss_sum = s->d_loss;
   la.loss_epoch = s->epoch_loss;
+  la.out_bias_grad = s->grad + b_offset(4);
   PP_HIP(ctx, launch_loss(la, st));
   // backward
-  PP_HIP(ctx, launch_zero_f32(s->grad, param_count(), st));
   const int splits = std::max(1, M / 512);
   // output layer
   if ((rc = gemm(ctx, kEpiAccum, s->dYT, M, s->HT[3], M, kOutPad, kHidden, M, splits, nullptr, nullptr, nullptr,
                  nullptr, 0, nullptr, s->grad + w_offset(4), st)) != PP_OK)
     return rc;
-  PP_HIP(ctx, launch_rowsum(s->dYT, M, kOutPad, M, s->grad + b_offset(4), st));
-  // dZ3 = (dY . W4) * gelu'(Z3)
+  // dZ3 = (dY . W4) * gelu'(Z3), and db3 = column sums of dZ3
   if ((rc = gemm(ctx, kEpiGeluBwd, s->dY, kOutPad, wt_ptr(s, 4), kOutPad, M, kHidden, kOutPad, 1, nullptr,
-                 nullptr, s->dZ[1], s->dZT, M, s->Z[3], nullptr, st)) != PP_OK)
+                 nullptr, s->dZ[1], s->dZT, M, s->Z[3], nullptr, st, s->grad + b_offset(3))) != PP_OK)
     return rc;
   int cur = 1;
   for (int l = 3; l >= 0; --l) {
-    // dW_l = dZ_l^T . H_{l-1} (X for l = 0), db_l = row sums of dZ_l^T
+    // dW_l = dZ_l^T . H_{l-1} (X for l = 0); db_l came with dZ_l
     const uint16_t *prevT = l > 0 ? s->HT[l - 1] : XT;
     const int64_t ld_prevT = l > 0 ? M : r.ld_XT;
     if ((rc = gemm(ctx, kEpiAccum, s->dZT, M, prevT, ld_prevT, kHidden, in_dim(l), M, splits, nullptr, nullptr,
                    nullptr, nullptr, 0, nullptr, s->grad + w_offset(l), st)) != PP_OK)
       return rc;
-    PP_HIP(ctx, launch_rowsum(s->dZT, M, kHidden, M, s->grad + b_offset(l), st));
     if (l == 0) break;
-    // dZ_{l-1} = (dZ_l . W_l) * gelu'(Z_{l-1})
+    // dZ_{l-1} = (dZ_l . W_l) * gelu'(Z_{l-1}), and its column sums db_{l-1}
     if ((rc = gemm(ctx, kEpiGeluBwd, s->dZ[cur], kHidden, wt_ptr(s, l), kHidden, M, kHidden, kHidden, 1, nullptr,
-                   nullptr, s->dZ[1 - cur], s->dZT, M, s->Z[l - 1], nullptr, st)) != PP_OK)
+                   nullptr, s->dZ[1 - cur], s->dZT, M, s->Z[l - 1], nullptr, st, s->grad + b_offset(l - 1))) !=
+        PP_OK)
       return rc;
     cur = 1 - cur;
   }

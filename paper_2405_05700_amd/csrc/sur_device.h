@@ -58,6 +58,7 @@ struct GemmArgs {
   int64_t ldt;
   const float *Zin;  // saved pre-activation for kEpiGeluBwd (ld N)
   float *out;        // kEpiAccum: f32 M x N (ld N)
+  float *col_sums;   // kEpiGeluBwd: += column sums of the stored bf16 output (bias gradient), may be null
 };
 
 struct FeatureArgs {
@@ -87,6 +88,7 @@ struct LossArgs {
   uint16_t *dYT;         // bf16 64 x M_pad
   double *loss_sum;
   double *loss_epoch;    // also accumulated into, if not null
+  float *out_bias_grad;  // += column sums of the stored bf16 dY (the output-layer bias gradient), may be null
 };
 
 // Copies training rows p(r) = (mul * r + add) mod P, r in [first, first + count),
@@ -107,7 +109,6 @@ hipError_t launch_gemm(int epi, const GemmArgs &g, int splits, hipStream_t s);
 hipError_t launch_gather(const GatherArgs &g, hipStream_t s);
 hipError_t launch_features(const FeatureArgs &f, hipStream_t s);
 hipError_t launch_loss(const LossArgs &l, hipStream_t s);
-hipError_t launch_rowsum(const uint16_t *XT, int64_t ld, int rows, int cols, float *out, hipStream_t s);
 hipError_t launch_adam(float *theta, const float *grad, float *m, float *v, int64_t n, float lr,
                        float c1, float c2, hipStream_t s);
 hipError_t launch_pack_weights(const float *theta, uint16_t *w_bf16, uint16_t *wt_bf16, hipStream_t s);

@@ -96,6 +96,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
   // Output layout of a 16 x 16 tile: lane holds rows 4 (lane / 16) + r,
   // r = 0..3, of column lane % 16.
   const f32x4 accs[4] = {acc00, acc01, acc10, acc11};
+  float csum[2] = {0.0f, 0.0f};  // kEpiGeluBwd: this lane's part of the column sums of the wave's 32 rows
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int i = t >> 1, j = t & 1;
@@ -124,6 +125,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
         const int64_t idx = (int64_t)(rbase + r) * g.N + col;
         h[r] = f2bf(v[r] * gelu_grad(g.Zin[idx]));
         g.H[idx] = h[r];
+        csum[j] += __uint_as_float((uint32_t)h[r] << 16);
       }
       const uint2 packed = make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
       *reinterpret_cast<uint2 *>(g.HT + (int64_t)col * g.ldt + rbase) = packed;
@@ -134,6 +136,17 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
       const float b = g.bias[col];
 #pragma unroll
       for (int r = 0; r < 4; ++r) g.out[(int64_t)(rbase + r) * g.N + col] = v[r] + b;
+    }
+  }
+  if (EPI == kEpiGeluBwd && g.col_sums) {
+    // lanes l, l + 16, l + 32, l + 48 hold the same column: sum them, then
+    // one atomic per column of the wave's 32 x 32 block
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      float cs = csum[j];
+      cs += __shfl_xor(cs, 16, 64);
+      cs += __shfl_xor(cs, 32, 64);
+      if (lane < 16) atomicAdd(&g.col_sums[col0 + j * 16 + lane], cs);
     }
   }
 }
@@ -230,6 +243,7 @@ __global__ void k_features(const FeatureArgs f, int64_t n_rows) {
 __global__ void __launch_bounds__(256) k_loss(const LossArgs l) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   double part = 0.0;
+  float bsum[3] = {0.0f, 0.0f, 0.0f};
   if (m < l.M_pad) {
     float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
     if (m < l.M_real) {
@@ -260,33 +274,28 @@ __global__ void __launch_bounds__(256) k_loss(const LossArgs l) {
     l.dYT[(int64_t)l.M_pad + m] = f2bf(g1);
     l.dYT[2 * (int64_t)l.M_pad + m] = f2bf(g2);
     for (int q = kOutReal; q < kOutPad; ++q) l.dYT[(int64_t)q * l.M_pad + m] = 0;
+    bsum[0] = __uint_as_float((uint32_t)row[0] << 16);
+    bsum[1] = __uint_as_float((uint32_t)row[1] << 16);
+    bsum[2] = __uint_as_float((uint32_t)row[2] << 16);
   }
   __shared__ double red[256];
+  __shared__ float bred[3][256];
   red[threadIdx.x] = part;
+  for (int q = 0; q < 3; ++q) bred[q][threadIdx.x] = bsum[q];
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    if ((int)threadIdx.x < o) {
+      red[threadIdx.x] += red[threadIdx.x + o];
+      for (int q = 0; q < 3; ++q) bred[q][threadIdx.x] += bred[q][threadIdx.x + o];
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     atomicAdd(l.loss_sum, red[0]);
     if (l.loss_epoch) atomicAdd(l.loss_epoch, red[0]);
+    if (l.out_bias_grad)
+      for (int q = 0; q < 3; ++q) atomicAdd(&l.out_bias_grad[q], bred[q][0]);
   }
-}
-
-// out[r] = sum over columns of the bf16 matrix row r (one workgroup per row).
-__global__ void __launch_bounds__(256) k_rowsum(const uint16_t *XT, int64_t ld, int cols, float *out) {
-  const uint16_t *row = XT + blockIdx.x * ld;
-  float s = 0.0f;
-  for (int c = threadIdx.x; c < cols; c += blockDim.x) s += __uint_as_float((uint32_t)row[c] << 16);
-  __shared__ float red[256];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 // Adam (Kingma & Ba) with bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t.
@@ -553,11 +562,6 @@ __global__ void __launch_bounds__(256) k_gather(const GatherArgs g) {
 
 hipError_t launch_gather(const GatherArgs &g, hipStream_t s) {
   hipLaunchKernelGGL(k_gather, dim3(blocks_for((int64_t)g.M * 72, 256)), dim3(256), 0, s, g);
-  return hipGetLastError();
-}
-
-hipError_t launch_rowsum(const uint16_t *XT, int64_t ld, int rows, int cols, float *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_rowsum, dim3(rows), dim3(256), 0, s, XT, ld, cols, out);
   return hipGetLastError();
 }
 
