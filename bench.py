@@ -86,6 +86,7 @@ def parse():
     ap.add_argument("--sur-train-rmax", type=float, default=25.0)
     ap.add_argument("--sur-epochs", type=int, default=48)
     ap.add_argument("--sur-ensemble", type=int, default=3)
+    ap.add_argument("--sur-batch", type=int, default=8192)
     ap.add_argument("--sur-lr", type=float, default=1e-3)
     ap.add_argument("--sur-lr-final", type=float, default=1e-5)
     ap.add_argument("--sur-infer-sources", type=int, default=100_000)
@@ -234,8 +235,8 @@ def surrogate_leg(args):
         m.set_training_set(b_tr)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        losses.append([float(x) for x in m.train(epochs=args.sur_epochs, batch_size=8192, lr=args.sur_lr,
-                                                 lr_final=args.sur_lr_final)])
+        losses.append([float(x) for x in m.train(epochs=args.sur_epochs, batch_size=args.sur_batch,
+                                                 lr=args.sur_lr, lr_final=args.sur_lr_final)])
         torch.cuda.synchronize()
         t_train += time.perf_counter() - t2
         members.append(m)
@@ -243,7 +244,8 @@ def surrogate_leg(args):
     n_pairs = sur.training_size()
     out.update({"train_sources": args.sur_train_sources, "train_photons_per_source": args.sur_train_photons,
                 "train_pairs": n_pairs, "label_mc_s": t1 - t0, "ensemble": args.sur_ensemble,
-                "train_epochs": args.sur_epochs, "train_lr": [args.sur_lr, args.sur_lr_final],
+                "train_epochs": args.sur_epochs, "train_batch": args.sur_batch,
+                "train_lr": [args.sur_lr, args.sur_lr_final],
                 "train_s": t_train,
                 "train_pairs_per_s": n_pairs * args.sur_epochs * args.sur_ensemble / t_train,
                 "epoch_loss_last": [l[-1] for l in losses]})

@@ -85,13 +85,20 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
   const uint16_t *a1 = a0 + 16 * g.lda;
   const uint16_t *b0 = g.B + (int64_t)(col0 + lr) * g.ldb + lk;
   const uint16_t *b1 = b0 + 16 * g.ldb;
+  // The operands of step k + 32 are loaded before the products of step k,
+  // so one step of loads is always in flight (the last step reloads its own
+  // operands, which stay in bounds).
+  bf16x8 va0 = load8(a0 + kbeg), va1 = load8(a1 + kbeg);
+  bf16x8 vb0 = load8(b0 + kbeg), vb1 = load8(b1 + kbeg);
   for (int k = kbeg; k < kend; k += 32) {
-    const bf16x8 va0 = load8(a0 + k), va1 = load8(a1 + k);
-    const bf16x8 vb0 = load8(b0 + k), vb1 = load8(b1 + k);
+    const int kn = k + 32 < kend ? k + 32 : k;
+    const bf16x8 na0 = load8(a0 + kn), na1 = load8(a1 + kn);
+    const bf16x8 nb0 = load8(b0 + kn), nb1 = load8(b1 + kn);
     acc00 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va0, vb0, acc00, 0, 0, 0);
     acc01 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va0, vb1, acc01, 0, 0, 0);
     acc10 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va1, vb0, acc10, 0, 0, 0);
     acc11 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va1, vb1, acc11, 0, 0, 0);
+    va0 = na0, va1 = na1, vb0 = nb0, vb1 = nb1;
   }
   // Output layout of a 16 x 16 tile: lane holds rows 4 (lane / 16) + r,
   // r = 0..3, of column lane % 16.
