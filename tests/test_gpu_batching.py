@@ -135,3 +135,40 @@ def test_full_uneven_spectrum_conserves_photons(pp):
     assert len(hits) == st["hits"]
     assert set(np.unique(hits["event_id"])) <= set(w.sources["event_id"].tolist())
     torch.cuda.synchronize()
+
+
+def test_reused_batch_memory_gives_identical_results(pp):
+    """Released batches hand their device buffers back to the context's
+    cache and later batches reuse them (no hipFree between batches): many
+    submit / propagate / fetch / release rounds of differently sized events
+    give exactly the hits of a fresh context, including after a device-side
+    fetch and a histogram on another stream."""
+    import torch
+    w = small_uneven(24, seed=5)
+    ref = {}
+    for i in range(len(w.sources)):
+        ctx = pp.Context(0, seed=0)
+        ctx.load_workload(w)
+        b = ctx.submit(w.sources[i:i + 1])
+        ctx.propagate(b)
+        ref[i] = np.sort(ctx.fetch_hits(b), order=["event_id", "photon_index"])
+        ctx.close()
+    ctx = pp.Context(0, seed=0)
+    ctx.load_workload(w)
+    s = torch.cuda.Stream()
+    counts = torch.empty(len(w.doms), dtype=torch.int32, device="cuda:0")
+    for rnd in range(3):
+        for i in np.random.default_rng(rnd).permutation(len(w.sources)):
+            b = ctx.submit(w.sources[i:i + 1])
+            ctx.propagate(b, s)
+            ctx.dom_counts(b, counts, s)
+            dev = torch.empty(32 * (len(ref[i]) + 16), dtype=torch.uint8, device="cuda:0")
+            n_dev = ctx.fetch_hits_device(b, dev, stream=s)
+            got = np.sort(ctx.fetch_hits(b), order=["event_id", "photon_index"])
+            ctx.release(b)  # waits for the stream work above before recycling
+            torch.cuda.synchronize()
+            assert len(got) == len(ref[i]) and (got == ref[i]).all(), (rnd, i)
+            assert int(counts.sum().item()) == len(ref[i]) and n_dev == len(ref[i])
+            d = np.sort(dev[:32 * n_dev].cpu().numpy().view(pp.HIT_DTYPE), order=["event_id", "photon_index"])
+            assert (d == ref[i]).all()
+    ctx.close()
