@@ -112,7 +112,8 @@ typedef struct {
 
 /* Hit (Sec. 4: the compact record keeps the producing particle's id, the
  * hit time and a weight; the event id, photon index and module id identify
- * it). weight is 1: the paper gives no photoelectron-probability formula. */
+ * it). weight is 1 unless an acceptance is set with pp_set_acceptance (the
+ * paper gives no photoelectron-probability formula). */
 typedef struct {
   uint64_t photon_index;
   uint32_t event_id;
@@ -175,8 +176,9 @@ typedef struct {
  * PP_EDEVICE. *out receives the context; on failure *out is NULL. */
 pp_status pp_create(int hip_device, uint64_t seed, pp_context **out);
 
-/* Frees the context and all its device memory; NULL is a no-op. Synchronises
- * the streams of pending batches first. */
+/* Frees the context and all its device memory (including cached batch
+ * buffers); NULL is a no-op. Synchronises the streams of pending batches
+ * first. */
 void pp_destroy(pp_context *ctx);
 
 /* Message of the last error on ctx (NULL ctx: last pp_create failure).
@@ -224,7 +226,10 @@ pp_status pp_geometry_cell(const pp_context *ctx, float x, float y, uint32_t *ne
 pp_status pp_submit(pp_context *ctx, const pp_source *sources, uint32_t n_sources,
                     uint64_t *batch_out);
 
-/* Frees a batch's device memory. */
+/* Releases a batch. Its device buffers go back to the context's cache for
+ * later batches (blocks up to 256 MB, at most 8 GB cached; larger ones are
+ * freed), after waiting for the batch's propagation and for any device
+ * fetch or count it enqueued; work on other streams is not waited for. */
 pp_status pp_release(pp_context *ctx, uint64_t batch);
 
 /* Wavelength dependence of the ice (Sec. 2, photon-propagation paragraph:
@@ -296,7 +301,9 @@ pp_status pp_dom_counts(pp_context *ctx, uint64_t batch, uint32_t *dev_counts, v
 
 /* Copies terminal records first .. first + count - 1 of the batch (photons
  * numbered in submission order: source by source, index by index) into
- * host memory out. Needs debug records on when the batch was propagated. */
+ * host memory out. Needs debug records on when the batch was propagated.
+ * wavelength_nm is the photon's drawn wavelength (the debug-record kernel
+ * always draws it). */
 pp_status pp_fetch_records(pp_context *ctx, uint64_t batch, pp_photon_record *out,
                            uint64_t first, uint64_t count);
 
