@@ -83,11 +83,11 @@ def test_cosine_acceptance_of_a_lit_sphere(beam):
 
 
 def test_acceptance_table_interpolates_in_wavelength(beam):
-    w = W.dataclasses.replace(beam, acceptance={"l0": 300.0, "dl": 210.0, "table": [1.0, 3.0, 0.5],
+    w = W.dataclasses.replace(beam, acceptance={"l0": 300.0, "dl": 150.0, "table": [1.0, 3.0, 0.5],
                                                 "poly": [1.0]})
     r = pyoracle.run(w, sel_src=np.zeros(200_000, np.uint64), sel_local=np.arange(200_000, dtype=np.uint64),
                      dom_mode=1)
     hit = r.fate == pyoracle.FATE_HIT
     assert hit.any()
-    # 405 nm lies half way between the first two table points
-    assert np.allclose(r.weight[hit], 2.0, rtol=1e-12)
+    # 405 nm lies 0.7 of the way from the first table point to the second
+    assert np.allclose(r.weight[hit], 1.0 * 0.3 + 3.0 * 0.7, rtol=1e-12)
