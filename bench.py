@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 # the issue rates measured on gfx950 relative to v_fma_f32. Counts of the
 # arithmetic each unit needs in the FP32 formulation, in gfx950 operations
 # (a three-input xor is one v_bitop3_b32):
-SLOTS_PER_STEP = 240        # one propagation step (Philox block 101 of it)
+SLOTS_PER_STEP = 254        # one propagation step (Philox block 101 of it)
 SLOTS_PER_CROSSING = 28     # each extra layer of the layer walk
 SLOTS_PER_DOM_TEST = 32     # each ray-sphere test
 SLOTS_PER_PHOTON = 185      # emission pass (Philox block 0, cone rotation, setup)
@@ -475,7 +475,6 @@ def main():
              + SLOTS_PER_CROSSING * st["layer_crossings"] + SLOTS_PER_DOM_TEST * st["dom_tests"])
     achieved = slots / avg_s
     value = n_photons * args.steps / elapsed
-    cfg = ctx.launch_config()
     out = {
         "metric": "photons propagated/s on 1 MI355X; surrogate+MC speedup at \u22642% per-DOM hit error",
         "value": value,
@@ -493,8 +492,8 @@ def main():
                                f"{len(w.sources)} Cherenkov segments x {args.photons_per_source} "
                                "photons",
                    "photons_per_step": n_photons, "seed": 0,
-                   "block_size": cfg["block_size"], "chunk_size": args.chunk_size or "auto",
-                   "refill_interval": cfg["refill_interval"],
+                   "block_size": st["block_size"], "grid_blocks": st["grid_blocks"],
+                   "chunk_size": st["chunk_size"], "refill_interval": st["refill_interval"],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "T lane-slots/s", "frac": achieved / PEAK_SLOTS,

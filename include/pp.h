@@ -149,13 +149,17 @@ typedef struct {
   uint64_t dom_tests;       /* ray-sphere tests performed */
   uint64_t hits, absorbed, capped, escaped;
   float kernel_ms;          /* device time of the propagation kernel */
-  uint32_t reserved;
+  uint32_t block_size;      /* launch actually used: threads per workgroup, */
+  uint32_t grid_blocks;     /*   workgroups, */
+  uint32_t chunk_size;      /*   photon ids per queue grab, */
+  uint32_t refill_interval; /*   passes between refills */
 } pp_stats;
 
 /* Launch parameters. They change speed only, never results. Zero picks the
  * default. */
 typedef struct {
-  uint32_t block_size;  /* threads per workgroup, multiple of 64, <= 1024 (default 256) */
+  uint32_t block_size;  /* threads per workgroup, multiple of 64, <= 1024 (default 256, or larger
+                           when the modules are staged in LDS, so that a CU runs 24 wavefronts) */
   uint32_t chunk_size;  /* photon ids taken per queue grab by one wavefront (default 256) */
   uint32_t grid_blocks; /* workgroups launched (default: enough to fill every CU) */
   uint32_t refill_interval; /* passes between refills of a wavefront's ended lanes
@@ -319,7 +323,7 @@ pp_status pp_get_stats(pp_context *ctx, uint64_t batch, pp_stats *out);
  * 1e3-photon event share the device without imbalance. */
 
 /* Times the batch under a fixed set of launch configurations (workgroup
- * size 256/512, chunk size 64/256/1024, refill interval 2/4/8), each one
+ * size 256/512/1024, chunk size 64/256/1024, refill interval 2/4/8), each one
  * full propagation on hip_stream, and keeps the fastest as the context's
  * launch configuration (also written to *best if non-NULL). Results do not
  * change; only speed does. Synchronises the stream. */

@@ -181,6 +181,7 @@ void build_geometry(pp_context *ctx, const pp_dom *doms, uint32_t n, float radiu
   ctx->strings.clear();
   ctx->cells.clear();
   ctx->doms_sorted.clear();
+  ctx->vertical_strings = true;
   std::map<uint32_t, std::vector<uint32_t>> by_string;
   for (uint32_t k = 0; k < n; ++k) by_string[doms[k].string_id].push_back(k);
   std::vector<double> cx, cy, reach;
@@ -217,6 +218,8 @@ void build_geometry(pp_context *ctx, const pp_dom *doms, uint32_t n, float radiu
     // rounding of positions up to a few km
     st.xy_reach_z0 = make_float4(static_cast<float>(sx), static_cast<float>(sy),
                                  static_cast<float>(rch + 0.01), static_cast<float>(z0));
+    for (uint32_t k : ids)
+      if (doms[k].x != st.xy_reach_z0.x || doms[k].y != st.xy_reach_z0.y) ctx->vertical_strings = false;
     for (uint32_t k : ids) {
       uint32_t bits = k;
       float fid;
@@ -351,17 +354,27 @@ struct Prepared {
 // fills the kernel arguments. No work is enqueued.
 pp_status prepare(pp_context *ctx, Batch &b, Prepared *out) {
   const pp_launch_config &c = ctx->cfg;
-  const uint32_t block = c.block_size ? c.block_size : default_block();
-  const size_t lds = pp::propagate_lds_bytes(static_cast<int>(ctx->ice.n_layers),
-                                             static_cast<int>(ctx->strings.size()),
-                                             static_cast<int>(ctx->geo.grid_nx * ctx->geo.grid_ny));
+  // With vertical strings each module's (z, id) joins the LDS tables when
+  // everything fits; a CU then holds fewer workgroups, so the default
+  // workgroup grows to keep 24 wavefronts per CU.
+  const int n_layers = static_cast<int>(ctx->ice.n_layers), n_strings = static_cast<int>(ctx->strings.size());
+  const int n_cells = static_cast<int>(ctx->geo.grid_nx * ctx->geo.grid_ny);
+  const size_t with_doms = pp::propagate_lds_bytes(n_layers, n_strings, n_cells, static_cast<int>(ctx->n_doms));
+  const bool lds_doms = ctx->n_doms > 0 && ctx->vertical_strings && with_doms <= pp::kMaxPropagateLds;
+  const size_t lds = lds_doms ? with_doms : pp::propagate_lds_bytes(n_layers, n_strings, n_cells, 0);
+  uint32_t block = c.block_size;
+  if (block == 0) {
+    const size_t per_cu = std::max<size_t>(1, (160 * 1024) / std::max<size_t>(lds, 1));
+    const size_t waves = (24 + per_cu - 1) / per_cu;
+    block = static_cast<uint32_t>(std::min<size_t>(1024, std::max<size_t>(default_block(), 64 * waves)));
+  }
   uint32_t grid = c.grid_blocks;
   if (grid == 0) {
     int per_cu = 0;
     const bool wave = (ctx->chroma.lambda_ref_nm > 0 &&
                        (ctx->chroma.kappa_abs != 0.0f || ctx->chroma.kappa_scat != 0.0f)) ||
                       !ctx->acc_table.empty();
-    PP_HIP(ctx, pp::propagate_occupancy(ctx->records, wave, static_cast<int>(block), lds, &per_cu));
+    PP_HIP(ctx, pp::propagate_occupancy(ctx->records, wave, lds_doms, static_cast<int>(block), lds, &per_cu));
     grid = static_cast<uint32_t>(std::max(per_cu, 1) * std::max(ctx->n_cu, 1));
   }
   // Default chunk: 256 ids (measured best on the full detector), smaller
@@ -412,6 +425,8 @@ pp_status prepare(pp_context *ctx, Batch &b, Prepared *out) {
   a.nx_max = static_cast<float>(a.nx - 1);
   a.ny_max = static_cast<float>(a.ny - 1);
   a.doms = ctx->d_doms;
+  a.n_doms = static_cast<int>(ctx->n_doms);
+  a.lds_doms = lds_doms ? 1 : 0;
   a.radius = ctx->radius;
   a.radius2 = ctx->radius * ctx->radius;
   a.sources = b.d_src;
@@ -976,7 +991,10 @@ pp_status pp_get_stats(pp_context *ctx, uint64_t batch, pp_stats *out) {
   float ms = 0;
   PP_HIP(ctx, hipEventElapsedTime(&ms, b->ev0, b->ev1));
   out->kernel_ms = ms;
-  out->reserved = 0;
+  out->block_size = b->used.block_size;
+  out->grid_blocks = b->used.grid_blocks;
+  out->chunk_size = b->used.chunk_size;
+  out->refill_interval = b->used.refill_interval;
   return PP_OK;
 }
 
@@ -990,7 +1008,7 @@ pp_status pp_autotune(pp_context *ctx, uint64_t batch, void *hip_stream, pp_laun
   const pp_launch_config base = ctx->cfg;
   pp_launch_config winner = base;
   float best_ms = -1.0f;
-  const uint32_t blocks[] = {256, 512};
+  const uint32_t blocks[] = {256, 512, 1024};
   const uint32_t chunks[] = {64, 256, 1024};
   const uint32_t refills[] = {2, 4, 8};
   bool first = true;

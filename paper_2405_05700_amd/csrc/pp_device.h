@@ -90,6 +90,8 @@ struct PropagateArgs {
   int nx, ny;
   float gx0, gy0, inv_cell, nx_max, ny_max;  // nx_max = nx - 1 as float
   const float4 *doms;  // sorted by string then z: x, y, z, module id (as bits)
+  int n_doms;
+  int lds_doms;        // 1: every string is vertical; the kernel stages each module's (z, id) in LDS
   float radius, radius2;
   // work
   const DevSource *sources;
@@ -116,14 +118,19 @@ struct PropagateArgs {
   Records rec;
 };
 
-// Dynamic LDS bytes the propagation kernel needs for these tables.
-size_t propagate_lds_bytes(int n_layers, int n_strings, int n_cells);
+// Dynamic LDS bytes the propagation kernel needs for these tables, plus
+// n_lds_doms staged (z, id) module records (8 bytes each, 8-byte aligned).
+size_t propagate_lds_bytes(int n_layers, int n_strings, int n_cells, int n_lds_doms);
+// Largest dynamic LDS a propagation launch may use (modules are staged in
+// LDS only if everything fits).
+constexpr size_t kMaxPropagateLds = 152 * 1024;
 
 hipError_t launch_reset(unsigned long long *counters, int n, hipStream_t stream);
 hipError_t launch_propagate(const PropagateArgs &args, int grid, int block, hipStream_t stream);
 // records: debug records on; wave: wavelength-dependent optics or hit
 // acceptance (the kernel variant that draws wavelengths).
-hipError_t propagate_occupancy(bool records, bool wave, int block, size_t lds_bytes, int *blocks_per_cu);
+hipError_t propagate_occupancy(bool records, bool wave, bool lds_doms, int block, size_t lds_bytes,
+                               int *blocks_per_cu);
 hipError_t launch_dom_histogram(const DevHit *hits, const unsigned long long *hit_count,
                                 unsigned long long hit_capacity, uint32_t *counts, uint32_t n_doms,
                                 hipStream_t stream);

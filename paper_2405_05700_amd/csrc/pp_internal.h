@@ -70,6 +70,7 @@ struct pp_context {
   uint32_t *d_cells = nullptr;
   float4 *d_doms = nullptr;
   float4 *d_doms_by_id = nullptr;  // module centres in module-id order
+  bool vertical_strings = false;   // every module sits exactly at its string's (x, y) centre
   // wavelength dependence and hit acceptance
   pp_chromatic chroma{};           // lambda_ref_nm 0: none
   std::vector<float> acc_table, acc_poly;

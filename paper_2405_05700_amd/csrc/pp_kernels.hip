@@ -116,15 +116,27 @@ __device__ __forceinline__ void test_module(const float4 m, const Segment &s, fl
   }
 }
 
-// Tests the modules of one string that the segment can reach: first a
-// horizontal reach check against the string centre, then the slots whose z
-// range overlaps the segment's (arithmetic for evenly spaced strings).
+// Tests the modules of one string that the segment can reach. First the
+// horizontal filter: the segment's projection on the horizontal plane must
+// pass within the string's reach (largest module offset from the axis + r +
+// margin) of the string's axis, a necessary condition for meeting any of its
+// spheres; then the slots whose z range overlaps the segment's (arithmetic
+// for evenly spaced strings). A module is read from the global table (x, y,
+// z, id), or, for a vertical string, rebuilt from the string centre and its
+// (z, id) pair in LDS.
+template <bool kLds>
 __device__ __forceinline__ void test_string(const DevString &st, const float4 *__restrict__ doms,
-                                            const Segment &s, float radius, float r2,
+                                            const float2 *zid, const Segment &s, float radius, float r2,
                                             float &best_t, uint32_t &best_id, uint32_t &tests) {
   const float dx = st.xy_reach_z0.x - s.px, dy = st.xy_reach_z0.y - s.py;
-  const float lim = __builtin_fmaf(s.len, 1.00001f, st.xy_reach_z0.z);
-  if (dx * dx + dy * dy > lim * lim) return;
+  // closest approach of the projected segment to the axis: t in [0, len]
+  // along v (a vertical segment stays at its start point)
+  const float hh = s.vx * s.vx + s.vy * s.vy;
+  const float proj = dx * s.vx + dy * s.vy;
+  const float tq = hh > 0.0f ? fminf(fmaxf(proj * __builtin_amdgcn_rcpf(hh), 0.0f), s.len) : 0.0f;
+  const float qx = __builtin_fmaf(-tq, s.vx, dx), qy = __builtin_fmaf(-tq, s.vy, dy);
+  const float reach = st.xy_reach_z0.z;
+  if (qx * qx + qy * qy > reach * reach) return;
   const float zend = __builtin_fmaf(s.len, s.vz, s.pz);
   const float zmin = fminf(s.pz, zend) - radius;  // fminf drops a NaN end (infinite flat step)
   const float zmax = fmaxf(s.pz, zend) + radius;
@@ -137,7 +149,12 @@ __device__ __forceinline__ void test_string(const DevString &st, const float4 *_
   const int khi = min((int)ceilf(fhi), st.n - 1);
   for (int k = klo; k <= khi; ++k) {
     ++tests;
-    test_module(doms[st.first + k], s, r2, best_t, best_id);
+    if (kLds) {
+      const float2 e = zid[st.first + k];
+      test_module(make_float4(st.xy_reach_z0.x, st.xy_reach_z0.y, e.x, e.y), s, r2, best_t, best_id);
+    } else {
+      test_module(doms[st.first + k], s, r2, best_t, best_id);
+    }
   }
 }
 
@@ -188,7 +205,11 @@ __device__ __forceinline__ float hit_weight(const PropagateArgs &a, uint32_t dom
 // kWave: the photon's wavelength matters (wavelength-dependent optics, hit
 // acceptance or debug records). Without it the kernel draws no wavelength
 // and scales nothing, and every hit weighs 1.
-template <bool kRecords, bool kWave>
+// kLdsDoms: every string is vertical, so a module is its string's centre
+// and a (z, id) pair, and the pairs of all modules are staged in LDS (8
+// bytes each): the ray-sphere tests of the few lanes near a string then read
+// LDS instead of stalling the whole wavefront on global memory.
+template <bool kRecords, bool kWave, bool kLdsDoms>
 __global__ void __launch_bounds__(1024)
 k_propagate(const PropagateArgs a) {
   static_assert(kWave || !kRecords, "records carry the wavelength");
@@ -201,6 +222,16 @@ k_propagate(const PropagateArgs a) {
   for (int i = threadIdx.x; i < a.n_strings; i += blockDim.x) s_strings[i] = a.strings[i];
   for (int i = threadIdx.x; i < a.nx * a.ny; i += blockDim.x) s_cells[i] = a.cells[i];
   for (int i = threadIdx.x; i <= a.n_layers; i += blockDim.x) s_bounds[i] = a.bounds[i];
+  float2 *s_zid = nullptr;
+  if (kLdsDoms) {
+    const size_t off = (static_cast<size_t>(reinterpret_cast<unsigned char *>(s_bounds + a.n_layers + 1) - lds_raw) +
+                        7) & ~static_cast<size_t>(7);
+    s_zid = reinterpret_cast<float2 *>(lds_raw + off);
+    for (int i = threadIdx.x; i < a.n_doms; i += blockDim.x) {
+      const float4 m = a.doms[i];
+      s_zid[i] = make_float2(m.z, m.w);
+    }
+  }
   __syncthreads();
 
   const uint32_t lane = __lane_id();
@@ -425,11 +456,11 @@ k_propagate(const PropagateArgs a) {
           const uint32_t s1 = word & 0xFFFFu;
           const float clearance = __uint_as_float(word & 0xFFFF0000u);
           if (s1 != 0xFFFFu)
-            test_string(s_strings[s1], a.doms, seg, a.radius, r2, best_t, best_id, st_tests);
+            test_string<kLdsDoms>(s_strings[s1], a.doms, s_zid, seg, a.radius, r2, best_t, best_id, st_tests);
           if (len >= clearance) {
             for (int s = 0; s < a.n_strings; ++s)
               if ((uint32_t)s != s1)
-                test_string(s_strings[s], a.doms, seg, a.radius, r2, best_t, best_id, st_tests);
+                test_string<kLdsDoms>(s_strings[s], a.doms, s_zid, seg, a.radius, r2, best_t, best_id, st_tests);
           }
         }
 
@@ -527,9 +558,10 @@ __global__ void k_dom_histogram_global(const DevHit *__restrict__ hits,
 
 }  // namespace
 
-size_t propagate_lds_bytes(int n_layers, int n_strings, int n_cells) {
-  return sizeof(DevLayer) * n_layers + sizeof(DevString) * n_strings + 4u * n_cells +
-         4u * (n_layers + 1);
+size_t propagate_lds_bytes(int n_layers, int n_strings, int n_cells, int n_lds_doms) {
+  const size_t tables = sizeof(DevLayer) * n_layers + sizeof(DevString) * n_strings + 4u * n_cells +
+                        4u * (n_layers + 1);
+  return n_lds_doms > 0 ? ((tables + 7) & ~static_cast<size_t>(7)) + sizeof(float2) * n_lds_doms : tables;
 }
 
 hipError_t launch_reset(unsigned long long *counters, int n, hipStream_t stream) {
@@ -539,23 +571,54 @@ hipError_t launch_reset(unsigned long long *counters, int n, hipStream_t stream)
 
 bool needs_wave(const PropagateArgs &a) { return a.kappa_abs != 0.0f || a.kappa_scat != 0.0f || a.n_acc != 0; }
 
-hipError_t launch_propagate(const PropagateArgs &args, int grid, int block, hipStream_t stream) {
-  const size_t lds = propagate_lds_bytes(args.n_layers, args.n_strings, args.nx * args.ny);
-  if (args.rec.fate != nullptr)
-    hipLaunchKernelGGL((k_propagate<true, true>), dim3(grid), dim3(block), lds, stream, args);
-  else if (needs_wave(args))
-    hipLaunchKernelGGL((k_propagate<false, true>), dim3(grid), dim3(block), lds, stream, args);
-  else
-    hipLaunchKernelGGL((k_propagate<false, false>), dim3(grid), dim3(block), lds, stream, args);
+// Launches / sizes one kernel variant; its dynamic-LDS limit is raised once
+// to kMaxPropagateLds.
+template <bool R, bool Wv, bool L>
+hipError_t allow_lds() {
+  static const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_propagate<R, Wv, L>),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  static_cast<int>(kMaxPropagateLds));
+  return e;
+}
+
+template <bool R, bool Wv, bool L>
+hipError_t launch_variant(const PropagateArgs &a, int grid, int block, size_t lds, hipStream_t stream) {
+  const hipError_t e = allow_lds<R, Wv, L>();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_propagate<R, Wv, L>), dim3(grid), dim3(block), lds, stream, a);
   return hipGetLastError();
 }
 
-hipError_t propagate_occupancy(bool records, bool wave, int block, size_t lds_bytes, int *blocks_per_cu) {
+template <bool R, bool Wv, bool L>
+hipError_t occupancy_variant(int block, size_t lds, int *per_cu) {
+  const hipError_t e = allow_lds<R, Wv, L>();
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_propagate<R, Wv, L>, block, lds);
+}
+
+hipError_t launch_propagate(const PropagateArgs &args, int grid, int block, hipStream_t stream) {
+  const bool L = args.lds_doms != 0;
+  const size_t lds = propagate_lds_bytes(args.n_layers, args.n_strings, args.nx * args.ny, L ? args.n_doms : 0);
+  if (args.rec.fate != nullptr)
+    return L ? launch_variant<true, true, true>(args, grid, block, lds, stream)
+             : launch_variant<true, true, false>(args, grid, block, lds, stream);
+  if (needs_wave(args))
+    return L ? launch_variant<false, true, true>(args, grid, block, lds, stream)
+             : launch_variant<false, true, false>(args, grid, block, lds, stream);
+  return L ? launch_variant<false, false, true>(args, grid, block, lds, stream)
+           : launch_variant<false, false, false>(args, grid, block, lds, stream);
+}
+
+hipError_t propagate_occupancy(bool records, bool wave, bool lds_doms, int block, size_t lds_bytes,
+                               int *blocks_per_cu) {
   if (records)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_propagate<true, true>, block, lds_bytes);
+    return lds_doms ? occupancy_variant<true, true, true>(block, lds_bytes, blocks_per_cu)
+                    : occupancy_variant<true, true, false>(block, lds_bytes, blocks_per_cu);
   if (wave)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_propagate<false, true>, block, lds_bytes);
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_propagate<false, false>, block, lds_bytes);
+    return lds_doms ? occupancy_variant<false, true, true>(block, lds_bytes, blocks_per_cu)
+                    : occupancy_variant<false, true, false>(block, lds_bytes, blocks_per_cu);
+  return lds_doms ? occupancy_variant<false, false, true>(block, lds_bytes, blocks_per_cu)
+                  : occupancy_variant<false, false, false>(block, lds_bytes, blocks_per_cu);
 }
 
 hipError_t launch_dom_histogram(const DevHit *hits, const unsigned long long *hit_count,

@@ -45,7 +45,8 @@ class _IceHeader(C.Structure):
 class _Stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("photons", "iterations", "layer_crossings", "dom_tests",
                                           "hits", "absorbed", "capped", "escaped")] + \
-               [("kernel_ms", C.c_float), ("reserved", C.c_uint32)]
+               [("kernel_ms", C.c_float), ("block_size", C.c_uint32), ("grid_blocks", C.c_uint32),
+                ("chunk_size", C.c_uint32), ("refill_interval", C.c_uint32)]
 
 
 class _LaunchConfig(C.Structure):
@@ -313,4 +314,4 @@ class Context:
     def stats(self, batch: int) -> dict:
         s = _Stats()
         self._check(_lib.pp_get_stats(self._h, batch, C.byref(s)))
-        return {k: getattr(s, k) for k, _ in _Stats._fields_ if k != "reserved"}
+        return {k: getattr(s, k) for k, _ in _Stats._fields_}

@@ -52,10 +52,10 @@ def test_struct_layouts_match_bindings(tmp_path, pp):
 #include <stdio.h>
 #include "pp.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(pp_source), sizeof(pp_hit),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(pp_source), sizeof(pp_hit),
          sizeof(pp_photon_record), sizeof(pp_dom), sizeof(pp_ice_layer), sizeof(pp_ice_header),
          offsetof(pp_source, n_photons), offsetof(pp_hit, time_ns), sizeof(pp_chromatic),
-         sizeof(pp_acceptance), offsetof(pp_acceptance, poly));
+         sizeof(pp_acceptance), offsetof(pp_acceptance, poly), sizeof(pp_stats));
   return 0;
 }''')
     exe = tmp_path / "layout"
@@ -64,7 +64,8 @@ int main(void) {
     assert got == [W.SOURCE_DTYPE.itemsize, pp.HIT_DTYPE.itemsize, pp.RECORD_DTYPE.itemsize,
                    W.DOM_DTYPE.itemsize, W.ICE_LAYER_DTYPE.itemsize, 16,
                    W.SOURCE_DTYPE.fields["n_photons"][1], pp.HIT_DTYPE.fields["time_ns"][1],
-                   C.sizeof(pp._Chromatic), C.sizeof(pp._Acceptance), pp._Acceptance.poly.offset]
+                   C.sizeof(pp._Chromatic), C.sizeof(pp._Acceptance), pp._Acceptance.poly.offset,
+                   C.sizeof(pp._Stats)]
 
 
 def test_chromatic_and_acceptance_validation(pp):
