@@ -20,7 +20,8 @@
  * outputs 1 and 2 are log(kappa) and log(theta / 50 ns) of a gamma
  * distribution of the hit delay. Loss per pair: the Poisson negative
  * log-likelihood of the hit count plus 0.1 times the gamma negative
- * log-likelihood of the delays, averaged over pairs.
+ * log-likelihood of the delays, times the row's weight, averaged over the
+ * rows of the batch.
  *
  * A pair set is every (source, module) pair of a batch submitted to the
  * context (pp_submit), source-major: pair p = source p / n_doms, module
@@ -53,14 +54,33 @@ pp_status pp_sur_get_params(pp_surrogate *sur, float *out, uint64_t n);
 /* Sets all parameters (n must equal the count) and clears the Adam state. */
 pp_status pp_sur_set_params(pp_surrogate *sur, const float *in, uint64_t n);
 
-/* Makes every (source, module) pair of the context's batch the training
- * set: computes the pair features on the device, and labels from the
- * batch's hits (which must have been propagated; the hit buffer is
- * completed first). Each source of the batch needs its own event id. */
+/* Which pairs of a batch the next pp_sur_set_training_set keeps. With
+ * far_stride = 1 (the default) every pair is a row of weight 1. With
+ * far_stride > 1 a pair is kept if the module centre lies within near_m
+ * metres of the segment centre (weight 1), or else if (module id + source
+ * index) mod far_stride == 0 (weight far_stride): an evenly spread
+ * 1-in-far_stride sample of the far pairs whose weighted loss has the
+ * expectation of the full set's, so training spends its work where the
+ * light is. near_m >= 0 (INFINITY keeps every pair); PP_EINVAL otherwise
+ * or for far_stride = 0. */
+pp_status pp_sur_set_sampling(pp_surrogate *sur, float near_m, uint32_t far_stride);
+
+/* Makes the (source, module) pairs of the context's batch the training set
+ * (all of them, or the sample chosen by pp_sur_set_sampling, in
+ * source-major order): computes the pair features on the device, and
+ * labels from the batch's hits (which must have been propagated; the hit
+ * buffer is completed first). Each source of the batch needs its own event
+ * id. With sampling, at most 2^31 pairs per batch. */
 pp_status pp_sur_set_training_set(pp_surrogate *sur, uint64_t batch);
 
-/* Number of pairs in the training set. */
+/* Number of rows (kept pairs) in the training set. */
 pp_status pp_sur_training_size(const pp_surrogate *sur, uint64_t *n_pairs);
+
+/* Copies, for training rows [first, first + count), the pair index
+ * (source-major, as above) and the loss weight to host memory. Either
+ * pointer may be NULL. */
+pp_status pp_sur_get_training_pairs(pp_surrogate *sur, uint64_t first, uint64_t count, uint64_t *pair,
+                                    float *weight);
 
 /* Number of real input features per (segment, module) pair (21): the pair
  * geometry up to a rotation about the vertical, the segment's extent, and

@@ -165,20 +165,34 @@ def forward(params, X):
     return h, (pre, acts)
 
 
-def loss_and_grad_out(Y, mu_base, n_photons, k, n_t, s1, s2):
-    """Mean over pairs of the Poisson + weighted gamma NLL, and dLoss/dY."""
+def loss_and_grad_out(Y, mu_base, n_photons, k, n_t, s1, s2, weight=None):
+    """Mean over rows of weight x (Poisson + 0.1 gamma NLL), and dLoss/dY.
+    A row of integer weight w counts as w copies of its pair (weight None:
+    every row 1)."""
     P = Y.shape[0]
+    w = np.ones(P) if weight is None else np.asarray(weight, np.float64)
     mu = n_photons * mu_base * np.exp(Y[:, 0])
     kappa = np.exp(Y[:, 1])
     theta = TAU0_NS * np.exp(Y[:, 2])
     poisson = mu - k * np.log(mu)
     gam = n_t * (special.gammaln(kappa) + kappa * np.log(theta)) - (kappa - 1.0) * s2 + s1 / theta
-    loss = (poisson + TIME_WEIGHT * gam).sum() / P
+    loss = (w * (poisson + TIME_WEIGHT * gam)).sum() / P
     dY = np.zeros_like(Y)
-    dY[:, 0] = (mu - k) / P
-    dY[:, 1] = TIME_WEIGHT * kappa * (n_t * (special.digamma(kappa) + np.log(theta)) - s2) / P
-    dY[:, 2] = TIME_WEIGHT * (n_t * kappa - s1 / theta) / P
+    dY[:, 0] = w * (mu - k) / P
+    dY[:, 1] = w * TIME_WEIGHT * kappa * (n_t * (special.digamma(kappa) + np.log(theta)) - s2) / P
+    dY[:, 2] = w * TIME_WEIGHT * (n_t * kappa - s1 / theta) / P
     return loss, dY
+
+
+def far_sample(R, src_idx, dom_idx, near_m, far_stride):
+    """Training-pair selection (a sampling rule of this implementation, not
+    of the paper): keep a pair whose module centre lies within near_m of the
+    segment centre (weight 1), else keep it if (module + source) mod
+    far_stride == 0 (weight far_stride). Returns (keep mask, weights)."""
+    near = np.asarray(R) <= near_m
+    far_keep = (np.asarray(dom_idx) + np.asarray(src_idx)) % far_stride == 0
+    keep = near | far_keep
+    return keep, np.where(near, 1.0, float(far_stride))[keep]
 
 
 def backward(params, cache, dY):

@@ -24,10 +24,15 @@ struct pp_surrogate {
   uint16_t *wb = nullptr, *wt = nullptr;
   int64_t adam_t = 0;
   float4 *doms_by_id = nullptr;
-  // training set
+  // training set; with pair selection (far_stride > 1) each row is the pair
+  // pair_of_row[row] with loss weight w[row], else row = pair and weight 1
   int64_t P = 0, P_pad = 0;
   uint16_t *X = nullptr, *XT = nullptr;
   float *mu_base = nullptr, *nph = nullptr, *k = nullptr, *n_t = nullptr, *s1 = nullptr, *s2 = nullptr;
+  float near_m = INFINITY;
+  uint32_t far_stride = 1;
+  int64_t *pair_of_row = nullptr;
+  float *w = nullptr;
   // minibatch work buffers (capacity Mcap rows)
   int64_t Mcap = 0;
   float *Z[4] = {};
@@ -39,7 +44,7 @@ struct pp_surrogate {
   // shuffled minibatch staging (capacity Gcap rows) and shuffle state
   int64_t Gcap = 0;
   uint16_t *gX = nullptr, *gXT = nullptr;
-  float *g_lab[6] = {};
+  float *g_lab[7] = {};  // mu_base, nph, k, n_t, s1, s2, w
   uint64_t shuffle_seed = 0;
   uint64_t epochs_done = 0;
   // inference buffers (capacity Icap rows; photons per source, capacity
@@ -67,6 +72,17 @@ template <class T>
 void dfree(T *&p) {
   if (p) (void)hipFree(p);
   p = nullptr;
+}
+
+// Runs f when the returned object goes out of scope.
+template <class F>
+struct OnExit {
+  F f;
+  ~OnExit() { f(); }
+};
+template <class F>
+OnExit<F> on_exit(F f) {
+  return OnExit<F>{f};
 }
 
 pp_status gemm(pp_context *ctx, int epi, const uint16_t *A, int64_t lda, const uint16_t *B, int64_t ldb, int M,
@@ -124,12 +140,13 @@ struct Rows {
   const uint16_t *X, *XT;
   int64_t ld_XT;
   const float *mu_base, *nph, *k, *n_t, *s1, *s2;
+  const float *w;  // null: weight 1
 };
 
 // Training rows [first, first + count) in stored order.
 Rows slice_rows(const pp_surrogate *s, int64_t first) {
   return Rows{s->X + first * sur::kInPad, s->XT + first, s->P_pad, s->mu_base + first, s->nph + first,
-              s->k + first, s->n_t + first, s->s1 + first, s->s2 + first};
+              s->k + first, s->n_t + first, s->s1 + first, s->s2 + first, s->w ? s->w + first : nullptr};
 }
 
 pp_status check_rows(pp_surrogate *s, int64_t first, int64_t count) {
@@ -174,6 +191,7 @@ pp_status forward_backward(pp_surrogate *s, const Rows &r, int64_t count, hipStr
   la.n_t = r.n_t;
   la.s1 = r.s1;
   la.s2 = r.s2;
+  la.w = r.w;
   la.M_real = static_cast<int>(count);
   la.M_pad = M;
   la.inv_norm = 1.0f / static_cast<float>(count);
@@ -256,6 +274,7 @@ pp_status gather_rows(pp_surrogate *s, uint64_t mul, uint64_t add, int64_t first
   g.n_t = s->n_t;
   g.s1 = s->s1;
   g.s2 = s->s2;
+  g.w = s->w;
   g.P = static_cast<uint64_t>(s->P);
   g.mul = mul;
   g.add = add;
@@ -270,8 +289,10 @@ pp_status gather_rows(pp_surrogate *s, uint64_t mul, uint64_t add, int64_t first
   g.g_n_t = s->g_lab[3];
   g.g_s1 = s->g_lab[4];
   g.g_s2 = s->g_lab[5];
+  g.g_w = s->g_lab[6];
   PP_HIP(s->ctx, sur::launch_gather(g, st));
-  *out = Rows{s->gX, s->gXT, M, s->g_lab[0], s->g_lab[1], s->g_lab[2], s->g_lab[3], s->g_lab[4], s->g_lab[5]};
+  *out = Rows{s->gX,         s->gXT,        M,           s->g_lab[0], s->g_lab[1], s->g_lab[2],
+              s->g_lab[3],   s->g_lab[4],   s->g_lab[5], s->w ? s->g_lab[6] : nullptr};
   return PP_OK;
 }
 
@@ -440,7 +461,7 @@ void pp_sur_destroy(pp_surrogate *s) {
   (void)hipDeviceSynchronize();
   dfree(s->theta), dfree(s->grad), dfree(s->adam_m), dfree(s->adam_v), dfree(s->wb), dfree(s->wt);
   dfree(s->doms_by_id), dfree(s->X), dfree(s->XT), dfree(s->mu_base), dfree(s->nph);
-  dfree(s->k), dfree(s->n_t), dfree(s->s1), dfree(s->s2);
+  dfree(s->k), dfree(s->n_t), dfree(s->s1), dfree(s->s2), dfree(s->pair_of_row), dfree(s->w);
   for (int l = 0; l < 4; ++l) dfree(s->Z[l]), dfree(s->H[l]), dfree(s->HT[l]);
   dfree(s->Y), dfree(s->dY), dfree(s->dYT), dfree(s->dZ[0]), dfree(s->dZ[1]), dfree(s->dZT), dfree(s->d_loss);
   dfree(s->i_mu), dfree(s->i_src_nph);
@@ -487,7 +508,50 @@ pp_status pp_sur_set_training_set(pp_surrogate *s, uint64_t batch) {
     if (ev[b->src[i].ids.y] >= 0) return fail(ctx, PP_EINVAL, "training sources need distinct event ids");
     ev[b->src[i].ids.y] = static_cast<int32_t>(i);
   }
-  s->P = n_src * s->n_doms;
+  const int64_t n_all = n_src * static_cast<int64_t>(s->n_doms);
+  // pair selection: rows are every pair, or the kept ones in source-major order
+  dfree(s->pair_of_row);
+  dfree(s->w);
+  // staging buffers, freed on every exit
+  float *d_src_nph = nullptr;
+  int32_t *d_ev = nullptr, *d_row_of_pair = nullptr;
+  uint32_t *d_count = nullptr;
+  int64_t *d_offset = nullptr;
+  const auto cleanup = on_exit([&] { dfree(d_src_nph), dfree(d_ev), dfree(d_row_of_pair), dfree(d_count), dfree(d_offset); });
+  if (s->far_stride > 1 && n_src > 0) {
+    if (n_all >= (int64_t{1} << 31)) return fail(ctx, PP_EINVAL, "pair selection supports up to 2^31 pairs");
+    sur::SelectArgs a{};
+    a.sources = b->d_src;
+    a.n_sources = static_cast<int>(n_src);
+    a.doms = s->doms_by_id;
+    a.n_doms = s->n_doms;
+    a.near2 = std::isinf(s->near_m) ? INFINITY : s->near_m * s->near_m;
+    a.far_stride = s->far_stride;
+    if ((st = dalloc(ctx, &d_count, n_src)) != PP_OK) return st;
+    a.count = d_count;
+    PP_HIP(ctx, sur::launch_select(a, false, nullptr));
+    std::vector<uint32_t> count(n_src);
+    PP_HIP(ctx, hipMemcpy(count.data(), d_count, sizeof(uint32_t) * n_src, hipMemcpyDeviceToHost));
+    dfree(d_count);
+    std::vector<int64_t> offset(n_src);
+    int64_t total = 0;
+    for (int64_t i = 0; i < n_src; ++i) offset[i] = total, total += count[i];
+    if ((st = dalloc(ctx, &d_offset, n_src)) != PP_OK || (st = dalloc(ctx, &s->pair_of_row, total)) != PP_OK ||
+        (st = dalloc(ctx, &s->w, round64(total))) != PP_OK || (st = dalloc(ctx, &d_row_of_pair, n_all)) != PP_OK)
+      return st;
+    PP_HIP(ctx, hipMemcpy(d_offset, offset.data(), sizeof(int64_t) * n_src, hipMemcpyHostToDevice));
+    PP_HIP(ctx, sur::launch_zero_f32(s->w, round64(total), nullptr));
+    a.row_offset = d_offset;
+    a.n_rows = total;
+    a.pair_of_row = s->pair_of_row;
+    a.row_of_pair = d_row_of_pair;
+    a.w = s->w;
+    PP_HIP(ctx, sur::launch_select(a, true, nullptr));
+    PP_HIP(ctx, hipDeviceSynchronize());
+    s->P = total;
+  } else {
+    s->P = n_all;
+  }
   s->P_pad = round64(s->P);
   const int64_t R = s->P_pad;
   if ((st = dalloc(ctx, &s->X, R * sur::kInPad)) != PP_OK || (st = dalloc(ctx, &s->XT, R * sur::kInPad)) != PP_OK ||
@@ -496,8 +560,6 @@ pp_status pp_sur_set_training_set(pp_surrogate *s, uint64_t batch) {
       (st = dalloc(ctx, &s->s1, R)) != PP_OK || (st = dalloc(ctx, &s->s2, R)) != PP_OK)
     return st;
   const std::vector<float> nph = source_photons(*b);
-  float *d_src_nph = nullptr;
-  int32_t *d_ev = nullptr;
   if ((st = dalloc(ctx, &d_src_nph, n_src)) != PP_OK) return st;
   if ((st = dalloc(ctx, &d_ev, static_cast<int64_t>(ev.size()))) != PP_OK) return st;
   PP_HIP(ctx, hipMemcpy(d_src_nph, nph.data(), sizeof(float) * nph.size(), hipMemcpyHostToDevice));
@@ -505,6 +567,7 @@ pp_status pp_sur_set_training_set(pp_surrogate *s, uint64_t batch) {
   sur::FeatureArgs f = feature_args(s, *b, d_src_nph);
   f.first_pair = 0;
   f.n_pairs = s->P;
+  f.pair_of_row = s->pair_of_row;
   f.X = s->X;
   f.XT = s->XT;
   f.ldxt = R;
@@ -516,10 +579,39 @@ pp_status pp_sur_set_training_set(pp_surrogate *s, uint64_t batch) {
   const float time_per_m = static_cast<float>(static_cast<double>(ctx->ice.n_group) / 0.299792458);
   PP_HIP(ctx, sur::launch_labels(b->d_hits, b->d_counters + pp::kHitCount, b->hit_cap, d_ev,
                                  static_cast<uint32_t>(ev.size()), b->d_src, s->doms_by_id, s->n_doms, ctx->radius,
-                                 time_per_m, s->k, s->n_t, s->s1, s->s2, nullptr));
+                                 time_per_m, d_row_of_pair, s->k, s->n_t, s->s1, s->s2, nullptr));
   PP_HIP(ctx, hipDeviceSynchronize());
-  dfree(d_src_nph);
-  dfree(d_ev);
+  return PP_OK;
+}
+
+pp_status pp_sur_set_sampling(pp_surrogate *s, float near_m, uint32_t far_stride) {
+  if (!s) return PP_EINVAL;
+  if (!(near_m >= 0.0f) || far_stride == 0)
+    return fail(s->ctx, PP_EINVAL, "near_m must be >= 0 (or +inf) and far_stride >= 1");
+  s->near_m = near_m;
+  s->far_stride = far_stride;
+  return PP_OK;
+}
+
+pp_status pp_sur_get_training_pairs(pp_surrogate *s, uint64_t first, uint64_t count, uint64_t *pair,
+                                    float *weight) {
+  if (!s) return PP_EINVAL;
+  pp_context *ctx = s->ctx;
+  if (first + count > static_cast<uint64_t>(s->P)) return fail(ctx, PP_EINVAL, "rows out of range");
+  PP_HIP(ctx, hipSetDevice(ctx->device));
+  PP_HIP(ctx, hipDeviceSynchronize());
+  if (pair && count) {
+    if (s->pair_of_row)
+      PP_HIP(ctx, hipMemcpy(pair, s->pair_of_row + first, sizeof(uint64_t) * count, hipMemcpyDeviceToHost));
+    else
+      for (uint64_t r = 0; r < count; ++r) pair[r] = first + r;
+  }
+  if (weight && count) {
+    if (s->w)
+      PP_HIP(ctx, hipMemcpy(weight, s->w + first, sizeof(float) * count, hipMemcpyDeviceToHost));
+    else
+      std::fill(weight, weight + count, 1.0f);
+  }
   return PP_OK;
 }
 

@@ -70,7 +70,8 @@ struct FeatureArgs {
   const pp::DevLayer *layers;
   int n_layers;
   float z_lo, inv_dz, radius;
-  int64_t first_pair, n_pairs;  // pairs [first, first + n) of the set
+  int64_t first_pair, n_pairs;  // rows [first, first + n) of the set
+  const int64_t *pair_of_row;   // pair index of each row (source-major), null: row = pair
   uint16_t *X;    // bf16 n x 64 (rows padded to a multiple of 64 with zeros)
   uint16_t *XT;   // bf16 64 x ldxt (column = pair - first), may be null
   int64_t ldxt;
@@ -82,6 +83,7 @@ struct FeatureArgs {
 struct LossArgs {
   const float *Y;        // f32 M x 64 (ld 64)
   const float *mu_base, *nph, *k, *n_t, *s1, *s2;  // per row
+  const float *w;        // loss weight per row, null: 1
   int M_real, M_pad;
   float inv_norm;        // 1 / number of pairs averaged over
   uint16_t *dY;          // bf16 M_pad x 64
@@ -97,13 +99,36 @@ struct LossArgs {
 struct GatherArgs {
   const uint16_t *X;                                // bf16 P_pad x 64
   const float *mu_base, *nph, *k, *n_t, *s1, *s2;   // per training row
+  const float *w;                                   // per training row, may be null
   uint64_t P, mul, add;
   int64_t first;
   int count, M;
   uint16_t *gX;    // bf16 M x 64
   uint16_t *gXT;   // bf16 64 x M
   float *g_mu_base, *g_nph, *g_k, *g_n_t, *g_s1, *g_s2;
+  float *g_w;      // written only if w is not null
 };
+
+// Training-pair selection: a (source, module) pair is kept if the module
+// centre lies within near_m of the segment centre, or else if
+// (module + source) mod far_stride == 0, with loss weight far_stride; the
+// far pairs kept are then an evenly spread 1-in-far_stride sample whose
+// weighted loss has the expectation of the full set's.
+struct SelectArgs {
+  const pp::DevSource *sources;
+  int n_sources;
+  const float4 *doms;   // module centres, module-id order
+  int n_doms;
+  float near2;          // near_m^2
+  uint32_t far_stride;
+  const int64_t *row_offset;  // first row of each source (exclusive prefix of the counts)
+  int64_t n_rows;             // rows allocated (scatter pass): no row at or past it is written
+  uint32_t *count;            // kept pairs per source (counting pass)
+  int64_t *pair_of_row;       // row -> pair (scatter pass)
+  int32_t *row_of_pair;       // pair -> row or -1 (scatter pass)
+  float *w;                   // row -> loss weight (scatter pass)
+};
+hipError_t launch_select(const SelectArgs &a, bool scatter, hipStream_t s);
 
 hipError_t launch_gemm(int epi, const GemmArgs &g, int splits, hipStream_t s);
 hipError_t launch_gather(const GatherArgs &g, hipStream_t s);
@@ -117,7 +142,7 @@ hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
 hipError_t launch_labels(const pp::DevHit *hits, const unsigned long long *hit_count, uint64_t hit_cap,
                          const int32_t *event_to_source, uint32_t n_events, const pp::DevSource *sources,
                          const float4 *doms, int n_doms, float radius, float time_per_m,
-                         float *k, float *n_t, float *s1, float *s2, hipStream_t s);
+                         const int32_t *row_of_pair, float *k, float *n_t, float *s1, float *s2, hipStream_t s);
 
 // Fused inference over pairs [f.first_pair, f.first_pair + f.n_pairs):
 // features, the five layers and the expected hits, kFusedRows pairs per

@@ -235,7 +235,8 @@ __global__ void k_features(const FeatureArgs f, int64_t n_rows) {
   for (int q = 0; q < kInReal; ++q) x[q] = 0.0f;
   float mu_base = 0.0f, nph = 0.0f, R = 0.0f;
   int dom = 0;
-  if (t < f.n_pairs) pair_features(f, f.first_pair + t, x, mu_base, nph, R, dom);
+  if (t < f.n_pairs)
+    pair_features(f, f.pair_of_row ? f.pair_of_row[f.first_pair + t] : f.first_pair + t, x, mu_base, nph, R, dom);
   uint16_t *row = f.X + t * kInPad;
   for (int q = 0; q < kInPad; ++q) row[q] = q < kInReal ? f2bf(x[q]) : 0;
   if (f.XT)
@@ -263,11 +264,13 @@ __global__ void __launch_bounds__(256) k_loss(const LossArgs l) {
       const float pois = mu - (k > 0.0f ? k * log_mu : 0.0f);
       const float gam = nt > 0.0f ? nt * (lgammaf(kappa) + kappa * logf(theta)) - (kappa - 1.0f) * s2 + s1 / theta
                                   : 0.0f;
-      part = (double)pois + (double)kTimeWeight * gam;
-      g0 = (mu - k) * l.inv_norm;
+      const float wt = l.w ? l.w[m] : 1.0f;
+      part = (double)wt * ((double)pois + (double)kTimeWeight * gam);
+      const float scale = wt * l.inv_norm;
+      g0 = (mu - k) * scale;
       if (nt > 0.0f) {
-        g1 = kTimeWeight * kappa * (nt * (digamma(kappa) + logf(theta)) - s2) * l.inv_norm;
-        g2 = kTimeWeight * (nt * kappa - s1 / theta) * l.inv_norm;
+        g1 = kTimeWeight * kappa * (nt * (digamma(kappa) + logf(theta)) - s2) * scale;
+        g2 = kTimeWeight * (nt * kappa - s1 / theta) * scale;
         if (y[1] != y1) g1 = 0.0f;  // clamped: no gradient through the clamp
         if (y[2] != y2) g2 = 0.0f;
       }
@@ -350,8 +353,8 @@ __global__ void k_zero_f64(double *p, int64_t n) {
 // photon reaches the module surface sooner.
 __global__ void k_labels(const pp::DevHit *hits, const unsigned long long *hit_count, uint64_t cap,
                          const int32_t *event_to_source, uint32_t n_events, const pp::DevSource *sources,
-                         const float4 *doms, int n_doms, float radius, float time_per_m, float *k, float *n_t,
-                         float *s1, float *s2) {
+                         const float4 *doms, int n_doms, float radius, float time_per_m,
+                         const int32_t *row_of_pair, float *k, float *n_t, float *s1, float *s2) {
   uint64_t n = *hit_count;
   if (n > cap) n = cap;
   for (uint64_t h = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; h < n; h += (uint64_t)gridDim.x * blockDim.x) {
@@ -367,10 +370,12 @@ __global__ void k_labels(const pp::DevHit *hits, const unsigned long long *hit_c
     const float R = sqrtf(dx * dx + dy * dy + dz * dz);
     const float delay = fmaxf(hit.time_ns - S.pos_t0.w - fmaxf(R - half - radius, 0.0f) * time_per_m, 0.0f) + 0.01f;
     const int64_t pair = (int64_t)i * n_doms + hit.dom_id;
-    atomicAdd(&k[pair], 1.0f);
-    atomicAdd(&n_t[pair], 1.0f);
-    atomicAdd(&s1[pair], delay);
-    atomicAdd(&s2[pair], logf(delay));
+    const int64_t row = row_of_pair ? (int64_t)row_of_pair[pair] : pair;
+    if (row < 0) continue;  // pair not in the training set
+    atomicAdd(&k[row], 1.0f);
+    atomicAdd(&n_t[row], 1.0f);
+    atomicAdd(&s1[row], delay);
+    atomicAdd(&s2[row], logf(delay));
   }
 }
 
@@ -562,6 +567,10 @@ __global__ void __launch_bounds__(256) k_gather(const GatherArgs g) {
     case 3: src = g.n_t, dst = g.g_n_t; break;
     case 4: src = g.s1, dst = g.g_s1; break;
     case 5: src = g.s2, dst = g.g_s2; break;
+    case 6:
+      if (!g.w) return;
+      src = g.w, dst = g.g_w;
+      break;
     default: return;
   }
   dst[i] = real ? src[p] : 0.0f;
@@ -597,10 +606,73 @@ hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s) {
 
 hipError_t launch_labels(const pp::DevHit *hits, const unsigned long long *hit_count, uint64_t hit_cap,
                          const int32_t *event_to_source, uint32_t n_events, const pp::DevSource *sources,
-                         const float4 *doms, int n_doms, float radius, float time_per_m, float *k, float *n_t,
-                         float *s1, float *s2, hipStream_t s) {
+                         const float4 *doms, int n_doms, float radius, float time_per_m,
+                         const int32_t *row_of_pair, float *k, float *n_t, float *s1, float *s2, hipStream_t s) {
   hipLaunchKernelGGL(k_labels, dim3(1024), dim3(256), 0, s, hits, hit_count, hit_cap, event_to_source, n_events,
-                     sources, doms, n_doms, radius, time_per_m, k, n_t, s1, s2);
+                     sources, doms, n_doms, radius, time_per_m, row_of_pair, k, n_t, s1, s2);
+  return hipGetLastError();
+}
+
+// Training-pair selection, one workgroup of 256 per source. The counting
+// pass writes the number of kept pairs of the source; the scatter pass
+// writes them in module order from the source's first row on, using the
+// wavefront ballot for the order within a wavefront and LDS for the order
+// between wavefronts, so the row order does not depend on scheduling.
+template <bool kScatter>
+__global__ void __launch_bounds__(256) k_select(const SelectArgs a) {
+  const int i = blockIdx.x;
+  if (i >= a.n_sources) return;
+  const pp::DevSource &S = a.sources[i];
+  // explicit fmaf: both passes must take the same decision for every pair,
+  // whatever the compiler would contract in either instantiation
+  const float half = 0.5f * S.dir_len.w;
+  const float cx = fmaf(half, S.dir_len.x, S.pos_t0.x), cy = fmaf(half, S.dir_len.y, S.pos_t0.y);
+  const float cz = fmaf(half, S.dir_len.z, S.pos_t0.z);
+  __shared__ uint32_t wave_kept[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t next_row = kScatter ? a.row_offset[i] : 0;
+  uint32_t kept_total = 0;
+  for (int j0 = 0; j0 < a.n_doms; j0 += 256) {
+    const int j = j0 + (int)threadIdx.x;
+    bool keep = false, near = false;
+    if (j < a.n_doms) {
+      const float4 m = a.doms[j];
+      const float dx = m.x - cx, dy = m.y - cy, dz = m.z - cz;
+      near = fmaf(dx, dx, fmaf(dy, dy, __fmul_rn(dz, dz))) <= a.near2;
+      keep = near || ((uint32_t)j + (uint32_t)i) % a.far_stride == 0u;
+    }
+    const uint64_t ballot = __ballot(keep);
+    if (lane == 0) wave_kept[wave] = (uint32_t)__popcll(ballot);
+    __syncthreads();
+    uint32_t before = 0, chunk = 0;
+    for (int q = 0; q < 4; ++q) {
+      before += q < wave ? wave_kept[q] : 0u;
+      chunk += wave_kept[q];
+    }
+    if (kScatter && j < a.n_doms) {
+      const int64_t pair = (int64_t)i * a.n_doms + j;
+      const int64_t row = next_row + before + (uint32_t)__popcll(ballot & ((1ull << lane) - 1ull));
+      if (keep && row < a.n_rows) {
+        a.pair_of_row[row] = pair;
+        a.w[row] = near ? 1.0f : (float)a.far_stride;
+        a.row_of_pair[pair] = (int32_t)row;
+      } else {
+        a.row_of_pair[pair] = -1;
+      }
+    }
+    next_row += chunk;
+    kept_total += chunk;
+    __syncthreads();  // wave_kept is rewritten by the next chunk
+  }
+  if (!kScatter && threadIdx.x == 0) a.count[i] = kept_total;
+}
+
+hipError_t launch_select(const SelectArgs &a, bool scatter, hipStream_t s) {
+  if (a.n_sources <= 0) return hipSuccess;
+  if (scatter)
+    hipLaunchKernelGGL(k_select<true>, dim3(a.n_sources), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_select<false>, dim3(a.n_sources), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

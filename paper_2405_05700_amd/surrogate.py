@@ -17,7 +17,9 @@ SIGNATURES = {
     "pp_sur_param_count": (_u64, []),
     "pp_sur_get_params": (C.c_int, [_vp, _vp, _u64]),
     "pp_sur_set_params": (C.c_int, [_vp, _vp, _u64]),
+    "pp_sur_set_sampling": (C.c_int, [_vp, C.c_float, _u32]),
     "pp_sur_set_training_set": (C.c_int, [_vp, _u64]),
+    "pp_sur_get_training_pairs": (C.c_int, [_vp, _u64, _u64, _vp, _vp]),
     "pp_sur_training_size": (C.c_int, [_vp, C.POINTER(_u64)]),
     "pp_sur_get_training_rows": (C.c_int, [_vp, _u64, _u64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pp_sur_loss_grad": (C.c_int, [_vp, _u64, _u64, C.POINTER(C.c_double), _vp]),
@@ -76,8 +78,21 @@ class Surrogate:
         theta = np.ascontiguousarray(theta, np.float32)
         self._check(_lib.pp_sur_set_params(self._h, _p(theta), theta.size))
 
+    def set_sampling(self, near_m: float = float("inf"), far_stride: int = 1):
+        """Pairs kept by the next set_training_set: all (far_stride 1), or
+        those within near_m plus a weighted 1-in-far_stride sample of the
+        rest."""
+        self._check(_lib.pp_sur_set_sampling(self._h, near_m, far_stride))
+
     def set_training_set(self, batch: int):
         self._check(_lib.pp_sur_set_training_set(self._h, batch))
+
+    def training_pairs(self, first: int, count: int):
+        """(pair index, loss weight) of training rows [first, first + count)."""
+        pair = np.empty(count, np.uint64)
+        w = np.empty(count, np.float32)
+        self._check(_lib.pp_sur_get_training_pairs(self._h, first, count, _p(pair), _p(w)))
+        return pair, w
 
     def training_size(self) -> int:
         n = C.c_uint64()

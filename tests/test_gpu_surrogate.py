@@ -178,6 +178,87 @@ def test_fused_expected_hits_equal_pair_sums(mods):
     assert np.isfinite(per_pair).all() and (per_pair >= 0).all()
 
 
+def test_far_pair_sampling_follows_rule_and_oracle(mods):
+    """Training-pair sampling on the device: the kept rows are exactly the
+    pairs the rule keeps (module within 150 m of the segment centre, or
+    (module + source) % 16 == 0), in source-major order, with weights 1 and
+    16; their features and labels equal those of the same pairs in the full
+    set; and the weighted loss and gradients match the oracle."""
+    pp, surrogate, M = mods
+    det = W.full_detector(n_sources=1, photons_per_source=1)
+    ev = W.near_module_segments(det, 6, 300_000, seed=9, r_min=3.0, r_max=25.0)
+    wl = det.with_sources(ev)
+    ctx = pp.Context(0, seed=0)
+    ctx.load_workload(det)
+    b = ctx.submit(ev)
+    ctx.propagate(b)
+    n_dom = len(det.doms)
+    full = surrogate.Surrogate(ctx, seed=1)
+    full.set_training_set(b)
+    P_all = full.training_size()
+    assert P_all == 6 * n_dom
+    pair_all, w_all = full.training_pairs(0, P_all)
+    assert np.array_equal(pair_all, np.arange(P_all)) and (w_all == 1).all()
+    rows_all = full.training_rows(0, P_all)
+    full.close()
+    sur = surrogate.Surrogate(ctx, seed=1)
+    sur.set_sampling(150.0, 16)
+    sur.set_training_set(b)
+    P = sur.training_size()
+    pair, wt = sur.training_pairs(0, P)
+    pair = pair.astype(np.int64)
+    src, dom = np.divmod(np.arange(P_all), n_dom)
+    _, _, R = M.pair_features(wl, src, dom)
+    keep_ref, w_ref = M.far_sample(R, src, dom, 150.0, 16)
+    kept = np.zeros(P_all, bool)
+    kept[pair] = True
+    clear = np.abs(R - 150.0) > 1e-3  # pairs on the boundary may round either way
+    say("sampled rows", P, "of", P_all, "near", int((wt == 1).sum()))
+    assert (np.diff(pair) > 0).all()
+    assert np.array_equal(kept[clear], keep_ref[clear])
+    w_full = np.zeros(P_all)
+    w_full[keep_ref] = w_ref
+    assert np.array_equal(wt[clear[pair]], w_full[pair][clear[pair]].astype(np.float32))
+    assert P < P_all / 8
+    rows = sur.training_rows(0, P)
+    assert np.array_equal(rows["features"], rows_all["features"][pair])
+    assert np.array_equal(rows["mu_base"], rows_all["mu_base"][pair])
+    assert np.array_equal(rows["k"], rows_all["k"][pair]) and np.array_equal(rows["n_t"], rows_all["n_t"][pair])
+    assert np.allclose(rows["s1"], rows_all["s1"][pair], rtol=1e-5, atol=1e-3)
+    assert np.allclose(rows["s2"], rows_all["s2"][pair], rtol=1e-5, atol=1e-3)
+    # every hit on a near pair is a label
+    near = R <= 150.0 - 1e-3
+    assert rows["k"][wt == 1].sum() >= rows_all["k"][near].sum() > 0
+    # weighted loss and gradients against the oracle
+    params0 = M.init_params(8)
+    theta = flatten(M, params0)
+    sur.set_params(theta)
+    count = min(P, 2048)
+    loss, grad = sur.loss_grad(0, count)
+    X, params = oracle_on_gpu_inputs(M, rows, theta, 0, count)
+    Y, cache = M.forward(params, X)
+    nph = ev["n_photons"][pair[:count] // n_dom].astype(float)
+    loss_ref, dY = M.loss_and_grad_out(Y, rows["mu_base"][:count].astype(float), nph, rows["k"][:count],
+                                       rows["n_t"][:count], rows["s1"][:count], rows["s2"][:count],
+                                       weight=wt[:count].astype(float))
+    g_ref = flatten(M, M.backward(params, cache, dY)).astype(np.float64)
+    say("weighted loss gpu", loss, "oracle", loss_ref)
+    assert abs(loss - loss_ref) <= 0.02 * abs(loss_ref) + 1e-6
+    o = 0
+    for li, (n_out, n_in) in enumerate(M.LAYER_SHAPES):
+        for part, size in (("W", n_out * n_in), ("b", n_out)):
+            a, r = grad[o:o + size].astype(np.float64), g_ref[o:o + size]
+            o += size
+            err = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
+            cos = a @ r / max(np.linalg.norm(a) * np.linalg.norm(r), 1e-30)
+            assert err < 0.06 and cos > 0.998, (li, part, err, cos)
+    # a shuffled epoch with lr = 0 visits every weighted row once
+    l_all, _ = sur.loss_grad(0, P)
+    losses = sur.train(epochs=2, batch_size=512, lr=0.0)
+    assert np.allclose(losses, l_all, rtol=2e-5, atol=1e-9)
+    sur.close()
+
+
 def test_adam_step_matches_definition(mods, small_set):
     pp, surrogate, M = mods
     w, ctx, b, sur = small_set

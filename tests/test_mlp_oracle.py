@@ -49,6 +49,50 @@ def test_loss_gradient_matches_finite_difference():
     assert (dY[:, 3:] == 0).all()
 
 
+def test_weighted_loss_equals_duplicated_rows():
+    """A row of integer weight w is w copies of its pair: the weighted loss
+    and dLoss/dY over P rows equal those over the duplicated rows, rescaled
+    from the duplicated count to P, and the gradient of a duplicated pair is
+    the sum over its copies."""
+    rng = np.random.default_rng(5)
+    P = 30
+    nph, mub, k, n_t, s1, s2 = random_labels(rng, P)
+    Y = rng.normal(0, 0.5, (P, M.OUT_PAD))
+    w = rng.integers(1, 5, P)
+    lw, dw = M.loss_and_grad_out(Y, mub, nph, k, n_t, s1, s2, weight=w)
+    rep = np.repeat(np.arange(P), w)
+    ld, dd = M.loss_and_grad_out(Y[rep], mub[rep], nph[rep], k[rep], n_t[rep], s1[rep], s2[rep])
+    assert abs(lw - ld * len(rep) / P) <= 1e-12 * abs(ld * len(rep) / P)
+    summed = np.zeros_like(dw)
+    np.add.at(summed, rep, dd)
+    assert np.allclose(dw, summed * len(rep) / P, rtol=1e-12, atol=1e-300)
+    # unit weights are the unweighted loss
+    l1, d1 = M.loss_and_grad_out(Y, mub, nph, k, n_t, s1, s2, weight=np.ones(P))
+    l0, d0 = M.loss_and_grad_out(Y, mub, nph, k, n_t, s1, s2)
+    assert l1 == l0 and np.array_equal(d1, d0)
+
+
+def test_far_sample_is_unbiased_and_keeps_every_near_pair():
+    """The sampling rule keeps every pair within near_m with weight 1, and of
+    the far pairs exactly those with (module + source) % stride == 0, with
+    weight stride; over all stride source offsets each far pair is kept
+    exactly once, so the weighted far count equals the full far count."""
+    n_src, n_dom, stride = 12, 50, 4
+    src = np.repeat(np.arange(n_src), n_dom)
+    dom = np.tile(np.arange(n_dom), n_src)
+    R = np.random.default_rng(2).uniform(0, 300, n_src * n_dom)
+    keep, wt = M.far_sample(R, src, dom, 150.0, stride)
+    assert keep[R <= 150].all() and (wt[(R <= 150)[keep]] == 1).all()
+    assert (wt[(R > 150)[keep]] == stride).all()
+    assert np.array_equal(keep[R > 150], ((dom + src) % stride == 0)[R > 150])
+    # same geometry for every source offset: each far pair kept once
+    kept_times = np.zeros(n_dom)
+    for s in range(stride):
+        kk, _ = M.far_sample(np.full(n_dom, 200.0), np.full(n_dom, s), np.arange(n_dom), 150.0, stride)
+        kept_times += kk
+    assert (kept_times == 1).all()
+
+
 def test_backward_matches_finite_difference():
     """Chain-rule gradients of a small random network (real shapes) against
     central differences of the loss on sampled parameters of every layer."""
