@@ -11,7 +11,7 @@
  * evaluation instead of many propagated photons. The Monte Carlo stays the
  * judge of its error and the fallback where the error check fails.
  *
- * Model (fixed shape): 21 features of a (source, module) pair, padded to
+ * Model (fixed shape): 29 features of a (source, module) pair, padded to
  * 64 -> five affine layers 64 -> 256 -> 256 -> 256 -> 256 -> 64 with GELU
  * between them; BF16
  * weights and activations, FP32 accumulation on the matrix cores, FP32
@@ -82,9 +82,10 @@ pp_status pp_sur_training_size(const pp_surrogate *sur, uint64_t *n_pairs);
 pp_status pp_sur_get_training_pairs(pp_surrogate *sur, uint64_t first, uint64_t count, uint64_t *pair,
                                     float *weight);
 
-/* Number of real input features per (segment, module) pair (21): the pair
- * geometry up to a rotation about the vertical, the segment's extent, and
- * the optics of the layers at the segment centre and at the module. */
+/* Number of real input features per (segment, module) pair (29): the pair
+ * geometry up to a rotation about the vertical, the segment's extent, the
+ * optics of the layers at the segment centre and at the module, and of the
+ * layers 20 m above and below each. */
 uint32_t pp_sur_feature_count(void);
 
 /* Copies training-set rows [first, first + count) to host memory:

@@ -2,14 +2,15 @@
 
 The surrogate predicts, for a light source and an optical module, the
 expected number of hits per emitted photon and gamma parameters of the hit
-delay. It is a multilayer perceptron: five affine layers (21 features + 43 zero columns)
+delay. It is a multilayer perceptron: five affine layers (29 features + 35 zero columns)
 -> 256 -> 256 -> 256 -> 256 -> 64, three outputs used) with GELU between
 them (GELU(z) = z Phi(z), Phi the standard normal CDF). Everything here is
 the plain definition, in float64:
 
 * features: geometry of the (source, module) pair up to a rotation about
   the vertical (the ice is layered in depth only) and the optical
-  properties of the layers holding the source centre and the module;
+  properties of the layers holding the source centre and the module, and
+  of the layers 20 m above and below each;
 * baseline: the diffusion estimate of the hit probability,
   mu_base = r^2 exp(-R/delta) / (4 D R), D = lambda_e/3,
   delta = sqrt(D lambda_a), with lambda_e and lambda_a averaged over the two
@@ -33,8 +34,9 @@ import numpy as np
 from scipy import special
 
 C_LIGHT = 0.299792458
-IN_REAL, IN_PAD, HIDDEN, OUT_PAD, OUT_REAL = 21, 64, 256, 64, 3
+IN_REAL, IN_PAD, HIDDEN, OUT_PAD, OUT_REAL = 29, 64, 256, 64, 3
 TAN_CHERENKOV = math.tan(math.radians(41.0))
+NEIGHBOUR_DZ_M = 20.0  # depth offset of the neighbouring optics features
 LAYER_SHAPES = [(HIDDEN, IN_PAD), (HIDDEN, HIDDEN), (HIDDEN, HIDDEN), (HIDDEN, HIDDEN),
                 (OUT_PAD, HIDDEN)]  # (out, in): weight matrices are out x in
 TAU0_NS = 50.0
@@ -57,8 +59,9 @@ def layer_index(z, z_lo, dz, n_layers):
 
 
 def pair_features(w, src_idx, dom_idx):
-    """Features (P x 64, last 48 zero) and baseline mu_base (P) per photon
-    for (source, module) pairs of workload w (Cherenkov sources)."""
+    """Features (P x 64, columns IN_REAL.. zero), baseline mu_base (P) per
+    photon and centre distance R (P) for (source, module) pairs of workload w
+    (Cherenkov sources)."""
     s = w.sources[np.asarray(src_idx)]
     d = w.doms[np.asarray(dom_idx)]
     L = w.layers
@@ -118,6 +121,14 @@ def pair_features(w, src_idx, dom_idx):
     X[:, 18] = np.clip((along - b / TAN_CHERENKOV) / L, -1.0, 2.0)
     X[:, 19] = np.linalg.norm(v, axis=1) / 100.0
     X[:, 20] = np.linalg.norm(v - L[:, None] * dirv, axis=1) / 100.0
+    # the optics NEIGHBOUR_DZ_M above and below the segment centre and the
+    # module: where the depth profile changes within the range light
+    # diffuses over (a dust layer), the two end layers alone do not say so
+    for q, z in enumerate((c[:, 2] + NEIGHBOUR_DZ_M, c[:, 2] - NEIGHBOUR_DZ_M,
+                           m[:, 2] + NEIGHBOUR_DZ_M, m[:, 2] - NEIGHBOUR_DZ_M)):
+        li = layer_index(z, w.z_lo_m, w.dz_m, n_layers)
+        X[:, 21 + 2 * q] = 100.0 * a_all[li]
+        X[:, 22 + 2 * q] = 10.0 / (le_all[li] * (1.0 - g_all[li]))
     # diffusion baseline with the two layers' mean lengths
     lam_a = 0.5 * (1.0 / a_s + 1.0 / a_d)
     lam_e = 0.5 * (le_all[ls] + le_all[ld])

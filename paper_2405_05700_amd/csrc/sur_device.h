@@ -9,8 +9,9 @@
 
 namespace sur {
 
-constexpr int kInReal = 21, kInPad = 64, kHidden = 256, kOutPad = 64, kOutReal = 3;
+constexpr int kInReal = 29, kInPad = 64, kHidden = 256, kOutPad = 64, kOutReal = 3;
 constexpr float kTanCherenkov = 0.86928673781622666f;  // tan 41 deg
+constexpr float kNeighbourDz = 20.0f;  // depth offset (m) of the neighbouring optics features
 constexpr int kLayers = 5;
 constexpr int kTile = 64;            // GEMM workgroup tile (rows and columns)
 constexpr float kTau0Ns = 50.0f;     // gamma scale unit of the delay model

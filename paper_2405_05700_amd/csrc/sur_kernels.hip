@@ -215,6 +215,16 @@ __device__ __forceinline__ void pair_features(const FeatureArgs &f, int64_t p, f
   x[18] = fminf(fmaxf((along - bimp / kTanCherenkov) / L, -1.0f), 2.0f);
   x[19] = sqrtf(vx * vx + vy * vy + vz * vz) / 100.0f;
   x[20] = sqrtf(ex * ex + ey * ey + ez * ez) / 100.0f;
+  // The optics 20 m above and below the segment centre and the module:
+  // where the depth profile changes within the range light diffuses over
+  // (a dust layer), the two end layers alone do not say so.
+  const float zq[4] = {cz + kNeighbourDz, cz - kNeighbourDz, m.z + kNeighbourDz, m.z - kNeighbourDz};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const pp::DevLayer Lq = f.layers[layer_of(zq[q], f.z_lo, f.inv_dz, f.n_layers)];
+    x[21 + 2 * q] = 100.0f * Lq.coef.x;
+    x[22 + 2 * q] = 10.0f * Lq.coef.y;
+  }
   // diffusion baseline with the two layers' mean absorption and
   // effective scattering lengths (lambda_e = (1/b) / (1 - g))
   const float lam_a = 0.5f * (Ls.coef.z + Ld.coef.z);

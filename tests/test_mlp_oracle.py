@@ -193,6 +193,16 @@ def test_features_geometry():
     assert inside.any() and np.allclose(cos_c[inside], math.cos(math.radians(41.0)))
     # the baseline falls with distance at fixed optics and is positive
     assert (mub > 0).all()
+    # neighbouring optics: the layer holding each depth 20 m above and below
+    # the centre and the module, found by searching the layer edges
+    edges = w.z_lo_m + w.dz_m * np.arange(1, len(w.layers))
+    a_tab = 100.0 / w.layers["abs_len_m"].astype(float)
+    b_tab = 10.0 / (w.layers["eff_scat_len_m"].astype(float) * (1.0 - w.layers["g"].astype(float)))
+    for q, z in enumerate((c[src, 2] + 20.0, c[src, 2] - 20.0, m[dom, 2] + 20.0, m[dom, 2] - 20.0)):
+        li = np.searchsorted(edges, z, side="right")
+        assert np.allclose(X[:, 21 + 2 * q], a_tab[li]) and np.allclose(X[:, 22 + 2 * q], b_tab[li])
+    # a module on a layer boundary sees different optics above and below it
+    assert (X[:, 25] != X[:, 27]).any()
 
 
 def test_features_do_not_depend_on_azimuth():
