@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--sur-train-sources", type=int, default=48000)
     ap.add_argument("--sur-train-photons", type=int, default=2_000_000)
     ap.add_argument("--sur-train-rmax", type=float, default=25.0)
+    ap.add_argument("--sur-structured-frac", type=float, default=0.4,
+                    help="fraction of training segments placed at modules with depth-structured optics")
     ap.add_argument("--sur-epochs", type=int, default=100)
     ap.add_argument("--sur-ensemble", type=int, default=4)
     ap.add_argument("--sur-near-m", type=float, default=150.0,
@@ -94,7 +96,7 @@ def parse():
     ap.add_argument("--sur-lr", type=float, default=1e-3)
     ap.add_argument("--sur-lr-final", type=float, default=1e-5)
     ap.add_argument("--sur-infer-sources", type=int, default=100_000)
-    ap.add_argument("--sur-eval-sets", type=int, default=2,
+    ap.add_argument("--sur-eval-sets", type=int, default=3,
                     help="held-out target sets of 40 modules (4 segments each)")
     ap.add_argument("--sur-truth-photons", type=int, default=400_000_000)
     ap.add_argument("--no-serving", action="store_true")
@@ -207,11 +209,13 @@ def cpu_baseline(w, per_source: int):
 def surrogate_leg(args):
     """Learned surrogate: an ensemble of four networks trained on the same
     labels from different initial weights. Training: Monte Carlo of 48000
-    segments placed 3-25 m from random modules of the full detector; of
+    segments placed 3-25 m from modules of the full detector (40% of them at
+    modules whose surroundings have depth-structured optics, the dust
+    layer; the rest at random modules); of
     their (segment, module) pairs every pair within 150 m is kept and 1 in
     64 of the rest, with that weight. Inference throughput: 1e5
     full-detector segments x 5160 modules. Accuracy and speed-up: clusters
-    of four held-out segments 4-20 m from each of 40 target modules, two
+    of four held-out segments 4-20 m from each of 40 target modules, three
     such sets; truth = high-statistics Monte Carlo (4e8 photons per
     segment); graded modules have >= 1e4 truth hits per 1e8 photons per
     segment (<= 0.5% statistical error at 4e8). Plain Monte Carlo of each
@@ -228,8 +232,9 @@ def surrogate_leg(args):
     det = W.full_detector(n_sources=1, photons_per_source=1)
     ctx = pp.Context(0, seed=7)
     ctx.load_workload(det)
+    targets = W.training_targets(det, args.sur_train_sources, args.sur_structured_frac, seed=77)
     tr = W.near_module_segments(det, args.sur_train_sources, args.sur_train_photons, seed=101,
-                                r_min=3.0, r_max=args.sur_train_rmax)
+                                r_min=3.0, r_max=args.sur_train_rmax, targets=targets)
     b_tr = ctx.submit(tr)
     t0 = time.perf_counter()
     ctx.propagate(b_tr)
@@ -254,6 +259,7 @@ def surrogate_leg(args):
     out.update({"train_sources": args.sur_train_sources, "train_photons_per_source": args.sur_train_photons,
                 "train_pairs": n_pairs, "train_pairs_all": args.sur_train_sources * len(det.doms),
                 "train_sampling": {"near_m": args.sur_near_m, "far_stride": args.sur_far_stride},
+                "train_structured_frac": args.sur_structured_frac,
                 "label_mc_s": t1 - t0, "ensemble": args.sur_ensemble,
                 "train_epochs": args.sur_epochs, "train_batch": args.sur_batch,
                 "train_lr": [args.sur_lr, args.sur_lr_final],

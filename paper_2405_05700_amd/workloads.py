@@ -266,6 +266,44 @@ def near_module_segments(w: Workload, n_sources: int, photons_per_source, seed: 
     return s
 
 
+def structured_modules(w: Workload, window_m: float = 30.0, rel: float = 0.2) -> np.ndarray:
+    """Ids of the modules whose surroundings have strongly depth-dependent
+    optics: some layer within window_m above or below the module has an
+    absorption or scattering coefficient differing from the module's own
+    layer by more than a factor 1 + rel. In the full-detector ice these are
+    the modules in and around the dust layer."""
+    L = w.layers
+    a = 1.0 / L["abs_len_m"].astype(np.float64)
+    b = 1.0 / (L["eff_scat_len_m"].astype(np.float64) * (1.0 - L["g"].astype(np.float64)))
+    z = w.doms["z"].astype(np.float64)
+
+    def layer(zz):
+        return np.clip(np.floor((zz - w.z_lo_m) / w.dz_m), 0, len(L) - 1).astype(np.int64)
+
+    own = layer(z)
+    dev = np.zeros(len(z))
+    for off in np.arange(-window_m, window_m + 1e-9, 0.5 * w.dz_m):
+        li = layer(z + off)
+        dev = np.maximum(dev, np.maximum(np.abs(np.log(a[li] / a[own])), np.abs(np.log(b[li] / b[own]))))
+    return np.nonzero(dev > np.log1p(rel))[0]
+
+
+def training_targets(w: Workload, n: int, structured_frac: float = 0.4, seed: int = 0) -> np.ndarray:
+    """Target modules for n training segments: a fraction structured_frac
+    drawn uniformly from structured_modules(w), the rest uniformly from all
+    modules, in shuffled order (numpy default_rng(seed): all-module draws,
+    structured draws, shuffle)."""
+    rng = np.random.default_rng(seed)
+    n_s = int(round(structured_frac * n))
+    hard = structured_modules(w)
+    if len(hard) == 0:
+        n_s = 0
+    t = np.concatenate([rng.integers(0, len(w.doms), n - n_s), rng.choice(hard, n_s) if n_s else
+                        np.zeros(0, np.int64)])
+    rng.shuffle(t)
+    return t
+
+
 def power_law_energies(n_events: int, seed: int = 0, index: float = 2.7,
                        e_min: float = 1e2, e_max: float = 1e7) -> np.ndarray:
     """Energies (GeV) from a density proportional to E^-index on
