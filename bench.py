@@ -81,7 +81,7 @@ def parse():
     ap.add_argument("--cpu-photons-per-source", type=int, default=0,
                     help="oracle sample: first N photons of every source (0 = auto, ~15 s)")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--sur-train-sources", type=int, default=48000)
+    ap.add_argument("--sur-train-sources", type=int, default=96000)
     ap.add_argument("--sur-train-photons", type=int, default=2_000_000)
     ap.add_argument("--sur-train-rmax", type=float, default=25.0)
     ap.add_argument("--sur-structured-frac", type=float, default=0.4,
@@ -208,7 +208,7 @@ def cpu_baseline(w, per_source: int):
 
 def surrogate_leg(args):
     """Learned surrogate: an ensemble of four networks trained on the same
-    labels from different initial weights. Training: Monte Carlo of 48000
+    labels from different initial weights. Training: Monte Carlo of 96000
     segments placed 3-25 m from modules of the full detector (40% of them at
     modules whose surroundings have depth-structured optics, the dust
     layer; the rest at random modules); of
@@ -232,6 +232,11 @@ def surrogate_leg(args):
     det = W.full_detector(n_sources=1, photons_per_source=1)
     ctx = pp.Context(0, seed=7)
     ctx.load_workload(det)
+    # segments 3-25 m from a module give about 2e-4 hits per photon: a
+    # 1e8-hit buffer (3.2 GB) holds the label and truth batches, where the
+    # default (photons / 64) would reserve tens of GB; an overflow would
+    # only rerun the batch
+    ctx.set_launch_config(hit_capacity=100_000_000)
     targets = W.training_targets(det, args.sur_train_sources, args.sur_structured_frac, seed=77)
     tr = W.near_module_segments(det, args.sur_train_sources, args.sur_train_photons, seed=101,
                                 r_min=3.0, r_max=args.sur_train_rmax, targets=targets)
