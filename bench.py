@@ -44,6 +44,11 @@ PEAK_BF16_FLOPS = 2.5e15
 PEAK_SLOTS = PEAK_FP32_FLOPS / 2
 
 
+def progress(msg: str):
+    """A progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def measured_traffic():
     """HBM bytes per launch of the propagation kernel from the committed
     rocprofv3 summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's
@@ -245,6 +250,7 @@ def surrogate_leg(args):
     ctx.propagate(b_tr)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    progress(f"surrogate: labels from {args.sur_train_sources} segments in {t1 - t0:.1f} s")
     # an ensemble of independently initialised networks on the same labels;
     # its expectation is the mean of theirs
     members, losses, t_train = [], [], 0.0
@@ -259,6 +265,7 @@ def surrogate_leg(args):
         torch.cuda.synchronize()
         t_train += time.perf_counter() - t2
         members.append(m)
+        progress(f"surrogate: network {seed} of {args.sur_ensemble} trained ({time.perf_counter() - t2:.1f} s)")
     sur = members[0]
     n_pairs = sur.training_size()
     out.update({"train_sources": args.sur_train_sources, "train_photons_per_source": args.sur_train_photons,
@@ -310,6 +317,7 @@ def surrogate_leg(args):
     torch.cuda.synchronize()
     n_truth = int(ev["n_photons"].sum())
     mc_rate = n_truth / (e0.elapsed_time(e1) / 1e3)
+    progress(f"surrogate: truth of {len(ev)} held-out segments ({n_truth:.2e} photons)")
     def ensemble_expectation():
         return (sum(m.expected_hits(b_ev) for m in members) / len(members)).cpu().numpy()
 
@@ -493,6 +501,7 @@ def main():
     t1 = time.perf_counter()
     elapsed = t1 - t0
     kernel_ms = [a.elapsed_time(b) for a, b in ev]
+    progress(f"timed {args.steps} steps: {1e3 * elapsed / args.steps:.2f} ms per step")
     st = ctx.stats(batch)
     assert st["photons"] == n_photons
     assert st["hits"] + st["absorbed"] + st["capped"] + st["escaped"] == n_photons
@@ -538,12 +547,15 @@ def main():
         out["detail"].update(end_to_end(ctx, w))
         out["detail"].update(tiny_rate())
     if not args.no_cpu_baseline:
+        progress("oracle baseline on the host cores")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_photons_per_source)
     sur_params = None
     if not args.no_surrogate:
         ctx.release(batch)
+        progress("surrogate leg")
         out["surrogate"], sur_params = surrogate_leg(args)
     if not args.no_serving:
+        progress("serving leg")
         out["serving"] = serving_leg(args, sur_params)
     print(json.dumps(out), flush=True)
 
