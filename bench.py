@@ -459,7 +459,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the photon "
-              "propagation path is single-GPU in this build.", file=sys.stderr)
+              "propagation path runs on a single GPU.", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.copy_calibration:
