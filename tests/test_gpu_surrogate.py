@@ -259,6 +259,34 @@ def test_far_pair_sampling_follows_rule_and_oracle(mods):
     sur.close()
 
 
+def test_sampling_edge_cases(mods, small_set):
+    """near_m = inf keeps every pair with weight 1 (any stride); near_m = 0
+    keeps exactly the strided pairs, each of weight stride; invalid
+    arguments are refused and leave the setting unchanged."""
+    pp, surrogate, M = mods
+    w, ctx, b, sur0 = small_set
+    n_dom = len(w.doms)
+    sur = surrogate.Surrogate(ctx, seed=2)
+    sur.set_sampling(float("inf"), 16)
+    sur.set_training_set(b)
+    P = sur.training_size()
+    pair, wt = sur.training_pairs(0, P)
+    assert P == 4 * n_dom and np.array_equal(pair, np.arange(P)) and (wt == 1).all()
+    sur.set_sampling(0.0, 7)
+    sur.set_training_set(b)
+    P = sur.training_size()
+    pair, wt = sur.training_pairs(0, P)
+    src, dom = np.divmod(pair.astype(np.int64), n_dom)
+    expect = np.nonzero((np.tile(np.arange(n_dom), 4) + np.repeat(np.arange(4), n_dom)) % 7 == 0)[0]
+    assert np.array_equal(pair.astype(np.int64), expect) and (wt == 7).all()
+    for bad in [(-1.0, 4), (float("nan"), 4), (10.0, 0)]:
+        with pytest.raises(pp.PPError):
+            sur.set_sampling(*bad)
+    sur.set_training_set(b)
+    assert sur.training_size() == P  # the valid setting still applies
+    sur.close()
+
+
 def test_adam_step_matches_definition(mods, small_set):
     pp, surrogate, M = mods
     w, ctx, b, sur = small_set
