@@ -303,6 +303,15 @@ pp_status pp_fetch_hits_device(pp_context *ctx, uint64_t batch, void *dev_out, u
  * buffer may have overflowed (the counts then cover every hit). */
 pp_status pp_dom_counts(pp_context *ctx, uint64_t batch, uint32_t *dev_counts, void *hip_stream);
 
+/* Per-module sums of hit weights: writes n_doms doubles into device memory
+ * dev_sums on hip_stream (same conditions as pp_dom_counts). With the
+ * default unit weights they equal the counts; with a hit acceptance
+ * (pp_set_acceptance) they are the detected-light expectation per module,
+ * the weighted histogram of the hits (Sec. 4: a hit carries a weight). The
+ * order of the additions is not fixed, so the last bits may vary between
+ * calls. */
+pp_status pp_dom_weights(pp_context *ctx, uint64_t batch, double *dev_sums, void *hip_stream);
+
 /* Copies terminal records first .. first + count - 1 of the batch (photons
  * numbered in submission order: source by source, index by index) into
  * host memory out. Needs debug records on when the batch was propagated.

@@ -936,6 +936,18 @@ pp_status pp_dom_counts(pp_context *ctx, uint64_t batch, uint32_t *dev_counts, v
   return note_use(ctx, *b, static_cast<hipStream_t>(hip_stream));
 }
 
+pp_status pp_dom_weights(pp_context *ctx, uint64_t batch, double *dev_sums, void *hip_stream) {
+  if (!ctx || (!dev_sums && ctx->n_doms > 0)) return PP_EINVAL;
+  Batch *b;
+  pp_status st = find_batch(ctx, batch, &b);
+  if (st != PP_OK) return st;
+  if ((st = need_device(ctx)) != PP_OK) return st;
+  if (!b->propagated) return fail(ctx, PP_ESTATE, "batch not propagated");
+  PP_HIP(ctx, pp::launch_dom_weights(b->d_hits, b->d_counters + pp::kHitCount, b->hit_cap, dev_sums, ctx->n_doms,
+                                     static_cast<hipStream_t>(hip_stream)));
+  return note_use(ctx, *b, static_cast<hipStream_t>(hip_stream));
+}
+
 pp_status pp_fetch_records(pp_context *ctx, uint64_t batch, pp_photon_record *out, uint64_t first,
                            uint64_t count) {
   if (!ctx || (count > 0 && !out)) return PP_EINVAL;

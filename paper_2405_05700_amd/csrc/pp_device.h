@@ -134,5 +134,7 @@ hipError_t propagate_occupancy(bool records, bool wave, bool lds_doms, int block
 hipError_t launch_dom_histogram(const DevHit *hits, const unsigned long long *hit_count,
                                 unsigned long long hit_capacity, uint32_t *counts, uint32_t n_doms,
                                 hipStream_t stream);
+hipError_t launch_dom_weights(const DevHit *hits, const unsigned long long *hit_count,
+                              unsigned long long hit_capacity, double *sums, uint32_t n_doms, hipStream_t stream);
 
 }  // namespace pp

@@ -556,6 +556,32 @@ __global__ void k_dom_histogram_global(const DevHit *__restrict__ hits,
   }
 }
 
+// Per-module sums of hit weights (double): a histogram per workgroup in
+// LDS, then one global atomic per non-empty bin; used when n_doms x 8 B fits
+// the LDS budget, else straight global atomics.
+template <bool kLds>
+__global__ void __launch_bounds__(256) k_dom_weights(const DevHit *__restrict__ hits,
+                                                     const unsigned long long *hit_count, unsigned long long cap,
+                                                     double *sums, uint32_t n_doms) {
+  extern __shared__ double wsum[];
+  if (kLds) {
+    for (uint32_t i = threadIdx.x; i < n_doms; i += blockDim.x) wsum[i] = 0.0;
+    __syncthreads();
+  }
+  unsigned long long n = *hit_count;
+  if (n > cap) n = cap;
+  for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    const uint32_t d = hits[i].dom_id;
+    if (d < n_doms) atomicAdd(kLds ? &wsum[d] : &sums[d], (double)hits[i].weight);
+  }
+  if (kLds) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n_doms; i += blockDim.x)
+      if (wsum[i] != 0.0) atomicAdd(&sums[i], wsum[i]);
+  }
+}
+
 }  // namespace
 
 size_t propagate_lds_bytes(int n_layers, int n_strings, int n_cells, int n_lds_doms) {
@@ -635,6 +661,23 @@ hipError_t launch_dom_histogram(const DevHit *hits, const unsigned long long *hi
   } else {
     hipLaunchKernelGGL(k_dom_histogram_global, dim3(256), dim3(256), 0, stream, hits, hit_count,
                        hit_capacity, counts, n_doms);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dom_weights(const DevHit *hits, const unsigned long long *hit_count,
+                              unsigned long long hit_capacity, double *sums, uint32_t n_doms, hipStream_t stream) {
+  if (n_doms == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3(min((2u * n_doms + 255u) / 256u, 1024u)), dim3(256), 0, stream,
+                     reinterpret_cast<uint32_t *>(sums), 2u * n_doms);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (n_doms <= 8192) {
+    hipLaunchKernelGGL(k_dom_weights<true>, dim3(256), dim3(256), n_doms * sizeof(double), stream, hits,
+                       hit_count, hit_capacity, sums, n_doms);
+  } else {
+    hipLaunchKernelGGL(k_dom_weights<false>, dim3(256), dim3(256), 0, stream, hits, hit_count, hit_capacity,
+                       sums, n_doms);
   }
   return hipGetLastError();
 }

@@ -93,6 +93,7 @@ SIGNATURES = {
     "pp_fetch_hits": (C.c_int, [_vp, _u64, _vp, _u64, C.POINTER(_u64)]),
     "pp_fetch_hits_device": (C.c_int, [_vp, _u64, _vp, _u64, C.POINTER(_u64), _vp]),
     "pp_dom_counts": (C.c_int, [_vp, _u64, _vp, _vp]),
+    "pp_dom_weights": (C.c_int, [_vp, _u64, _vp, _vp]),
     "pp_fetch_records": (C.c_int, [_vp, _u64, _vp, _u64, _u64]),
     "pp_get_stats": (C.c_int, [_vp, _u64, C.POINTER(_Stats)]),
     "pp_autotune": (C.c_int, [_vp, _u64, _vp, C.POINTER(_LaunchConfig)]),
@@ -286,6 +287,16 @@ class Context:
             out = torch.empty(max(self.n_doms, 1), dtype=torch.int32, device=f"cuda:{self.device}")
         self._check(_lib.pp_dom_counts(self._h, batch, C.c_void_p(out.data_ptr()),
                                        _stream_handle(stream)))
+        return out[: self.n_doms]
+
+    def dom_weights(self, batch: int, out=None, stream=None):
+        """Per-module sums of hit weights as a float64 CUDA tensor (computed
+        on the device, asynchronously on the stream)."""
+        import torch
+        if out is None:
+            out = torch.empty(max(self.n_doms, 1), dtype=torch.float64, device=f"cuda:{self.device}")
+        self._check(_lib.pp_dom_weights(self._h, batch, C.c_void_p(out.data_ptr()),
+                                        _stream_handle(stream)))
         return out[: self.n_doms]
 
     def fetch_records(self, batch: int, first: int = 0, count: int | None = None) -> np.ndarray:

@@ -326,6 +326,21 @@ def test_hit_weights_match_oracle(pp, oracle):
         "max abs diff", dw.max())
     assert same.mean() >= MIN_AGREE and tight.mean() >= 0.98 and (dw <= 2e-3).mean() >= MIN_AGREE
     assert (hits["weight"] >= 0).all() and hits["weight"].std() > 0.05
+    # per-module weight sums on the device: the weighted histogram of the
+    # fetched hits (up to the order of additions), and the oracle's
+    import torch
+    ctx, b = g["ctx"], g["batch"]
+    sums = ctx.dom_weights(b).cpu().numpy()
+    torch.cuda.synchronize()
+    n_dom = len(w.doms)
+    mine = np.bincount(hits["dom_id"], weights=hits["weight"].astype(np.float64), minlength=n_dom)
+    assert np.allclose(sums, mine, rtol=1e-12, atol=0)
+    hit_ref = ref.fate == oracle.FATE_HIT
+    theirs = np.bincount(ref.dom[hit_ref].astype(np.int64), weights=ref.weight[hit_ref], minlength=n_dom)
+    say("weight sums: total gpu", sums.sum(), "oracle", theirs.sum())
+    assert abs(sums.sum() - theirs.sum()) <= 2e-3 * theirs.sum()
+    busy = theirs > 50
+    assert busy.any() and np.allclose(sums[busy], theirs[busy], rtol=0.02)
 
 
 def test_default_optics_and_weights_unchanged(pp, oracle):
@@ -343,3 +358,9 @@ def test_default_optics_and_weights_unchanged(pp, oracle):
     rec = ctx.fetch_records(b, 0, w.n_photons)
     assert (rec == a["rec"]).all()
     assert (a["hits"]["weight"] == 1.0).all() and (ctx.fetch_hits(b)["weight"] == 1.0).all()
+    # unit weights: the per-module weight sums are the counts
+    import torch
+    sums = ctx.dom_weights(b).cpu().numpy()
+    counts = ctx.dom_counts(b).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(sums, counts.astype(np.float64))
