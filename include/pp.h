@@ -292,6 +292,13 @@ pp_status pp_hit_count(pp_context *ctx, uint64_t batch, uint64_t *n_total);
 pp_status pp_fetch_hits(pp_context *ctx, uint64_t batch, pp_hit *out, uint64_t cap,
                         uint64_t *n_total);
 
+/* Sorts n hits in host memory by (event_id, photon_index), the order in
+ * which a client takes an event's hits back (Sec. 4: hits return to the
+ * process that sent the event). A photon has at most one hit, so the order
+ * is unique. Host only, no context needed; PP_EINVAL if hits is NULL with
+ * n > 0. */
+pp_status pp_sort_hits(pp_hit *hits, uint64_t n);
+
 /* Same, into device memory dev_out (e.g. a torch tensor's data_ptr), copied
  * on hip_stream. */
 pp_status pp_fetch_hits_device(pp_context *ctx, uint64_t batch, void *dev_out, uint64_t cap,

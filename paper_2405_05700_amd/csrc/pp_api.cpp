@@ -936,6 +936,14 @@ pp_status pp_dom_counts(pp_context *ctx, uint64_t batch, uint32_t *dev_counts, v
   return note_use(ctx, *b, static_cast<hipStream_t>(hip_stream));
 }
 
+pp_status pp_sort_hits(pp_hit *hits, uint64_t n) {
+  if (n > 0 && !hits) return PP_EINVAL;
+  std::sort(hits, hits + n, [](const pp_hit &a, const pp_hit &b) {
+    return a.event_id != b.event_id ? a.event_id < b.event_id : a.photon_index < b.photon_index;
+  });
+  return PP_OK;
+}
+
 pp_status pp_dom_weights(pp_context *ctx, uint64_t batch, double *dev_sums, void *hip_stream) {
   if (!ctx || (!dev_sums && ctx->n_doms > 0)) return PP_EINVAL;
   Batch *b;

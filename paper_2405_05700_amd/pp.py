@@ -94,6 +94,7 @@ SIGNATURES = {
     "pp_fetch_hits_device": (C.c_int, [_vp, _u64, _vp, _u64, C.POINTER(_u64), _vp]),
     "pp_dom_counts": (C.c_int, [_vp, _u64, _vp, _vp]),
     "pp_dom_weights": (C.c_int, [_vp, _u64, _vp, _vp]),
+    "pp_sort_hits": (C.c_int, [_vp, _u64]),
     "pp_fetch_records": (C.c_int, [_vp, _u64, _vp, _u64, _u64]),
     "pp_get_stats": (C.c_int, [_vp, _u64, C.POINTER(_Stats)]),
     "pp_autotune": (C.c_int, [_vp, _u64, _vp, C.POINTER(_LaunchConfig)]),
@@ -121,6 +122,17 @@ _lib = load_library()
 
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
+
+
+def sort_hits(hits: np.ndarray) -> np.ndarray:
+    """Sorts a HIT_DTYPE array in place by (event_id, photon_index) with
+    pp_sort_hits; returns it."""
+    if hits.dtype != HIT_DTYPE or not hits.flags["C_CONTIGUOUS"] or not hits.flags["WRITEABLE"]:
+        raise ValueError("sort_hits needs a writable contiguous HIT_DTYPE array")
+    st = _lib.pp_sort_hits(_ptr(hits) if len(hits) else None, len(hits))
+    if st != PP_OK:
+        raise PPError(st, "pp_sort_hits failed")
+    return hits
 
 
 def _stream_handle(stream):
@@ -255,12 +267,16 @@ class Context:
         self._check(_lib.pp_hit_count(self._h, batch, C.byref(n)))
         return n.value
 
-    def fetch_hits(self, batch: int) -> np.ndarray:
+    def fetch_hits(self, batch: int, sort: bool = False) -> np.ndarray:
+        """All hits in host memory; sort=True orders them by (event_id,
+        photon_index) (pp_sort_hits), else the order is unspecified."""
         n = self.hit_count(batch)
         out = np.zeros(n, HIT_DTYPE)
         tot = C.c_uint64()
         self._check(_lib.pp_fetch_hits(self._h, batch, _ptr(out), n, C.byref(tot)))
         assert tot.value == n
+        if sort:
+            sort_hits(out)
         return out
 
     def fetch_hits_into(self, batch: int, out: np.ndarray) -> int:

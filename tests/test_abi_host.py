@@ -271,3 +271,21 @@ def test_admission_plan_policy(pp):
     # the admission cost covers the default hit buffer and grows with photons
     assert server.request_bytes(1, 1000) >= 32 * 65536
     assert server.request_bytes(1, 10**9) > server.request_bytes(1, 10**6)
+
+
+def test_sort_hits_orders_by_event_then_photon(pp):
+    """pp_sort_hits (host only) against numpy's sort of the same records."""
+    rng = np.random.default_rng(8)
+    n = 5000
+    hits = np.zeros(n, pp.HIT_DTYPE)
+    ev = rng.integers(0, 40, n).astype(np.uint32)
+    ph = rng.permutation(10 * n)[:n].astype(np.uint64) + np.uint64(2**40)  # distinct, above 32 bits
+    hits["event_id"], hits["photon_index"] = ev, ph
+    hits["dom_id"] = rng.integers(0, 5160, n)
+    hits["time_ns"] = rng.random(n).astype(np.float32)
+    want = np.sort(hits.copy(), order=["event_id", "photon_index"])
+    got = pp.sort_hits(hits)
+    assert got is hits and (hits == want).all()
+    assert len(pp.sort_hits(np.zeros(0, pp.HIT_DTYPE))) == 0
+    with pytest.raises(ValueError):
+        pp.sort_hits(np.zeros(3, np.float64))
