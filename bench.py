@@ -104,6 +104,8 @@ def parse():
     ap.add_argument("--sur-eval-sets", type=int, default=3,
                     help="held-out target sets of 40 modules (4 segments each)")
     ap.add_argument("--sur-truth-photons", type=int, default=400_000_000)
+    ap.add_argument("--sur-cut-m", type=float, default=300.0,
+                    help="inference distance cut of the speed-up measurement (inf: none)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
@@ -318,6 +320,11 @@ def surrogate_leg(args):
     n_truth = int(ev["n_photons"].sum())
     mc_rate = n_truth / (e0.elapsed_time(e1) / 1e3)
     progress(f"surrogate: truth of {len(ev)} held-out segments ({n_truth:.2e} photons)")
+    # the speed-up path evaluates only pairs within the inference cut (the
+    # throughput figure above is over every pair)
+    for m in members:
+        m.set_inference_cut(args.sur_cut_m)
+
     def ensemble_expectation():
         return (sum(m.expected_hits(b_ev) for m in members) / len(members)).cpu().numpy()
 
@@ -331,7 +338,7 @@ def surrogate_leg(args):
     graded = np.nonzero(truth >= 1e4 * args.sur_truth_photons / 1e8)[0]
     rel = np.abs(pred[graded] - truth[graded]) / truth[graded]
     within = rel <= 0.02
-    res = {"eval_sources": len(ev), "eval_targets": n_cl,
+    res = {"eval_sources": len(ev), "eval_targets": n_cl, "infer_cut_m": args.sur_cut_m,
            "truth_photons_per_source": args.sur_truth_photons, "graded_modules": int(len(graded)),
            "mc_photons_per_s": mc_rate, "t_surrogate_s": t_sur}
     if len(graded):

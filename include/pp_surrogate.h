@@ -114,6 +114,15 @@ pp_status pp_sur_train_step(pp_surrogate *sur, uint64_t first, uint64_t count, f
 pp_status pp_sur_train(pp_surrogate *sur, uint32_t epochs, uint32_t batch_size, float lr, float lr_final,
                        void *hip_stream, float *epoch_loss);
 
+/* Distance beyond which inference takes a pair's expected hits as 0
+ * without evaluating the network (default +inf: no cut). The distance is
+ * from the segment centre to the module centre; a tile of 128 pairs with
+ * none inside the cut is skipped whole. Light is absorbed within about
+ * 100 m in this ice, so a cut of a few hundred metres changes no
+ * expectation that matters and skips most of the detector. PP_EINVAL
+ * unless cut_m > 0. Applies to the two calls below. */
+pp_status pp_sur_set_inference_cut(pp_surrogate *sur, float cut_m);
+
 /* Expected hits (photons of the source times the predicted probability
  * per photon) of every (source, module) pair of the context's batch,
  * summed per module into dev_dom_sums (n_doms doubles in device memory,

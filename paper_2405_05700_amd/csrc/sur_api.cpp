@@ -31,6 +31,7 @@ struct pp_surrogate {
   float *mu_base = nullptr, *nph = nullptr, *k = nullptr, *n_t = nullptr, *s1 = nullptr, *s2 = nullptr;
   float near_m = INFINITY;
   uint32_t far_stride = 1;
+  float cut_m = INFINITY;  // inference distance cut
   int64_t *pair_of_row = nullptr;
   float *w = nullptr;
   // minibatch work buffers (capacity Mcap rows)
@@ -381,6 +382,7 @@ pp_status infer(pp_surrogate *s, Batch &b, hipStream_t st, double *dom_sums, Sin
     a.b[l] = bias_ptr(s, l);
   }
   a.dom_sums = dom_sums;
+  a.cut2 = std::isinf(s->cut_m) ? INFINITY : s->cut_m * s->cut_m;
   // sources per launch: all of them, or as many as the per-pair buffer holds
   const int64_t per_launch =
       pair_sink ? std::max<int64_t>(1, kInferRows / std::max(s->n_doms, 1)) : std::max<int64_t>(n_src, 1);
@@ -590,6 +592,13 @@ pp_status pp_sur_set_sampling(pp_surrogate *s, float near_m, uint32_t far_stride
     return fail(s->ctx, PP_EINVAL, "near_m must be >= 0 (or +inf) and far_stride >= 1");
   s->near_m = near_m;
   s->far_stride = far_stride;
+  return PP_OK;
+}
+
+pp_status pp_sur_set_inference_cut(pp_surrogate *s, float cut_m) {
+  if (!s) return PP_EINVAL;
+  if (!(cut_m > 0.0f)) return fail(s->ctx, PP_EINVAL, "cut_m must be > 0 (or +inf)");
+  s->cut_m = cut_m;
   return PP_OK;
 }
 

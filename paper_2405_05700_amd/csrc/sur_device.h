@@ -156,6 +156,7 @@ struct FusedArgs {
   const float *b[kLayers];       // biases
   double *dom_sums;              // += expected hits per module, may be null
   float *pair_mu;                // expected hits of pair first_pair + i at i, may be null
+  float cut2;                    // pairs farther apart than sqrt(cut2) expect 0 hits (+inf: no cut)
 };
 size_t fused_lds_bytes();
 hipError_t launch_infer_fused(const FusedArgs &a, hipStream_t s);

@@ -493,6 +493,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     float mub = 0.0f, nph = 0.0f, R = 0.0f;
     int dom = -1;
     if (q0 + tid < a.f.n_pairs) pair_features(a.f, a.f.first_pair + q0 + tid, x, mub, nph, R, dom);
+    if (R * R > a.cut2) mub = 0.0f;  // beyond the cut: no light, the pair's expectation is 0
     static_assert(kInReal <= 32, "the first layer reads one K step of 32 inputs");
     uint32_t w[16];
 #pragma unroll
@@ -504,7 +505,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     s_scale[tid] = nph * mub;
     s_dom[tid] = dom;
   }
-  __syncthreads();
+  // A tile with no pair inside the cut skips the network: its pairs expect 0.
+  const bool live = tid < kFusedRows && s_scale[tid] > 0.0f;
+  if (!__syncthreads_or(live)) {
+    if (a.pair_mu && tid < kFusedRows && s_dom[tid] >= 0) a.pair_mu[q0 + tid] = 0.0f;
+    return;
+  }
 
   fused_hidden_layer<32, kInPad>(lds_h, a.w[0], a.b[0], lane, wave);  // kInReal real inputs: one K step of 32
   fused_hidden_layer<kHidden, kHidden>(lds_h, a.w[1], a.b[1], lane, wave);
@@ -530,7 +536,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       const int pr = (2 * wave + j) * 16 + lane;
       const int d = s_dom[pr];
       if (d >= 0) {
-        const float mu = s_scale[pr] * expf((j ? o1[0] : o0[0]) + b);
+        const float sc = s_scale[pr];
+        const float mu = sc > 0.0f ? sc * expf((j ? o1[0] : o0[0]) + b) : 0.0f;
         if (a.dom_sums) atomicAdd(&a.dom_sums[d], (double)mu);
         if (a.pair_mu) a.pair_mu[q0 + pr] = mu;
       }

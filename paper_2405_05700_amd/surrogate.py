@@ -18,6 +18,7 @@ SIGNATURES = {
     "pp_sur_get_params": (C.c_int, [_vp, _vp, _u64]),
     "pp_sur_set_params": (C.c_int, [_vp, _vp, _u64]),
     "pp_sur_set_sampling": (C.c_int, [_vp, C.c_float, _u32]),
+    "pp_sur_set_inference_cut": (C.c_int, [_vp, C.c_float]),
     "pp_sur_set_training_set": (C.c_int, [_vp, _u64]),
     "pp_sur_get_training_pairs": (C.c_int, [_vp, _u64, _u64, _vp, _vp]),
     "pp_sur_training_size": (C.c_int, [_vp, C.POINTER(_u64)]),
@@ -83,6 +84,11 @@ class Surrogate:
         those within near_m plus a weighted 1-in-far_stride sample of the
         rest."""
         self._check(_lib.pp_sur_set_sampling(self._h, near_m, far_stride))
+
+    def set_inference_cut(self, cut_m: float = float("inf")):
+        """Pairs farther apart than cut_m expect 0 hits; tiles of pairs all
+        beyond it skip the network."""
+        self._check(_lib.pp_sur_set_inference_cut(self._h, cut_m))
 
     def set_training_set(self, batch: int):
         self._check(_lib.pp_sur_set_training_set(self._h, batch))

@@ -287,6 +287,41 @@ def test_sampling_edge_cases(mods, small_set):
     sur.close()
 
 
+def test_inference_cut(mods):
+    """With a 300 m cut, pairs farther apart expect exactly 0 hits, pairs
+    inside are bit-identical to the uncut evaluation (whole tiles beyond
+    the cut are skipped, the rest compute as before), and the module sums
+    are the sums of the pairs; invalid cuts are refused."""
+    pp, surrogate, M = mods
+    import torch
+    w = W.full_detector(n_sources=37, photons_per_source=1000, seed=31)
+    ctx = pp.Context(0, seed=0)
+    ctx.load_workload(w)
+    b = ctx.submit(w.sources)
+    sur = surrogate.Surrogate(ctx, seed=6)
+    full = sur.predict_pairs(b, len(w.sources))
+    sur.set_inference_cut(300.0)
+    cut = sur.predict_pairs(b, len(w.sources))
+    sums = sur.expected_hits(b).cpu().numpy()
+    torch.cuda.synchronize()
+    n_dom = len(w.doms)
+    src, dom = np.divmod(np.arange(len(w.sources) * n_dom), n_dom)
+    _, _, R = M.pair_features(w, src, dom)
+    R = R.reshape(len(w.sources), n_dom)
+    inside, outside = R < 300.0 - 1e-3, R > 300.0 + 1e-3
+    say("cut: pairs inside", int(inside.sum()), "outside", int(outside.sum()))
+    assert inside.sum() > 1000 and outside.sum() > 10 * inside.sum()
+    assert (cut[outside] == 0).all() and np.array_equal(cut[inside], full[inside])
+    assert (full[outside] > 0).any()
+    assert np.allclose(sums, cut.astype(np.float64).sum(0), rtol=1e-6, atol=1e-300)
+    for bad in (0.0, -5.0, float("nan")):
+        with pytest.raises(pp.PPError):
+            sur.set_inference_cut(bad)
+    sur.set_inference_cut(float("inf"))
+    assert np.array_equal(sur.predict_pairs(b, len(w.sources)), full)
+    sur.close()
+
+
 def test_adam_step_matches_definition(mods, small_set):
     pp, surrogate, M = mods
     w, ctx, b, sur = small_set
