@@ -297,6 +297,17 @@ def surrogate_leg(args):
                                    "achieved": pairs_inf * INFER_FLOP_PER_PAIR / (t4 - t3) / 1e12,
                                    "peak": PEAK_BF16_FLOPS / 1e12, "unit": "TFLOP/s",
                                    "frac": pairs_inf * INFER_FLOP_PER_PAIR / (t4 - t3) / PEAK_BF16_FLOPS}})
+    # the same workload with the inference cut: tiles wholly beyond it skip
+    # the network (pairs covered per second; the roofline above stays uncut)
+    sur.set_inference_cut(args.sur_cut_m)
+    sur.expected_hits(b_inf)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    sur.expected_hits(b_inf)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    sur.set_inference_cut(float("inf"))
+    out.update({"infer_cut_m": args.sur_cut_m, "infer_cut_s": t4 - t3, "infer_cut_pairs_per_s": pairs_inf / (t4 - t3)})
     ctx.release(b_inf)
 
     # accuracy and speed-up on held-out clusters around target modules: set q
