@@ -1,15 +1,127 @@
-"""Pins of the surrogate's FP64 oracle (oracle/mlp_oracle.py): every
-derivative is checked against central finite differences of the function it
-differentiates, Adam against its closed form for a constant gradient, and
-the features against their geometric meaning."""
+"""Pins of the surrogate's FP64 oracle (oracle/mlp_oracle.py): the
+likelihood values against scipy.stats' Poisson and gamma densities on
+explicit delay lists, every derivative against central finite differences of
+the function it differentiates, GELU against the normal CDF, the diffusion
+baseline against the normalisation and spread that transport theory fixes,
+Adam against its closed form for a constant gradient, and the features
+against their geometric meaning.
+
+PP_MLP_ORACLE names a mutated copy of the oracle to test instead (the
+mutation check in test_oracle_mutations.py)."""
 import dataclasses
+import importlib.util
 import math
+import os
 
 import numpy as np
 import pytest
+from scipy import stats
 
-from oracle import mlp_oracle as M
 from paper_2405_05700_amd import workloads as W
+
+
+def _load_oracle():
+    path = os.environ.get("PP_MLP_ORACLE")
+    if not path:
+        from oracle import mlp_oracle
+        return mlp_oracle
+    spec = importlib.util.spec_from_file_location("mlp_oracle_under_test", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+M = _load_oracle()
+
+
+def test_gelu_is_z_times_the_normal_cdf():
+    z = np.linspace(-9, 9, 3601)
+    # 1 + erf cancels for z << 0: absolute agreement there, relative elsewhere
+    assert np.allclose(M.gelu(z), z * stats.norm.cdf(z), rtol=1e-12, atol=1e-14)
+    mid = z > -4
+    assert np.allclose(M.gelu(z[mid]), z[mid] * stats.norm.cdf(z[mid]), rtol=1e-11, atol=0)
+
+
+def likelihood_grid(seed=17):
+    """Rows over a grid of (mu, kappa, theta, k) with explicit delay lists
+    drawn for each row: (Y, mu_base, N, k, delays)."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for kappa in (0.3, 1.0, 2.5, 7.0):
+        for theta in (3.0, 50.0, 400.0):
+            for j, k in enumerate((0, 1, 4, 23)):
+                mu = (0.2, 3.0, 40.0, 7.5)[(j + len(rows)) % 4]
+                n_ph, mu_base = 2.0e5, 1.0e-5 * (1 + j)
+                delays = rng.gamma(1.7, 0.5 * theta, k) + 0.01
+                y = np.zeros(M.OUT_PAD)
+                y[0] = math.log(mu / (n_ph * mu_base))
+                y[1] = math.log(kappa)
+                y[2] = math.log(theta / M.TAU0_NS)
+                rows.append((y, mu_base, n_ph, k, delays))
+    return rows
+
+
+def scipy_nll(y, mu_base, n_ph, k, delays):
+    """Poisson NLL of k (without its constant lgamma(k + 1)) plus 0.1 x the
+    gamma NLL of the delays (shape exp(y1), scale 50 exp(y2)), by scipy."""
+    mu = n_ph * mu_base * math.exp(y[0])
+    poisson = -stats.poisson.logpmf(k, mu) - math.lgamma(k + 1)
+    gam = -stats.gamma.logpdf(delays, a=math.exp(y[1]), scale=M.TAU0_NS * math.exp(y[2])).sum()
+    return poisson + M.TIME_WEIGHT * gam
+
+
+def test_likelihood_matches_scipy_on_explicit_delays():
+    """The loss of a row, from the sufficient statistics (n, sum of delays,
+    sum of log delays), equals scipy's Poisson and gamma negative
+    log-likelihoods of the count and the delay list itself; and dLoss/dY
+    equals central differences of scipy's value (not of the oracle's)."""
+    for y, mu_base, n_ph, k, delays in likelihood_grid():
+        Y = y[None, :]
+        args = (np.array([mu_base]), np.array([n_ph]), np.array([float(k)]), np.array([float(len(delays))]),
+                np.array([delays.sum()]), np.array([np.log(delays).sum()]))
+        loss, dY = M.loss_and_grad_out(Y, *args)
+        ref = scipy_nll(y, mu_base, n_ph, k, delays)
+        assert abs(loss - ref) <= 1e-9 * max(1.0, abs(ref)), (k, np.exp(y[1]), loss, ref)
+        for col in range(3):
+            h = 1e-5
+            yp, ym = y.copy(), y.copy()
+            yp[col] += h
+            ym[col] -= h
+            fd = (scipy_nll(yp, mu_base, n_ph, k, delays) - scipy_nll(ym, mu_base, n_ph, k, delays)) / (2 * h)
+            assert abs(dY[0, col] - fd) <= 1e-5 * max(1.0, abs(fd)), (col, k, dY[0, col], fd)
+
+
+def test_baseline_is_a_normalised_diffusion_fluence():
+    """mu_base / (pi r^2) is taken as the photon fluence at distance R of a
+    unit isotropic source in homogeneous ice (a small sphere of radius r in
+    an isotropic fluence F meets F pi r^2 photons). Checked by quadrature
+    over R, not against the closed form:
+    * every photon is absorbed: the absorption density F / lambda_a
+      integrates to 1 over all space;
+    * the mean squared distance at absorption is the transport result
+      E[R^2] = 2 lambda_e lambda_a^2 / (lambda_e + lambda_a) (the same moment
+      pins the Monte Carlo oracle), to within lambda_e / lambda_a here;
+    * the hits scale with the module's cross-section, r^2."""
+    lam_a, lam_e = 10000.0, 10.0
+    for r in (0.1651, 2.0):
+        w = W.tiny_point_source(1, dom_radius_m=r, abs_len_m=lam_a, eff_scat_len_m=lam_e)
+        src = W.cherenkov_segments(1, 1, seed=0)
+        src["x"] = src["y"] = 0.0
+        src["z"] = -5.0
+        src["dx"], src["dy"], src["dz"] = 0.0, 0.0, 1.0  # centre at the origin
+        R = np.linspace(0.5, 6000.0, 240_001)
+        doms = np.zeros(len(R), dtype=W.DOM_DTYPE)
+        doms["x"] = R
+        wk = dataclasses.replace(w.with_sources(src), doms=doms)
+        _, mub, Rf = M.pair_features(wk, np.zeros(len(R), int), np.arange(len(R)))
+        R = Rf  # the float32-stored module positions
+        wr = float(wk.dom_radius_m)
+        dens = 4.0 * math.pi * R ** 2 * (mub / (math.pi * wr * wr)) / lam_a
+        total = np.trapezoid(dens, R)
+        msd = np.trapezoid(dens * R ** 2, R) / total
+        transport = 2.0 * lam_e * lam_a ** 2 / (lam_e + lam_a)
+        assert abs(total - 1.0) < 1e-4, total
+        assert abs(msd / transport - 1.0) < 2 * lam_e / lam_a, (msd, transport)
 
 
 def test_gelu_grad_matches_finite_difference():
@@ -230,11 +342,10 @@ def test_features_do_not_depend_on_azimuth():
         assert np.allclose(mub1, mub0, rtol=1e-4)
 
 
-def test_baseline_is_the_diffusion_estimate_in_homogeneous_ice():
-    """In one homogeneous layer the baseline reduces to
-    r^2 exp(-R/delta) / (4 D R), D = lambda_e/3, delta = sqrt(D lambda_a),
-    and matches the oracle Monte Carlo's module rate within a factor of 2 in
-    the diffusive range (an estimate, not an exact law)."""
+def test_baseline_is_near_the_monte_carlo_rate_in_homogeneous_ice():
+    """In one homogeneous layer the baseline matches the oracle Monte
+    Carlo's module rate within a factor of 2 in the diffusive range (an
+    estimate, not an exact law: a sanity check, not a pin)."""
     from oracle import pyoracle
     w = W.tiny_point_source(200_000, dom_radius_m=2.0)
     src = W.cherenkov_segments(1, 200_000, seed=0, length_m=1e-3)
@@ -242,9 +353,6 @@ def test_baseline_is_the_diffusion_estimate_in_homogeneous_ice():
     src["cherenkov_deg"] = 90.0  # nearly isotropic in the vertical direction
     wk = w.with_sources(src)
     _, mub, R = M.pair_features(wk, np.zeros(60, int), np.arange(60))
-    D = 25.0 / 3
-    expect = 4.0 * np.exp(-R / math.sqrt(D * 100.0)) / (4 * D * R)
-    assert np.allclose(mub, expect, rtol=1e-9)
     r = pyoracle.run(wk, records=False, dom_mode=1)
     ratio = r.dom_counts.sum() / (200_000 * mub.sum())
     assert 0.5 < ratio < 2.0, ratio

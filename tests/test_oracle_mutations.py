@@ -66,6 +66,67 @@ def run_mutant(tmp, i, name, old, new):
     return name, r.returncode
 
 
+# Mistakes planted in the surrogate's oracle (oracle/mlp_oracle.py). Where a
+# mistake would be made the same way in a value and its derivative, both are
+# planted, so the finite-difference pins alone cannot see it.
+MLP_MUTANTS = [
+    ("sign of (kappa - 1) sum log delay, in the loss and its gradient",
+     [("- (kappa - 1.0) * s2 + s1 / theta", "+ (kappa - 1.0) * s2 + s1 / theta"),
+      ("np.log(theta)) - s2) / P", "np.log(theta)) + s2) / P")]),
+    ("gamma scale used as a rate, in the loss and its gradient",
+     [("n_t * (special.gammaln(kappa) + kappa * np.log(theta)) - (kappa - 1.0) * s2 + s1 / theta",
+       "n_t * (special.gammaln(kappa) - kappa * np.log(theta)) - (kappa - 1.0) * s2 + s1 * theta"),
+      ("(n_t * (special.digamma(kappa) + np.log(theta)) - s2)", "(n_t * (special.digamma(kappa) - np.log(theta)) - s2)"),
+      ("(n_t * kappa - s1 / theta)", "(-n_t * kappa + s1 * theta)")]),
+    ("sign of k log mu, in the loss and its gradient",
+     [("poisson = mu - k * np.log(mu)", "poisson = mu + k * np.log(mu)"), ("w * (mu - k) / P", "w * (mu + k) / P")]),
+    ("lgamma(kappa) dropped, in the loss and its gradient",
+     [("special.gammaln(kappa) + kappa * np.log(theta)", "kappa * np.log(theta)"),
+      ("special.digamma(kappa) + np.log(theta)", "np.log(theta)")]),
+    ("diffusion constant lambda_e instead of lambda_e / 3", [("D = lam_e / 3.0", "D = lam_e")]),
+    ("diffusion length without D", [("dl = np.sqrt(D * lam_a)", "dl = np.sqrt(lam_e * lam_a)")]),
+    ("module radius instead of its square in the baseline",
+     [("mu_base = r * r * np.exp(-R / dl)", "mu_base = r * np.exp(-R / dl)")]),
+    ("GELU with erf(z / 2), and its derivative",
+     [("special.erf(z / math.sqrt(2.0))", "special.erf(z / 2.0)"),
+      ("z * np.exp(-0.5 * z * z) / math.sqrt(2 * math.pi)", "z * np.exp(-0.25 * z * z) / (2.0 * math.sqrt(math.pi))")]),
+    ("Adam bias correction of v with beta1", [("c2 = 1.0 - self.b2 ** self.t", "c2 = 1.0 - self.b1 ** self.t")]),
+    ("neighbouring scattering feature without (1 - g)",
+     [("X[:, 22 + 2 * q] = 10.0 / (le_all[li] * (1.0 - g_all[li]))", "X[:, 22 + 2 * q] = 10.0 / le_all[li]")]),
+    ("Cherenkov emission point with tan instead of 1/tan",
+     [("(along - b / TAN_CHERENKOV) / L", "(along - b * TAN_CHERENKOV) / L")]),
+    ("GELU derivative dropped from the backward pass", [("g = (g @ W) * gelu_grad(pre[li - 1])", "g = (g @ W)")]),
+    ("weighted loss normalised by the weight sum",
+     [("loss = (w * (poisson + TIME_WEIGHT * gam)).sum() / P", "loss = (w * (poisson + TIME_WEIGHT * gam)).sum() / w.sum()")]),
+    ("far pairs kept with weight 1", [("np.where(near, 1.0, float(far_stride))", "np.where(near, 1.0, 1.0)")]),
+]
+MLP_SRC = os.path.join(ROOT, "oracle", "mlp_oracle.py")
+
+
+def run_mlp_mutant(tmp, i, name, edits):
+    src = open(MLP_SRC).read()
+    for old, new in edits:
+        assert old in src, f"mutation site missing: {name}: {old}"
+        src = src.replace(old, new)
+    path = os.path.join(tmp, f"mlp_mutant{i}.py")
+    with open(path, "w") as f:
+        f.write(src)
+    env = dict(os.environ, PP_MLP_ORACLE=path)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_mlp_oracle.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return name, r.returncode
+
+
+def test_every_planted_surrogate_oracle_mistake_fails_a_pin(tmp_path):
+    workers = max(1, min(4, (os.cpu_count() or 2) // 2))
+    with concurrent.futures.ThreadPoolExecutor(workers) as pool:
+        results = list(pool.map(lambda a: run_mlp_mutant(str(tmp_path), *a),
+                                [(i, *m) for i, m in enumerate(MLP_MUTANTS)]))
+    missed = [name for name, rc in results if rc == 0]
+    assert not missed, f"surrogate-oracle mutants no pin caught: {missed}"
+
+
 def test_every_planted_mistake_fails_a_pin(tmp_path):
     workers = max(1, min(4, (os.cpu_count() or 2) // 2))
     with concurrent.futures.ThreadPoolExecutor(workers) as pool:
