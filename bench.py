@@ -84,7 +84,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the end-to-end and small-workload rates (profiling runs)")
     ap.add_argument("--cpu-photons-per-source", type=int, default=0,
-                    help="oracle sample: first N photons of every source (0 = auto, ~15 s)")
+                    help="oracle sample: first N photons of every source (0 = all of them if that "
+                         "takes at most ~40 s, else a sample of that size)")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--sur-train-sources", type=int, default=96000)
     ap.add_argument("--sur-train-photons", type=int, default=2_000_000)
@@ -101,8 +102,9 @@ def parse():
     ap.add_argument("--sur-lr", type=float, default=1e-3)
     ap.add_argument("--sur-lr-final", type=float, default=1e-5)
     ap.add_argument("--sur-infer-sources", type=int, default=100_000)
-    ap.add_argument("--sur-eval-sets", type=int, default=3,
-                    help="held-out target sets of 40 modules (4 segments each)")
+    ap.add_argument("--sur-eval-sets", type=int, default=4,
+                    help="held-out target sets of 40 modules (4 segments each): the first calibrates the "
+                         "fallback rule, the rest are graded")
     ap.add_argument("--sur-truth-photons", type=int, default=400_000_000)
     ap.add_argument("--sur-cut-m", type=float, default=300.0,
                     help="inference distance cut of the speed-up measurement (inf: none)")
@@ -167,6 +169,56 @@ def tiny_rate():
     return {"tiny_point_source_kernel_ms_median": med, "tiny_point_source_photons_per_s": 1e5 / (med / 1e3)}
 
 
+def uneven_rate():
+    """Batched uneven events: 4096 full-detector segments with E^-2.7 photon
+    counts (round(10 E), E on [1e2, 1e7] GeV, numpy seed 0: 9.72e6 photons,
+    1e3 to 1e8 per event) in one persistent launch. Kernel time (HIP events
+    on the launch stream, median of 5) with the default launch, after the
+    autotuner, and as a replay of the captured HIP graph."""
+    import torch
+    from paper_2405_05700_amd import pp
+    from paper_2405_05700_amd import workloads as W
+    w = W.uneven_events(4096, seed=0)
+    ctx = pp.Context(0, seed=0)
+    ctx.load_workload(w)
+    b = ctx.submit(w.sources)
+    s = torch.cuda.Stream()
+
+    def timed(launch, n=5):
+        launch()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(n):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            launch()
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return sorted(ms)[len(ms) // 2]
+
+    ms_default = timed(lambda: ctx.propagate(b, s))
+    st_default = ctx.stats(b)
+    best = ctx.autotune(b, s)
+    ms_tuned = timed(lambda: ctx.propagate(b, s))
+    st_tuned = ctx.stats(b)
+    ctx.graph_capture(b, s)
+    ms_graph = timed(lambda: ctx.graph_launch(b, s))
+    assert st_tuned["photons"] == st_default["photons"] == w.n_photons
+    assert st_tuned["hits"] == st_default["hits"]
+    ctx.close()
+    n = w.n_photons
+    return {"workload": "4096 full-detector segments, photons round(10 E), E ~ E^-2.7 on [1e2, 1e7] GeV",
+            "photons": n, "events": 4096, "max_event_photons": int(w.sources["n_photons"].max()),
+            "default_launch": {"block_size": st_default["block_size"], "chunk_size": st_default["chunk_size"],
+                               "refill_interval": st_default["refill_interval"]},
+            "kernel_ms_default": ms_default, "photons_per_s_default": n / (ms_default / 1e3),
+            "autotuned_launch": {k: best[k] for k in ("block_size", "chunk_size", "refill_interval")},
+            "kernel_ms_autotuned": ms_tuned, "photons_per_s_autotuned": n / (ms_tuned / 1e3),
+            "autotune_gain": ms_default / ms_tuned,
+            "graph_replay_ms": ms_graph, "photons_per_s_graph": n / (ms_graph / 1e3)}
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -182,7 +234,9 @@ def cpu_baseline(w, per_source: int):
     import numpy as np
     threads = min(16, len(os.sched_getaffinity(0)))
     if per_source == 0:
-        # calibrate on a tiny sample, then size the sample to ~15 s
+        # calibrate on a tiny sample, then take the whole workload if it
+        # takes at most ~40 s on these cores (1e8 photons: ~32 s on 16),
+        # else a sample of that size
         probe = max(20, 2 * threads // len(w.sources) + 1)
         sel_src = np.repeat(np.arange(len(w.sources)), probe)
         sel_loc = np.tile(np.arange(probe), len(w.sources))
@@ -190,15 +244,15 @@ def cpu_baseline(w, per_source: int):
         pyoracle.run(w, sel_src=sel_src, sel_local=sel_loc, dom_mode=1, threads=threads,
                      records=False, dom_counts=False)
         dt = time.perf_counter() - t0
-        per_source = int(max(1, min(w.sources["n_photons"].min(), probe * 15.0 / max(dt, 1e-3))))
+        per_source = int(max(1, min(w.sources["n_photons"].min(), probe * 40.0 / max(dt, 1e-3))))
     sel_src = np.repeat(np.arange(len(w.sources)), per_source)
     sel_loc = np.tile(np.arange(per_source), len(w.sources))
     t0 = time.perf_counter()
     r = pyoracle.run(w, sel_src=sel_src, sel_local=sel_loc, dom_mode=1, threads=threads,
                      records=False, dom_counts=False)
     dt = time.perf_counter() - t0
-    # the same oracle on one thread, over a sixteenth of the sample
-    per1 = max(1, per_source // 16)
+    # the same oracle on one thread, over a fortieth of the sample
+    per1 = max(1, per_source // 40)
     t2 = time.perf_counter()
     r1 = pyoracle.run(w, sel_src=np.repeat(np.arange(len(w.sources)), per1),
                       sel_local=np.tile(np.arange(per1), len(w.sources)), dom_mode=1, threads=1,
@@ -218,18 +272,10 @@ def surrogate_leg(args):
     labels from different initial weights. Training: Monte Carlo of 96000
     segments placed 3-25 m from modules of the full detector (40% of them at
     modules whose surroundings have depth-structured optics, the dust
-    layer; the rest at random modules); of
-    their (segment, module) pairs every pair within 150 m is kept and 1 in
-    64 of the rest, with that weight. Inference throughput: 1e5
-    full-detector segments x 5160 modules. Accuracy and speed-up: clusters
-    of four held-out segments 4-20 m from each of 40 target modules, three
-    such sets; truth = high-statistics Monte Carlo (4e8 photons per
-    segment); graded modules have >= 1e4 truth hits per 1e8 photons per
-    segment (<= 0.5% statistical error at 4e8). Plain Monte Carlo of each
-    cluster needs enough photons for >= 2500 hits (2%) on its graded
-    modules; surrogate+MC takes the surrogate's expectation where it is
-    within 2% of the truth and simulates a cluster only for its failing
-    modules."""
+    layer; the rest at random modules); of their (segment, module) pairs
+    every pair within 150 m is kept and 1 in 64 of the rest, with that
+    weight. Inference throughput: 1e5 full-detector segments x 5160
+    modules. Accuracy and speed-up: hybrid_leg."""
     import numpy as np
     import torch
     from paper_2405_05700_amd import pp, surrogate
@@ -310,95 +356,44 @@ def surrogate_leg(args):
     out.update({"infer_cut_m": args.sur_cut_m, "infer_cut_s": t4 - t3, "infer_cut_pairs_per_s": pairs_inf / (t4 - t3)})
     ctx.release(b_inf)
 
-    # accuracy and speed-up on held-out clusters around target modules: set q
-    # draws 40 targets from default_rng(404 + 101 q) and their segments with
-    # seed 202 + 1000 q
-    n_cl = 40 * args.sur_eval_sets
-    parts = []
-    for q in range(args.sur_eval_sets):
-        targets = np.random.default_rng(404 + 101 * q).choice(len(det.doms), 40, replace=False)
-        parts.append(W.near_module_segments(det, 160, args.sur_truth_photons, seed=202 + 1000 * q, r_min=4.0,
-                                            r_max=20.0, targets=targets, first_event_id=160 * q))
-    ev = np.concatenate(parts)
-    b_ev = ctx.submit(ev)
-    s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    ctx.propagate(b_ev, s)
-    e1.record(s)
-    truth = ctx.dom_counts(b_ev, stream=s).cpu().numpy().astype(np.float64)
-    torch.cuda.synchronize()
-    n_truth = int(ev["n_photons"].sum())
-    mc_rate = n_truth / (e0.elapsed_time(e1) / 1e3)
-    progress(f"surrogate: truth of {len(ev)} held-out segments ({n_truth:.2e} photons)")
-    # the speed-up path evaluates only pairs within the inference cut (the
-    # throughput figure above is over every pair)
-    for m in members:
-        m.set_inference_cut(args.sur_cut_m)
-
-    def ensemble_expectation():
-        return (sum(m.expected_hits(b_ev) for m in members) / len(members)).cpu().numpy()
-
-    ensemble_expectation()  # warm-up, including torch's first use of the tensor ops
-    torch.cuda.synchronize()
-    t5 = time.perf_counter()
-    pred = ensemble_expectation()
-    torch.cuda.synchronize()
-    t_sur = time.perf_counter() - t5
-    per_pair = sum(m.predict_pairs(b_ev, len(ev)).astype(np.float64) for m in members) / len(members)
-    graded = np.nonzero(truth >= 1e4 * args.sur_truth_photons / 1e8)[0]
-    rel = np.abs(pred[graded] - truth[graded]) / truth[graded]
-    within = rel <= 0.02
-    res = {"eval_sources": len(ev), "eval_targets": n_cl, "infer_cut_m": args.sur_cut_m,
-           "truth_photons_per_source": args.sur_truth_photons, "graded_modules": int(len(graded)),
-           "mc_photons_per_s": mc_rate, "t_surrogate_s": t_sur}
-    if len(graded):
-        # A graded module belongs to the cluster (four segments around one
-        # target) that the surrogate says gives it most light. Monte Carlo of
-        # a cluster needs 2500 hits on its dimmest module that must be
-        # simulated: all of them for plain MC, the failing ones for
-        # surrogate+MC. Photons per cluster for module j: 2500 / (truth_j /
-        # photons of the cluster).
-        cl_light = np.stack([per_pair[4 * c:4 * c + 4, graded].sum(0) for c in range(n_cl)])
-        cl = np.argmax(cl_light, axis=0)
-        need = 2500.0 * 4 * args.sur_truth_photons / truth[graded]
-        clusters = np.unique(cl)
-        t_plain = sum(need[cl == c].max() for c in clusters) / mc_rate
-        failing = [c for c in clusters if ((cl == c) & ~within).any()]
-        t_fallback = sum(need[(cl == c) & ~within].max() for c in failing) / mc_rate
-        # the stricter global form: any failing module sends every segment to MC
-        n_glob = args.sur_truth_photons * 2500.0 / truth[graded].min()
-        t_glob = len(ev) * n_glob / mc_rate
-        t_glob_h = t_sur + (len(ev) * args.sur_truth_photons * 2500.0 / truth[graded][~within].min() / mc_rate
-                            if (~within).any() else 0.0)
-        res.update({"per_dom_rel_error_median": float(np.median(rel)),
-                    "per_dom_rel_error_p90": float(np.quantile(rel, 0.9)),
-                    "per_dom_signed_bias_median": float(np.median((pred[graded] - truth[graded]) / truth[graded])),
-                    "frac_modules_within_2pct": float(within.mean()),
-                    "frac_modules_within_5pct": float((rel <= 0.05).mean()),
-                    "clusters": int(len(clusters)), "clusters_passing": int(len(clusters) - len(failing)),
-                    "t_plain_mc_to_2pct_s": t_plain, "t_surrogate_plus_mc_s": t_sur + t_fallback,
-                    "speedup_at_2pct": t_plain / (t_sur + t_fallback),
-                    "speedup_at_2pct_global": t_glob / t_glob_h})
-    out.update(res)
+    out.update(hybrid_leg(args, ctx, det, members, t1 - t0 + t_train))
     params = sur.get_params()
     for m in members:
         m.close()
     return out, params
 
 
+def hybrid_leg(args, ctx, det, members, t_setup):
+    """Surrogate+MC against plain MC, both executed, on held-out clusters of
+    segments around target modules (paper_2405_05700_amd.hybrid.evaluate):
+    set 0 calibrates the fallback rule, the other sets are graded against a
+    4e8-photon truth per segment. Speed-up = plain MC time / (inference
+    time + fallback MC time); the break-even counts the clusters after
+    which the label Monte Carlo and training have paid for themselves."""
+    from paper_2405_05700_amd import hybrid
+    res = hybrid.evaluate(ctx, det, members, n_sets=args.sur_eval_sets, truth_photons=args.sur_truth_photons,
+                          cut_m=args.sur_cut_m, log=progress)
+    saved = (res["t_plain_mc_s"] - res["t_surrogate_s"] - res["t_fallback_mc_s"]) / res["clusters_graded"]
+    res["setup_s"] = t_setup
+    res["break_even_clusters"] = t_setup / saved if saved > 0 else None
+    return res
+
+
 def serving_leg(args, sur_params=None):
-    """Serving loop: 16 client threads submit events (one Cherenkov segment
-    each, N = round(10 E) photons, E ~ E^-2.7 on [1e2, 1e7] GeV) to the
-    photon server (continuous batching, 200 GB HBM budget, surrogate
-    expectations attached).
-    * offered load: Poisson streams totalling 200 events/s for a fixed
-      duration; throughput and p50/p99 event latency from the server's own
+    """Serving loop: 16 native client threads (pp_server_run_clients) submit
+    events (one Cherenkov segment each, N = round(10 E) photons, E ~ E^-2.7
+    on [1e2, 1e7] GeV) to the photon server (device-resident queue,
+    continuous batching over 4 launch slots, 200 GB HBM budget).
+    * offered load: Poisson arrivals totalling 200 events/s for a fixed
+      duration, with the surrogate's per-module expectations attached to
+      every request (computed beside its Monte Carlo; no Monte Carlo work is
+      skipped); throughput and p50/p99 event latency from the server's own
       submit/done stamps;
-    * saturation: each client keeps 32 requests outstanding (a closed loop)
-      for a fixed duration; sustained events/s and photons/s through the
-      server, with the same latency figures."""
-    import threading
+    * saturation: a closed loop with 32 requests outstanding per client for
+      a fixed duration, Monte Carlo only: sustained events/s and photons/s,
+      the same latency figures, events per launch and the GPU busy
+      fraction (union of the launches' device intervals over the wall
+      time)."""
     import numpy as np
     import torch
     from paper_2405_05700_amd import pp, server, surrogate
@@ -407,69 +402,49 @@ def serving_leg(args, sur_params=None):
     base = W.full_detector(n_sources=1, photons_per_source=1)
     ctx = pp.Context(0, seed=0)
     ctx.load_workload(base)
-    sur = None
-    if sur_params is not None:
-        sur = surrogate.Surrogate(ctx, seed=0)
-        sur.set_params(sur_params)
     n_clients = 16
 
-    def events_of(c, n):
-        energies = W.power_law_energies(n, seed=2000 + c)
-        segs = W.cherenkov_segments(n, 1, seed=3000 + c)
+    def events(n, seed):
+        energies = W.power_law_energies(n, seed=seed)
+        segs = W.cherenkov_segments(n, 1, seed=seed + 1)
         segs["n_photons"] = np.rint(10.0 * energies).astype(np.uint64)
-        segs["event_id"] = c * 10_000_000 + np.arange(n)
+        segs["event_id"] = np.arange(n)
         return segs
 
-    def run(mode, duration):
+    def run(mode, duration, sur):
         srv = server.Server(ctx, max_inflight=4, hbm_budget_bytes=200_000_000_000, surrogate=sur)
-        infos, lock = [], threading.Lock()
-
-        def client(c):
-            rng = np.random.default_rng(1000 + c)
-            n_max = int(args.serve_rate * duration / n_clients * 3) + 16 if mode == "poisson" else 400_000
-            segs = events_of(c, n_max)
-            tickets, mine = [], []
-            t_end = time.perf_counter() + duration
-            k = 0
-            while k < len(segs):
-                if mode == "poisson":
-                    time.sleep(rng.exponential(n_clients / args.serve_rate))
-                elif len(tickets) >= 32:
-                    mine.append(srv.wait(tickets.pop(0), expected=sur is not None)[1])
-                if time.perf_counter() >= t_end:
-                    break
-                tickets.append(srv.submit(segs[k:k + 1]))
-                k += 1
-            for t in tickets:
-                mine.append(srv.wait(t, expected=sur is not None)[1])
-            with lock:
-                infos.extend(mine)
-
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        th = [threading.Thread(target=client, args=(c,)) for c in range(n_clients)]
-        for t in th:
-            t.start()
-        for t in th:
-            t.join()
-        wall = time.perf_counter() - t0
+        if mode == "poisson":
+            ev = events(int(args.serve_rate * duration * 2) + 64, seed=2000)
+            r = srv.run_clients(ev, n_clients, rate_per_s=args.serve_rate, duration_s=duration, seed=7)
+        else:
+            ev = events(2_000_000, seed=3000)
+            r = srv.run_clients(ev, n_clients, rate_per_s=0.0, outstanding=32, duration_s=duration)
         st = srv.stats()
         srv.close()
-        lat = np.array([i["t_done_s"] - i["t_submit_s"] for i in infos])
-        photons = sum(i["photons"] for i in infos)
-        span = max(i["t_done_s"] for i in infos) - min(i["t_submit_s"] for i in infos)
-        return {"duration_s": duration, "events": len(infos), "events_per_s": len(infos) / span,
-                "photons_per_s": photons / span,
+        lat = r["latency_s"]
+        return {"duration_s": duration, "events": r["done"], "events_per_s": r["done"] / r["wall_s"],
+                "photons_per_s": r["photons"] / r["wall_s"], "hits": r["hits"],
                 "latency_p50_ms": 1e3 * float(np.percentile(lat, 50)),
                 "latency_p99_ms": 1e3 * float(np.percentile(lat, 99)),
                 "latency_max_ms": 1e3 * float(lat.max()),
                 "launches": st["launches"], "events_per_launch": st["completed"] / max(st["launches"], 1),
-                "peak_device_bytes": st["peak_bytes_in_use"], "wall_s": wall}
+                "overlapped_launches": st["overlapped_launches"],
+                "gpu_busy_frac": st["gpu_busy_s"] / r["wall_s"],
+                "queue_peak_bytes": st["peak_bytes_in_use"], "arena_bytes": st["arena_bytes"],
+                "overflow_bytes_peak": st["overflow_bytes_peak"], "wall_s": r["wall_s"]}
 
-    out = {"clients": n_clients, "offered_events_per_s": args.serve_rate, "surrogate_attached": sur is not None}
-    out.update(run("poisson", args.serve_seconds))
-    out["saturation"] = run("closed", args.serve_saturation_seconds)
+    sur = None
+    if sur_params is not None:
+        sur = surrogate.Surrogate(ctx, seed=0)
+        sur.set_params(sur_params)
+    out = {"clients": n_clients, "client_threads": "native (pp_server_run_clients)",
+           "offered_events_per_s": args.serve_rate, "surrogate_expectations_attached": sur is not None}
+    out.update(run("poisson", args.serve_seconds, sur))
+    out["saturation"] = run("closed", args.serve_saturation_seconds, None)
     out["saturation"]["outstanding_per_client"] = 32
+    if sur is not None:
+        sur.close()
     return out
 
 
@@ -570,6 +545,8 @@ def main():
     if not args.no_extras:
         out["detail"].update(end_to_end(ctx, w))
         out["detail"].update(tiny_rate())
+        progress("batched uneven events")
+        out["detail"]["uneven"] = uneven_rate()
     if not args.no_cpu_baseline:
         progress("oracle baseline on the host cores")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_photons_per_source)

@@ -273,8 +273,18 @@ typedef struct {
 pp_status pp_set_acceptance(pp_context *ctx, const pp_acceptance *acc);
 
 /* Turns per-photon terminal records on or off for later pp_propagate calls
- * (48 bytes of device memory per photon). */
-pp_status pp_set_debug_records(pp_context *ctx, int on);
+ * (48 bytes of device memory per photon). mode:
+ *   PP_RECORDS_OFF: no records (the default).
+ *   PP_RECORDS_ON: records, written by the kernel variant that draws each
+ *     photon's wavelength (so wavelength_nm is always set).
+ *   PP_RECORDS_PRODUCTION: records written by the same kernel variant that
+ *     runs with records off, i.e. the arithmetic the hits come from; that
+ *     variant draws no wavelength unless the optics or an acceptance need
+ *     it, and then wavelength_nm is 0.
+ * A photon's path, fate and hit are the same in every mode (the wavelength
+ * has a random word of its own). PP_EINVAL on another mode. */
+enum { PP_RECORDS_OFF = 0, PP_RECORDS_ON = 1, PP_RECORDS_PRODUCTION = 2 };
+pp_status pp_set_debug_records(pp_context *ctx, int mode);
 
 /* Propagates every photon of the batch: one persistent kernel on hip_stream
  * (a hipStream_t; NULL is the null stream), asynchronous. Ice, geometry and
@@ -305,13 +315,17 @@ pp_status pp_fetch_hits_device(pp_context *ctx, uint64_t batch, void *dev_out, u
                                uint64_t *n_total, void *hip_stream);
 
 /* Per-module hit counts: writes n_doms uint32 counts into device memory
- * dev_counts on hip_stream, from the batch's hits on the device, without
- * synchronising. Needs a complete hit buffer: call after pp_hit_count if the
- * buffer may have overflowed (the counts then cover every hit). */
+ * dev_counts on hip_stream, from the batch's hits on the device. The work on
+ * hip_stream waits for the batch's propagation, whatever stream that ran on.
+ * The counts cover every hit: if the hit buffer could have overflowed
+ * (fewer slots than photons) and pp_hit_count has not been called since the
+ * propagation, the call first checks the count as pp_hit_count does (so it
+ * synchronises the batch's stream, and reruns the batch on overflow);
+ * otherwise it does not synchronise. */
 pp_status pp_dom_counts(pp_context *ctx, uint64_t batch, uint32_t *dev_counts, void *hip_stream);
 
 /* Per-module sums of hit weights: writes n_doms doubles into device memory
- * dev_sums on hip_stream (same conditions as pp_dom_counts). With the
+ * dev_sums on hip_stream (same ordering and completeness as pp_dom_counts). With the
  * default unit weights they equal the counts; with a hit acceptance
  * (pp_set_acceptance) they are the detected-light expectation per module,
  * the weighted histogram of the hits (Sec. 4: a hit carries a weight). The
@@ -322,8 +336,8 @@ pp_status pp_dom_weights(pp_context *ctx, uint64_t batch, double *dev_sums, void
 /* Copies terminal records first .. first + count - 1 of the batch (photons
  * numbered in submission order: source by source, index by index) into
  * host memory out. Needs debug records on when the batch was propagated.
- * wavelength_nm is the photon's drawn wavelength (the debug-record kernel
- * always draws it). */
+ * wavelength_nm is the photon's drawn wavelength, or 0 under
+ * PP_RECORDS_PRODUCTION when the kernel drew none. */
 pp_status pp_fetch_records(pp_context *ctx, uint64_t batch, pp_photon_record *out,
                            uint64_t first, uint64_t count);
 

@@ -298,17 +298,7 @@ void build_geometry(pp_context *ctx, const pp_dom *doms, uint32_t n, float radiu
 pp_status build_chunks(pp_context *ctx, Batch &b, uint32_t chunk) {
   if (b.d_chunks && b.chunk_size == chunk) return PP_OK;
   std::vector<pp::DevChunk> ch;
-  for (uint32_t s = 0; s < b.src.size(); ++s) {
-    const uint64_t begin = b.src[s].seq_base;
-    const uint64_t total = (s + 1 < b.src.size() ? b.src[s + 1].seq_base : b.n_photons) - begin;
-    for (uint64_t l = 0; l < total; l += chunk) {
-      pp::DevChunk c{};
-      c.src = s;
-      c.count = static_cast<uint32_t>(std::min<uint64_t>(chunk, total - l));
-      c.local = l;
-      ch.push_back(c);
-    }
-  }
+  split_chunks(b.src, b.n_photons, chunk, &ch);
   if (ch.size() >= 0xFFFFFFFFull) return fail(ctx, PP_EINVAL, "too many work chunks; raise chunk_size");
   drop_graph(b);
   pp_status st = pool_upload(ctx, &b.d_chunks, ch);
@@ -350,9 +340,12 @@ struct Prepared {
   pp_launch_config used;
 };
 
-// Allocates what the batch needs for the context's launch configuration and
-// fills the kernel arguments. No work is enqueued.
-pp_status prepare(pp_context *ctx, Batch &b, Prepared *out) {
+bool wants_wavelength(const pp_context *ctx) {
+  return (ctx->chroma.lambda_ref_nm > 0 && (ctx->chroma.kappa_abs != 0.0f || ctx->chroma.kappa_scat != 0.0f)) ||
+         !ctx->acc_table.empty();
+}
+
+pp_status launch_shape(pp_context *ctx, uint64_t n_photons, bool records, LaunchShape *out) {
   const pp_launch_config &c = ctx->cfg;
   // With vertical strings each module's (z, id) joins the LDS tables when
   // everything fits; a CU then holds fewer workgroups, so the default
@@ -371,10 +364,8 @@ pp_status prepare(pp_context *ctx, Batch &b, Prepared *out) {
   uint32_t grid = c.grid_blocks;
   if (grid == 0) {
     int per_cu = 0;
-    const bool wave = (ctx->chroma.lambda_ref_nm > 0 &&
-                       (ctx->chroma.kappa_abs != 0.0f || ctx->chroma.kappa_scat != 0.0f)) ||
-                      !ctx->acc_table.empty();
-    PP_HIP(ctx, pp::propagate_occupancy(ctx->records, wave, lds_doms, static_cast<int>(block), lds, &per_cu));
+    const bool wave = wants_wavelength(ctx) || (records && ctx->records_wavelength);
+    PP_HIP(ctx, pp::propagate_occupancy(records, wave, lds_doms, static_cast<int>(block), lds, &per_cu));
     grid = static_cast<uint32_t>(std::max(per_cu, 1) * std::max(ctx->n_cu, 1));
   }
   // Default chunk: 256 ids (measured best on the full detector), smaller
@@ -383,30 +374,23 @@ pp_status prepare(pp_context *ctx, Batch &b, Prepared *out) {
   if (chunk == 0) {
     const uint64_t waves = static_cast<uint64_t>(grid) * (block / 64);
     chunk = static_cast<uint32_t>(std::min<uint64_t>(default_chunk(),
-                                                     std::max<uint64_t>(64, b.n_photons / (waves * 8) + 1)));
+                                                     std::max<uint64_t>(64, n_photons / (waves * 8) + 1)));
   }
-  pp_status st = build_chunks(ctx, b, chunk);
-  if (st != PP_OK) return st;
-  // no more workgroups than there are chunks to share among their wavefronts
-  grid = static_cast<uint32_t>(std::min<uint64_t>(
-      grid, std::max<uint64_t>(1, (static_cast<uint64_t>(b.n_chunks) * 64 + block - 1) / block)));
-  if (!b.d_counters) {
-    void *p = nullptr;
-    if ((st = pool_alloc(ctx, &p, sizeof(unsigned long long) * pp::kNumCounters)) != PP_OK) return st;
-    b.d_counters = static_cast<unsigned long long *>(p);
-  }
-  if (!b.d_hits) {
-    const uint64_t cap = c.hit_capacity ? c.hit_capacity : default_hit_capacity(b.n_photons);
-    st = alloc_hits(ctx, b, cap);
-    if (st != PP_OK) return st;
-  }
-  if (ctx->records) {
-    st = alloc_records(ctx, b);
-    if (st != PP_OK) return st;
-  }
-  if (!b.ev0) PP_HIP(ctx, hipEventCreate(&b.ev0));
-  if (!b.ev1) PP_HIP(ctx, hipEventCreate(&b.ev1));
+  out->block = block;
+  out->grid = grid;
+  out->chunk = chunk;
+  out->lds_doms = lds_doms;
+  return PP_OK;
+}
 
+uint32_t clamp_grid(uint32_t grid, uint32_t block, uint64_t n_chunks) {
+  // no more workgroups than there are chunks to share among their wavefronts
+  return static_cast<uint32_t>(
+      std::min<uint64_t>(grid, std::max<uint64_t>(1, (n_chunks * 64 + block - 1) / block)));
+}
+
+void fill_args(const pp_context *ctx, const LaunchShape &shape, pp::PropagateArgs *out) {
+  const pp_launch_config &c = ctx->cfg;
   pp::PropagateArgs a{};
   a.layers = ctx->d_layers;
   a.bounds = ctx->d_bounds;
@@ -426,20 +410,13 @@ pp_status prepare(pp_context *ctx, Batch &b, Prepared *out) {
   a.ny_max = static_cast<float>(a.ny - 1);
   a.doms = ctx->d_doms;
   a.n_doms = static_cast<int>(ctx->n_doms);
-  a.lds_doms = lds_doms ? 1 : 0;
+  a.lds_doms = shape.lds_doms ? 1 : 0;
   a.radius = ctx->radius;
   a.radius2 = ctx->radius * ctx->radius;
-  a.sources = b.d_src;
-  a.chunks = b.d_chunks;
-  a.n_chunks = b.n_chunks;
   a.seed_lo = static_cast<uint32_t>(ctx->seed);
   a.seed_hi = static_cast<uint32_t>(ctx->seed >> 32);
   a.step_cap = static_cast<uint32_t>(ctx->step_cap);
   a.refill_interval = c.refill_interval ? c.refill_interval : default_refill_interval();
-  a.counters = b.d_counters;
-  a.hits = b.d_hits;
-  a.hit_capacity = b.hit_cap;
-  if (ctx->records) a.rec = b.rec;
   const bool chroma = ctx->chroma.lambda_ref_nm > 0;
   a.inv_lambda_ref = chroma ? 1.0f / ctx->chroma.lambda_ref_nm : 1.0f;
   a.kappa_abs = chroma ? ctx->chroma.kappa_abs : 0.0f;
@@ -452,13 +429,70 @@ pp_status prepare(pp_context *ctx, Batch &b, Prepared *out) {
   for (uint32_t k = 0; k < a.n_poly; ++k) a.poly[k] = ctx->acc_poly[k];
   a.doms_by_id = ctx->d_doms_by_id;
   a.inv_radius = 1.0f / ctx->radius;
+  *out = a;
+}
+
+void split_chunks(const std::vector<pp::DevSource> &src, uint64_t n_photons, uint32_t chunk,
+                  std::vector<pp::DevChunk> *out) {
+  out->clear();
+  for (uint32_t s = 0; s < src.size(); ++s) {
+    const uint64_t begin = src[s].seq_base;
+    const uint64_t total = (s + 1 < src.size() ? src[s + 1].seq_base : n_photons) - begin;
+    for (uint64_t l = 0; l < total; l += chunk) {
+      pp::DevChunk c{};
+      c.src = s;
+      c.count = static_cast<uint32_t>(std::min<uint64_t>(chunk, total - l));
+      c.local = l;
+      out->push_back(c);
+    }
+  }
+}
+
+// Allocates what the batch needs for the context's launch configuration and
+// fills the kernel arguments. No work is enqueued.
+pp_status prepare(pp_context *ctx, Batch &b, Prepared *out) {
+  const pp_launch_config &c = ctx->cfg;
+  LaunchShape shape;
+  pp_status st = launch_shape(ctx, b.n_photons, ctx->records, &shape);
+  if (st != PP_OK) return st;
+  if ((st = build_chunks(ctx, b, shape.chunk)) != PP_OK) return st;
+  const uint32_t grid = clamp_grid(shape.grid, shape.block, b.n_chunks);
+  if (!b.d_counters) {
+    void *p = nullptr;
+    if ((st = pool_alloc(ctx, &p, sizeof(unsigned long long) * pp::kNumCounters)) != PP_OK) return st;
+    b.d_counters = static_cast<unsigned long long *>(p);
+  }
+  if (!b.d_hits) {
+    const uint64_t cap = c.hit_capacity ? c.hit_capacity : default_hit_capacity(b.n_photons);
+    st = alloc_hits(ctx, b, cap);
+    if (st != PP_OK) return st;
+  }
+  if (ctx->records) {
+    st = alloc_records(ctx, b);
+    if (st != PP_OK) return st;
+  }
+  if (!b.ev0) PP_HIP(ctx, hipEventCreate(&b.ev0));
+  if (!b.ev1) PP_HIP(ctx, hipEventCreate(&b.ev1));
+
+  pp::PropagateArgs a;
+  fill_args(ctx, shape, &a);
+  a.sources = b.d_src;
+  a.chunks = b.d_chunks;
+  a.n_chunks = b.n_chunks;
+  a.counters = b.d_counters;
+  a.hits = b.d_hits;
+  a.hit_capacity = b.hit_cap;
+  if (ctx->records) {
+    a.rec = b.rec;
+    a.records_wavelength = ctx->records_wavelength ? 1 : 0;
+  }
 
   out->args = a;
   out->grid = grid;
-  out->block = block;
+  out->block = shape.block;
   out->used = c;
-  out->used.block_size = block;
-  out->used.chunk_size = chunk;
+  out->used.block_size = shape.block;
+  out->used.chunk_size = shape.chunk;
   out->used.grid_blocks = grid;
   out->used.refill_interval = a.refill_interval;
   out->used.hit_capacity = b.hit_cap;
@@ -474,11 +508,13 @@ pp_status enqueue(pp_context *ctx, Batch &b, const Prepared &p, hipStream_t stre
   return PP_OK;
 }
 
-void mark_propagated(pp_context *ctx, Batch &b, const pp_launch_config &used, bool records, hipStream_t stream) {
-  (void)ctx;
+void mark_propagated(Batch &b, const pp_launch_config &used, bool records, bool rec_wavelength,
+                     hipStream_t stream) {
   b.stream = stream;
   b.propagated = true;
   b.rec_valid = records;
+  b.rec_wavelength = records && rec_wavelength;
+  b.hits_complete = false;
   b.used = used;
 }
 
@@ -489,7 +525,7 @@ pp_status launch(pp_context *ctx, Batch &b, hipStream_t stream) {
   PP_HIP(ctx, hipEventRecord(b.ev0, stream));
   if ((st = enqueue(ctx, b, p, stream)) != PP_OK) return st;
   PP_HIP(ctx, hipEventRecord(b.ev1, stream));
-  mark_propagated(ctx, b, p.used, ctx->records, stream);
+  mark_propagated(b, p.used, ctx->records, ctx->records_wavelength, stream);
   return PP_OK;
 }
 
@@ -512,13 +548,15 @@ pp_status complete_hits(pp_context *ctx, Batch &b, uint64_t *n_total) {
     st = alloc_hits(ctx, b, need + need / 8 + 1024);
     if (st != PP_OK) return st;
     const pp_launch_config saved = ctx->cfg;
-    const bool saved_rec = ctx->records;
+    const bool saved_rec = ctx->records, saved_wave = ctx->records_wavelength;
     ctx->cfg = b.used;
     ctx->cfg.hit_capacity = 0;
     ctx->records = b.rec_valid;
+    ctx->records_wavelength = b.rec_wavelength;
     st = launch(ctx, b, b.stream);
     ctx->cfg = saved;
     ctx->records = saved_rec;
+    ctx->records_wavelength = saved_wave;
     if (st != PP_OK) return st;
     st = sync_counters(ctx, b, cnt);
     if (st != PP_OK) return st;
@@ -527,6 +565,22 @@ pp_status complete_hits(pp_context *ctx, Batch &b, uint64_t *n_total) {
                   cnt[pp::kHitCount], (unsigned long long)need);
   }
   *n_total = cnt[pp::kHitCount];
+  b.hits_complete = true;
+  return PP_OK;
+}
+
+// Makes the batch's complete hit buffer visible to work enqueued next on
+// stream: if the buffer could have overflowed and its count has not been
+// checked since the propagation, checks it (synchronising the batch's stream
+// and rerunning on overflow); then orders stream after the propagation.
+pp_status hits_ready_on(pp_context *ctx, Batch &b, hipStream_t stream) {
+  if (!b.propagated) return fail(ctx, PP_ESTATE, "batch not propagated");
+  if (!b.hits_complete && b.hit_cap < b.n_photons) {
+    uint64_t n = 0;
+    pp_status st = complete_hits(ctx, b, &n);
+    if (st != PP_OK) return st;
+  }
+  PP_HIP(ctx, hipStreamWaitEvent(stream, b.ev1, 0));
   return PP_OK;
 }
 
@@ -726,9 +780,12 @@ pp_status pp_set_acceptance(pp_context *ctx, const pp_acceptance *acc) {
   return PP_OK;
 }
 
-pp_status pp_set_debug_records(pp_context *ctx, int on) {
+pp_status pp_set_debug_records(pp_context *ctx, int mode) {
   if (!ctx) return PP_EINVAL;
-  ctx->records = on != 0;
+  if (mode != PP_RECORDS_OFF && mode != PP_RECORDS_ON && mode != PP_RECORDS_PRODUCTION)
+    return fail(ctx, PP_EINVAL, "records mode %d is not PP_RECORDS_OFF, _ON or _PRODUCTION", mode);
+  ctx->records = mode != PP_RECORDS_OFF;
+  ctx->records_wavelength = mode == PP_RECORDS_ON;
   return PP_OK;
 }
 
@@ -930,7 +987,7 @@ pp_status pp_dom_counts(pp_context *ctx, uint64_t batch, uint32_t *dev_counts, v
   pp_status st = find_batch(ctx, batch, &b);
   if (st != PP_OK) return st;
   if ((st = need_device(ctx)) != PP_OK) return st;
-  if (!b->propagated) return fail(ctx, PP_ESTATE, "batch not propagated");
+  if ((st = hits_ready_on(ctx, *b, static_cast<hipStream_t>(hip_stream))) != PP_OK) return st;
   PP_HIP(ctx, pp::launch_dom_histogram(b->d_hits, b->d_counters + pp::kHitCount, b->hit_cap, dev_counts,
                                        ctx->n_doms, static_cast<hipStream_t>(hip_stream)));
   return note_use(ctx, *b, static_cast<hipStream_t>(hip_stream));
@@ -950,7 +1007,7 @@ pp_status pp_dom_weights(pp_context *ctx, uint64_t batch, double *dev_sums, void
   pp_status st = find_batch(ctx, batch, &b);
   if (st != PP_OK) return st;
   if ((st = need_device(ctx)) != PP_OK) return st;
-  if (!b->propagated) return fail(ctx, PP_ESTATE, "batch not propagated");
+  if ((st = hits_ready_on(ctx, *b, static_cast<hipStream_t>(hip_stream))) != PP_OK) return st;
   PP_HIP(ctx, pp::launch_dom_weights(b->d_hits, b->d_counters + pp::kHitCount, b->hit_cap, dev_sums, ctx->n_doms,
                                      static_cast<hipStream_t>(hip_stream)));
   return note_use(ctx, *b, static_cast<hipStream_t>(hip_stream));
@@ -1089,6 +1146,7 @@ pp_status pp_graph_capture(pp_context *ctx, uint64_t batch, void *hip_stream) {
   b->graph = exec;
   b->graph_cfg = p.used;
   b->graph_records = ctx->records;
+  b->graph_rec_wavelength = ctx->records_wavelength;
   return PP_OK;
 }
 
@@ -1103,7 +1161,7 @@ pp_status pp_graph_launch(pp_context *ctx, uint64_t batch, void *hip_stream) {
   PP_HIP(ctx, hipEventRecord(b->ev0, stream));
   PP_HIP(ctx, hipGraphLaunch(b->graph, stream));
   PP_HIP(ctx, hipEventRecord(b->ev1, stream));
-  mark_propagated(ctx, *b, b->graph_cfg, b->graph_records, stream);
+  mark_propagated(*b, b->graph_cfg, b->graph_records, b->graph_rec_wavelength, stream);
   return PP_OK;
 }
 

@@ -111,6 +111,9 @@ struct PropagateArgs {
   float poly[kMaxPoly];
   const float4 *doms_by_id;  // module centres by module id
   float inv_radius;
+  // debug records draw each photon's wavelength even when nothing else
+  // needs it (0: records come from the variant that runs without them)
+  int records_wavelength;
   // outputs
   unsigned long long *counters;
   DevHit *hits;
@@ -127,8 +130,9 @@ constexpr size_t kMaxPropagateLds = 152 * 1024;
 
 hipError_t launch_reset(unsigned long long *counters, int n, hipStream_t stream);
 hipError_t launch_propagate(const PropagateArgs &args, int grid, int block, hipStream_t stream);
-// records: debug records on; wave: wavelength-dependent optics or hit
-// acceptance (the kernel variant that draws wavelengths).
+// records: debug records on; wave: the kernel variant that draws
+// wavelengths (wavelength-dependent optics, hit acceptance, or records that
+// ask for the wavelength).
 hipError_t propagate_occupancy(bool records, bool wave, bool lds_doms, int block, size_t lds_bytes,
                                int *blocks_per_cu);
 hipError_t launch_dom_histogram(const DevHit *hits, const unsigned long long *hit_count,

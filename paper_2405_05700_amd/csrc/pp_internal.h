@@ -11,6 +11,8 @@
 #include "../../include/pp.h"
 #include "pp_device.h"
 
+struct pp_surrogate;
+
 namespace ppi {
 
 constexpr uint32_t kMaxLayers = 1024;
@@ -31,14 +33,15 @@ struct Batch {
   uint64_t hit_cap = 0;
   void *d_rec = nullptr;
   pp::Records rec{};
-  bool propagated = false, rec_valid = false;
+  bool propagated = false, rec_valid = false, rec_wavelength = false;
+  bool hits_complete = false;  // hit count checked against the buffer since the last propagation
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t ev_use = nullptr;  // after the last other enqueued work that reads the batch's buffers
   pp_launch_config used{};
   hipGraphExec_t graph = nullptr;  // captured reset + propagation, if any
   pp_launch_config graph_cfg{};
-  bool graph_records = false;
+  bool graph_records = false, graph_rec_wavelength = false;
 };
 
 }  // namespace ppi
@@ -50,6 +53,7 @@ struct pp_context {
   pp_launch_config cfg{};
   uint64_t step_cap = ppi::kDefaultStepCap;
   bool records = false;
+  bool records_wavelength = false;  // records from the wavelength-drawing kernel variant
   int n_cu = 0;
   // ice
   bool ice_loaded = false;
@@ -99,6 +103,27 @@ inline uint64_t batch_device_bytes(uint64_t n_sources, uint64_t n_photons, uint6
                                    uint64_t hit_capacity) {
   return 80 * n_sources + 16 * (n_sources + n_photons / chunk + 1) + 8 * 16 + 32 * hit_capacity;
 }
+// Launch shape of one propagation: workgroup size, workgroups (before the
+// clamp to the number of work chunks), photon ids per chunk, and whether the
+// modules' (z, id) pairs are staged in LDS.
+struct LaunchShape {
+  uint32_t block, grid, chunk;
+  bool lds_doms;
+};
+// Shape for n_photons photons under the context's launch configuration.
+pp_status launch_shape(pp_context *ctx, uint64_t n_photons, bool records, LaunchShape *out);
+uint32_t clamp_grid(uint32_t grid, uint32_t block, uint64_t n_chunks);
+// Kernel arguments that come from the context (ice, geometry, optics, seed,
+// step cap); work, counters and outputs are left for the caller.
+void fill_args(const pp_context *ctx, const LaunchShape &shape, pp::PropagateArgs *out);
+// Work-queue entries of at most chunk photon ids, source by source.
+void split_chunks(const std::vector<pp::DevSource> &src, uint64_t n_photons, uint32_t chunk,
+                  std::vector<pp::DevChunk> *out);
+bool wants_wavelength(const pp_context *ctx);
+// Expected hits of every (source, module) pair of a batch that need not be
+// registered with the context (host records b.src, device records b.d_src),
+// source-major into host memory out (b.src.size() x n_doms floats).
+pp_status sur_predict_batch(pp_surrogate *s, Batch &b, float *out);
 pp_status fail(pp_context *ctx, pp_status st, const char *fmt, ...);
 pp_status need_device(pp_context *ctx);
 pp_status find_batch(pp_context *ctx, uint64_t id, Batch **out);

@@ -203,8 +203,10 @@ __device__ __forceinline__ float hit_weight(const PropagateArgs &a, uint32_t dom
 }
 
 // kWave: the photon's wavelength matters (wavelength-dependent optics, hit
-// acceptance or debug records). Without it the kernel draws no wavelength
-// and scales nothing, and every hit weighs 1.
+// acceptance, or debug records that ask for it). Without it the kernel draws
+// no wavelength and scales nothing, and every hit weighs 1; its photons take
+// the same paths, since the wavelength has a Philox word of its own.
+// kRecords: per-photon terminal records (parity checks only).
 // kLdsDoms: every string is vertical, so a module is its string's centre
 // and a (z, id) pair, and the pairs of all modules are staged in LDS (8
 // bytes each): the ray-sphere tests of the few lanes near a string then read
@@ -212,7 +214,6 @@ __device__ __forceinline__ float hit_weight(const PropagateArgs &a, uint32_t dom
 template <bool kRecords, bool kWave, bool kLdsDoms>
 __global__ void __launch_bounds__(1024)
 k_propagate(const PropagateArgs a) {
-  static_assert(kWave || !kRecords, "records carry the wavelength");
   extern __shared__ __align__(16) unsigned char lds_raw[];
   DevLayer *s_layers = reinterpret_cast<DevLayer *>(lds_raw);
   DevString *s_strings = reinterpret_cast<DevString *>(s_layers + a.n_layers);
@@ -295,7 +296,7 @@ k_propagate(const PropagateArgs a) {
         a.rec.vx[seq] = vx;
         a.rec.vy[seq] = vy;
         a.rec.vz[seq] = vz;
-        a.rec.wavelength[seq] = lambda;
+        a.rec.wavelength[seq] = kWave ? lambda : 0.0f;  // a variant without kWave draws none
       }
       if (ended) phase = kFree;
 
@@ -625,9 +626,13 @@ hipError_t occupancy_variant(int block, size_t lds, int *per_cu) {
 hipError_t launch_propagate(const PropagateArgs &args, int grid, int block, hipStream_t stream) {
   const bool L = args.lds_doms != 0;
   const size_t lds = propagate_lds_bytes(args.n_layers, args.n_strings, args.nx * args.ny, L ? args.n_doms : 0);
-  if (args.rec.fate != nullptr)
-    return L ? launch_variant<true, true, true>(args, grid, block, lds, stream)
-             : launch_variant<true, true, false>(args, grid, block, lds, stream);
+  if (args.rec.fate != nullptr) {
+    if (needs_wave(args) || args.records_wavelength)
+      return L ? launch_variant<true, true, true>(args, grid, block, lds, stream)
+               : launch_variant<true, true, false>(args, grid, block, lds, stream);
+    return L ? launch_variant<true, false, true>(args, grid, block, lds, stream)
+             : launch_variant<true, false, false>(args, grid, block, lds, stream);
+  }
   if (needs_wave(args))
     return L ? launch_variant<false, true, true>(args, grid, block, lds, stream)
              : launch_variant<false, true, false>(args, grid, block, lds, stream);
@@ -637,9 +642,12 @@ hipError_t launch_propagate(const PropagateArgs &args, int grid, int block, hipS
 
 hipError_t propagate_occupancy(bool records, bool wave, bool lds_doms, int block, size_t lds_bytes,
                                int *blocks_per_cu) {
-  if (records)
+  if (records && wave)
     return lds_doms ? occupancy_variant<true, true, true>(block, lds_bytes, blocks_per_cu)
                     : occupancy_variant<true, true, false>(block, lds_bytes, blocks_per_cu);
+  if (records)
+    return lds_doms ? occupancy_variant<true, false, true>(block, lds_bytes, blocks_per_cu)
+                    : occupancy_variant<true, false, false>(block, lds_bytes, blocks_per_cu);
   if (wave)
     return lds_doms ? occupancy_variant<false, true, true>(block, lds_bytes, blocks_per_cu)
                     : occupancy_variant<false, true, false>(block, lds_bytes, blocks_per_cu);

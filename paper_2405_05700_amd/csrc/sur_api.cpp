@@ -18,6 +18,7 @@ using namespace ppi;
 
 struct pp_surrogate {
   pp_context *ctx = nullptr;
+  int device = -1;  // the context's device (teardown does not read the context)
   int n_doms = 0;
   // parameters (f32 master), gradient, Adam moments, bf16 copies
   float *theta = nullptr, *grad = nullptr, *adam_m = nullptr, *adam_v = nullptr;
@@ -41,6 +42,10 @@ struct pp_surrogate {
   float *Y = nullptr;
   uint16_t *dY = nullptr, *dYT = nullptr, *dZ[2] = {}, *dZT = nullptr;
   double *d_loss = nullptr;
+  // fixed-order reductions: split-K partials of the weight gradients,
+  // per-32-row column sums of the bias gradients, per-workgroup loss parts
+  float *ws = nullptr, *col_part = nullptr, *bias_part = nullptr;
+  double *loss_part = nullptr;
   double *epoch_loss = nullptr;  // device accumulator while training, else null
   // shuffled minibatch staging (capacity Gcap rows) and shuffle state
   int64_t Gcap = 0;
@@ -58,6 +63,7 @@ struct pp_surrogate {
 namespace {
 
 constexpr int64_t kInferRows = 1 << 21;  // pairs per inference chunk
+constexpr int kMaxSplits = 64;            // K slices of a weight-gradient GEMM
 
 int64_t round64(int64_t n) { return (n + 63) / 64 * 64; }
 
@@ -88,7 +94,8 @@ OnExit<F> on_exit(F f) {
 
 pp_status gemm(pp_context *ctx, int epi, const uint16_t *A, int64_t lda, const uint16_t *B, int64_t ldb, int M,
                int N, int K, int splits, const float *bias, float *Z, uint16_t *H, uint16_t *HT, int64_t ldt,
-               const float *Zin, float *out, hipStream_t st, float *col_sums = nullptr) {
+               const float *Zin, float *out, hipStream_t st, float *col_sums = nullptr, float *ws = nullptr,
+               float *col_part = nullptr) {
   sur::GemmArgs g{};
   g.A = A;
   g.lda = lda;
@@ -107,7 +114,9 @@ pp_status gemm(pp_context *ctx, int epi, const uint16_t *A, int64_t lda, const u
   g.ldt = ldt;
   g.Zin = Zin;
   g.out = out;
+  g.ws = ws;
   g.col_sums = col_sums;
+  g.col_part = col_sums ? col_part : nullptr;
   PP_HIP(ctx, sur::launch_gemm(epi, g, splits, st));
   return PP_OK;
 }
@@ -131,6 +140,11 @@ pp_status ensure_work(pp_surrogate *s, int64_t M) {
   if ((st = dalloc(ctx, &s->dZ[0], M * sur::kHidden)) != PP_OK) return st;
   if ((st = dalloc(ctx, &s->dZ[1], M * sur::kHidden)) != PP_OK) return st;
   if ((st = dalloc(ctx, &s->dZT, M * sur::kHidden)) != PP_OK) return st;
+  if ((st = dalloc(ctx, &s->col_part, (M / 32) * sur::kHidden)) != PP_OK) return st;
+  if ((st = dalloc(ctx, &s->loss_part, sur::loss_blocks(static_cast<int>(M)))) != PP_OK) return st;
+  if ((st = dalloc(ctx, &s->bias_part, 3 * static_cast<int64_t>(sur::loss_blocks(static_cast<int>(M))))) != PP_OK)
+    return st;
+  if (!s->ws && (st = dalloc(ctx, &s->ws, int64_t{kMaxSplits} * sur::kHidden * sur::kHidden)) != PP_OK) return st;
   s->Mcap = M;
   return PP_OK;
 }
@@ -182,8 +196,6 @@ pp_status forward_backward(pp_surrogate *s, const Rows &r, int64_t count, hipStr
                  nullptr, nullptr, nullptr, 0, nullptr, s->Y, st)) != PP_OK)
     return rc;
   // loss and output gradient
-  PP_HIP(ctx, launch_zero_f64(s->d_loss, 1, st));
-  PP_HIP(ctx, launch_zero_f32(s->grad, param_count(), st));  // the loss and GELU-backward kernels add bias gradients
   LossArgs la{};
   la.Y = s->Y;
   la.mu_base = r.mu_base;
@@ -201,30 +213,33 @@ pp_status forward_backward(pp_surrogate *s, const Rows &r, int64_t count, hipStr
   la.loss_sum = s->d_loss;
   la.loss_epoch = s->epoch_loss;
   la.out_bias_grad = s->grad + b_offset(4);
+  la.loss_part = s->loss_part;
+  la.bias_part = s->bias_part;
   PP_HIP(ctx, launch_loss(la, st));
-  // backward
-  const int splits = std::max(1, M / 512);
+  // backward: every gradient element is written once (no accumulation)
+  const int splits = std::min(kMaxSplits, std::max(1, M / 512));
   // output layer
-  if ((rc = gemm(ctx, kEpiAccum, s->dYT, M, s->HT[3], M, kOutPad, kHidden, M, splits, nullptr, nullptr, nullptr,
-                 nullptr, 0, nullptr, s->grad + w_offset(4), st)) != PP_OK)
+  if ((rc = gemm(ctx, kEpiSplitK, s->dYT, M, s->HT[3], M, kOutPad, kHidden, M, splits, nullptr, nullptr, nullptr,
+                 nullptr, 0, nullptr, s->grad + w_offset(4), st, nullptr, s->ws)) != PP_OK)
     return rc;
   // dZ3 = (dY . W4) * gelu'(Z3), and db3 = column sums of dZ3
   if ((rc = gemm(ctx, kEpiGeluBwd, s->dY, kOutPad, wt_ptr(s, 4), kOutPad, M, kHidden, kOutPad, 1, nullptr,
-                 nullptr, s->dZ[1], s->dZT, M, s->Z[3], nullptr, st, s->grad + b_offset(3))) != PP_OK)
+                 nullptr, s->dZ[1], s->dZT, M, s->Z[3], nullptr, st, s->grad + b_offset(3), nullptr, s->col_part)) !=
+      PP_OK)
     return rc;
   int cur = 1;
   for (int l = 3; l >= 0; --l) {
     // dW_l = dZ_l^T . H_{l-1} (X for l = 0); db_l came with dZ_l
     const uint16_t *prevT = l > 0 ? s->HT[l - 1] : XT;
     const int64_t ld_prevT = l > 0 ? M : r.ld_XT;
-    if ((rc = gemm(ctx, kEpiAccum, s->dZT, M, prevT, ld_prevT, kHidden, in_dim(l), M, splits, nullptr, nullptr,
-                   nullptr, nullptr, 0, nullptr, s->grad + w_offset(l), st)) != PP_OK)
+    if ((rc = gemm(ctx, kEpiSplitK, s->dZT, M, prevT, ld_prevT, kHidden, in_dim(l), M, splits, nullptr, nullptr,
+                   nullptr, nullptr, 0, nullptr, s->grad + w_offset(l), st, nullptr, s->ws)) != PP_OK)
       return rc;
     if (l == 0) break;
     // dZ_{l-1} = (dZ_l . W_l) * gelu'(Z_{l-1}), and its column sums db_{l-1}
     if ((rc = gemm(ctx, kEpiGeluBwd, s->dZ[cur], kHidden, wt_ptr(s, l), kHidden, M, kHidden, kHidden, 1, nullptr,
-                   nullptr, s->dZ[1 - cur], s->dZT, M, s->Z[l - 1], nullptr, st, s->grad + b_offset(l - 1))) !=
-        PP_OK)
+                   nullptr, s->dZ[1 - cur], s->dZT, M, s->Z[l - 1], nullptr, st, s->grad + b_offset(l - 1), nullptr,
+                   s->col_part)) != PP_OK)
       return rc;
     cur = 1 - cur;
   }
@@ -426,6 +441,7 @@ pp_status pp_sur_create(pp_context *ctx, uint64_t init_seed, pp_surrogate **out)
   pp_surrogate *s = new (std::nothrow) pp_surrogate;
   if (!s) return PP_ENOMEM;
   s->ctx = ctx;
+  s->device = ctx->device;
   s->n_doms = static_cast<int>(ctx->n_doms);
   const int64_t np = sur::param_count();
   if ((st = dalloc(ctx, &s->theta, np)) != PP_OK || (st = dalloc(ctx, &s->grad, np)) != PP_OK ||
@@ -434,6 +450,13 @@ pp_status pp_sur_create(pp_context *ctx, uint64_t init_seed, pp_surrogate **out)
       (st = dalloc(ctx, &s->d_loss, 1)) != PP_OK) {
     pp_sur_destroy(s);
     return st;
+  }
+  // Every gradient element a step computes is overwritten by it; the
+  // output-layer bias entries past the real outputs are never computed and
+  // stay 0.
+  if (sur::launch_zero_f32(s->grad, np, nullptr) != hipSuccess) {
+    pp_sur_destroy(s);
+    return fail(ctx, PP_EDEVICE, "clearing the gradient failed");
   }
   // module centres in module-id order
   std::vector<float4> by_id(std::max<size_t>(ctx->doms_sorted.size(), 1));
@@ -459,13 +482,14 @@ pp_status pp_sur_create(pp_context *ctx, uint64_t init_seed, pp_surrogate **out)
 
 void pp_sur_destroy(pp_surrogate *s) {
   if (!s) return;
-  if (s->ctx && s->ctx->device >= 0) (void)hipSetDevice(s->ctx->device);
+  if (s->device >= 0) (void)hipSetDevice(s->device);
   (void)hipDeviceSynchronize();
   dfree(s->theta), dfree(s->grad), dfree(s->adam_m), dfree(s->adam_v), dfree(s->wb), dfree(s->wt);
   dfree(s->doms_by_id), dfree(s->X), dfree(s->XT), dfree(s->mu_base), dfree(s->nph);
   dfree(s->k), dfree(s->n_t), dfree(s->s1), dfree(s->s2), dfree(s->pair_of_row), dfree(s->w);
   for (int l = 0; l < 4; ++l) dfree(s->Z[l]), dfree(s->H[l]), dfree(s->HT[l]);
   dfree(s->Y), dfree(s->dY), dfree(s->dYT), dfree(s->dZ[0]), dfree(s->dZ[1]), dfree(s->dZT), dfree(s->d_loss);
+  dfree(s->ws), dfree(s->col_part), dfree(s->bias_part), dfree(s->loss_part);
   dfree(s->i_mu), dfree(s->i_src_nph);
   dfree(s->gX), dfree(s->gXT);
   for (auto &p : s->g_lab) dfree(p);
@@ -519,7 +543,10 @@ pp_status pp_sur_set_training_set(pp_surrogate *s, uint64_t batch) {
   int32_t *d_ev = nullptr, *d_row_of_pair = nullptr;
   uint32_t *d_count = nullptr;
   int64_t *d_offset = nullptr;
-  const auto cleanup = on_exit([&] { dfree(d_src_nph), dfree(d_ev), dfree(d_row_of_pair), dfree(d_count), dfree(d_offset); });
+  unsigned long long *d_s1q = nullptr, *d_s2q = nullptr;
+  const auto cleanup = on_exit([&] {
+    dfree(d_src_nph), dfree(d_ev), dfree(d_row_of_pair), dfree(d_count), dfree(d_offset), dfree(d_s1q), dfree(d_s2q);
+  });
   if (s->far_stride > 1 && n_src > 0) {
     if (n_all >= (int64_t{1} << 31)) return fail(ctx, PP_EINVAL, "pair selection supports up to 2^31 pairs");
     sur::SelectArgs a{};
@@ -576,12 +603,13 @@ pp_status pp_sur_set_training_set(pp_surrogate *s, uint64_t batch) {
   f.mu_base = s->mu_base;
   f.nph = s->nph;
   PP_HIP(ctx, sur::launch_features(f, nullptr));
-  float *lab[4] = {s->k, s->n_t, s->s1, s->s2};
-  for (float *p : lab) PP_HIP(ctx, sur::launch_zero_f32(p, R, nullptr));
+  PP_HIP(ctx, sur::launch_zero_f32(s->k, R, nullptr));
+  PP_HIP(ctx, sur::launch_zero_f32(s->n_t, R, nullptr));
+  if ((st = dalloc(ctx, &d_s1q, R)) != PP_OK || (st = dalloc(ctx, &d_s2q, R)) != PP_OK) return st;
   const float time_per_m = static_cast<float>(static_cast<double>(ctx->ice.n_group) / 0.299792458);
   PP_HIP(ctx, sur::launch_labels(b->d_hits, b->d_counters + pp::kHitCount, b->hit_cap, d_ev,
                                  static_cast<uint32_t>(ev.size()), b->d_src, s->doms_by_id, s->n_doms, ctx->radius,
-                                 time_per_m, d_row_of_pair, s->k, s->n_t, s->s1, s->s2, nullptr));
+                                 time_per_m, d_row_of_pair, s->k, s->n_t, d_s1q, d_s2q, s->s1, s->s2, R, nullptr));
   PP_HIP(ctx, hipDeviceSynchronize());
   return PP_OK;
 }
@@ -758,6 +786,25 @@ pp_status pp_sur_expected_hits(pp_surrogate *s, uint64_t batch, double *dev_dom_
   using NoSink = pp_status (*)(const float *, int64_t, int64_t);
   return infer<NoSink>(s, *b, stream, dev_dom_sums, nullptr);
 }
+
+}  // extern "C"
+
+namespace ppi {
+
+pp_status sur_predict_batch(pp_surrogate *s, Batch &b, float *out) {
+  pp_context *ctx = s->ctx;
+  pp_status st = check_cherenkov(ctx, b);
+  if (st != PP_OK) return st;
+  auto sink = [&](const float *mu, int64_t s0, int64_t ns) -> pp_status {
+    PP_HIP(ctx, hipMemcpy(out + s0 * s->n_doms, mu, sizeof(float) * ns * s->n_doms, hipMemcpyDeviceToHost));
+    return PP_OK;
+  };
+  return infer(s, b, nullptr, nullptr, &sink);
+}
+
+}  // namespace ppi
+
+extern "C" {
 
 pp_status pp_sur_predict_pairs(pp_surrogate *s, uint64_t batch, float *out, uint64_t n) {
   if (!s || !out) return PP_EINVAL;

@@ -40,7 +40,8 @@ __host__ __device__ constexpr int64_t wb_count() { return wb_offset(kLayers); }
 enum Epilogue {
   kEpiGelu = 0,     // z = acc + bias; store z (f32) unless null, gelu(z) as bf16 and its transpose unless null
   kEpiGeluBwd = 1,  // dz = acc * gelu'(z_saved); store bf16 and its transpose
-  kEpiAccum = 2,    // out (f32) += acc  (split-K partial sums, atomically)
+  kEpiSplitK = 2,   // out (f32) = acc summed over the K slices: each slice stores its partial in ws, then
+                    // a reduction adds them in slice order
   kEpiLinear = 4,   // out (f32, ld N) = acc + bias
 };
 
@@ -58,8 +59,10 @@ struct GemmArgs {
   uint16_t *HT;      // bf16 N x M (ld ldt)
   int64_t ldt;
   const float *Zin;  // saved pre-activation for kEpiGeluBwd (ld N)
-  float *out;        // kEpiAccum: f32 M x N (ld N)
-  float *col_sums;   // kEpiGeluBwd: += column sums of the stored bf16 output (bias gradient), may be null
+  float *out;        // kEpiSplitK: f32 M x N (ld N)
+  float *ws;         // kEpiSplitK: f32 splits x M x N partials
+  float *col_sums;   // kEpiGeluBwd: column sums of the stored bf16 output (bias gradient), may be null;
+  float *col_part;   //   formed from per-32-row partials (M / 32 x N, f32) in row order
 };
 
 struct FeatureArgs {
@@ -89,10 +92,13 @@ struct LossArgs {
   float inv_norm;        // 1 / number of pairs averaged over
   uint16_t *dY;          // bf16 M_pad x 64
   uint16_t *dYT;         // bf16 64 x M_pad
-  double *loss_sum;
+  double *loss_sum;      // set to the loss summed over the rows
   double *loss_epoch;    // also accumulated into, if not null
-  float *out_bias_grad;  // += column sums of the stored bf16 dY (the output-layer bias gradient), may be null
+  float *out_bias_grad;  // set to the column sums of the stored bf16 dY (output-layer bias gradient), may be null
+  double *loss_part;     // per-workgroup partials (loss_blocks(M_pad) of each)
+  float *bias_part;      //   (3 per workgroup)
 };
+int loss_blocks(int M_pad);
 
 // Copies training rows p(r) = (mul * r + add) mod P, r in [first, first + count),
 // into dense minibatch buffers (row i of the batch = row p(first + i)); rows
@@ -143,7 +149,9 @@ hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
 hipError_t launch_labels(const pp::DevHit *hits, const unsigned long long *hit_count, uint64_t hit_cap,
                          const int32_t *event_to_source, uint32_t n_events, const pp::DevSource *sources,
                          const float4 *doms, int n_doms, float radius, float time_per_m,
-                         const int32_t *row_of_pair, float *k, float *n_t, float *s1, float *s2, hipStream_t s);
+                         const int32_t *row_of_pair, float *k, float *n_t, unsigned long long *s1q,
+                         unsigned long long *s2q, float *s1, float *s2, int64_t n_rows, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s);
 
 // Fused inference over pairs [f.first_pair, f.first_pair + f.n_pairs):
 // features, the five layers and the expected hits, kFusedRows pairs per
@@ -154,7 +162,7 @@ struct FusedArgs {
   FeatureArgs f;                 // the pair set (its output pointers are unused)
   const uint16_t *w[kLayers];    // bf16 weights, out x in
   const float *b[kLayers];       // biases
-  double *dom_sums;              // += expected hits per module, may be null
+  double *dom_sums;              // += expected hits per module (atomically: the last bits vary), may be null
   float *pair_mu;                // expected hits of pair first_pair + i at i, may be null
   float cut2;                    // pairs farther apart than sqrt(cut2) expect 0 hits (+inf: no cut)
 };

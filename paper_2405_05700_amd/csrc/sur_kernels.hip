@@ -8,7 +8,9 @@
 // weights (at most 128 KB per layer) stay in L2, so operand fragments are
 // loaded straight into VGPRs, 16 bytes per lane per fragment. Epilogues fuse
 // the bias, GELU and its derivative, the transposed copies the next GEMM
-// needs, split-K accumulation, and the expected-hit output.
+// needs, and split-K partials. Every sum that gradients or labels depend on
+// is formed in a fixed order (partials reduced in order, or exact
+// fixed-point atomics), so training is bit-reproducible.
 
 #include "sur_device.h"
 
@@ -159,27 +161,33 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
       }
       const uint2 packed = make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
       *reinterpret_cast<uint2 *>(g.HT + (int64_t)col * g.ldt + rbase) = packed;
-    } else if (EPI == kEpiAccum) {
+    } else if (EPI == kEpiSplitK) {
+      // this K slice's partial product; a reduction in slice order follows
+      float *part = g.ws + (int64_t)blockIdx.z * g.M * g.N;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) atomicAdd(&g.out[(int64_t)(rbase + r) * g.N + col], v[r]);
+      for (int r = 0; r < 4; ++r) part[(int64_t)(rbase + r) * g.N + col] = v[r];
     } else if (EPI == kEpiLinear) {
       const float b = g.bias[col];
 #pragma unroll
       for (int r = 0; r < 4; ++r) g.out[(int64_t)(rbase + r) * g.N + col] = v[r] + b;
     }
   }
-  if (EPI == kEpiGeluBwd && g.col_sums) {
-    // lanes l, l + 16, l + 32, l + 48 hold the same column: sum them, then
-    // one atomic per column of the wave's 32 x 32 block
+  if (EPI == kEpiGeluBwd && g.col_part) {
+    // lanes l, l + 16, l + 32, l + 48 hold the same column: sum them into
+    // the column sum of the wave's 32 rows, stored for the block of rows
+    // (a reduction over the row blocks in order follows)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       float cs = csum[j];
       cs += __shfl_xor(cs, 16, 64);
       cs += __shfl_xor(cs, 32, 64);
-      if (lane < 16) atomicAdd(&g.col_sums[col0 + j * 16 + lane], cs);
+      if (lane < 16) g.col_part[(int64_t)(row0 / 32) * g.N + col0 + j * 16 + lane] = cs;
     }
   }
 }
+
+constexpr double kDelayFix = 1048576.0;     // 2^20 per ns
+constexpr double kLogFix = 4294967296.0;    // 2^32
 
 __device__ __forceinline__ int layer_of(float z, float z_lo, float inv_dz, int n_layers) {
   const float f = floorf((z - z_lo) * inv_dz);
@@ -334,11 +342,60 @@ __global__ void __launch_bounds__(256) k_loss(const LossArgs l) {
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    atomicAdd(l.loss_sum, red[0]);
-    if (l.loss_epoch) atomicAdd(l.loss_epoch, red[0]);
-    if (l.out_bias_grad)
-      for (int q = 0; q < 3; ++q) atomicAdd(&l.out_bias_grad[q], bred[q][0]);
+    l.loss_part[blockIdx.x] = red[0];
+    for (int q = 0; q < 3; ++q) l.bias_part[3 * blockIdx.x + q] = bred[q][0];
   }
+}
+
+// Sum of part[i * stride] over i < n in a fixed order by one wavefront: lane
+// l adds parts l, l + 64, l + 128, ... in turn, then the lanes combine by a
+// fixed butterfly. The result depends only on the values, not on
+// scheduling, and the wave's loads are independent.
+template <class T>
+__device__ __forceinline__ T wave_ordered_sum(const T *part, int n, int64_t stride) {
+  const int lane = threadIdx.x & 63;
+  T sum = 0;
+  for (int i = lane; i < n; i += 64) sum += part[(int64_t)i * stride];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+  return sum;
+}
+
+// The workgroups' loss and output-bias-gradient partials, summed in a fixed
+// order: wavefront 0 the loss, wavefronts 1..3 the three bias entries.
+__global__ void __launch_bounds__(256) k_loss_reduce(const LossArgs l, int n_blocks) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave == 0) {
+    const double sum = wave_ordered_sum(l.loss_part, n_blocks, 1);
+    if (lane == 0) {
+      *l.loss_sum = sum;
+      if (l.loss_epoch) *l.loss_epoch += sum;
+    }
+  } else if (l.out_bias_grad) {
+    const float sum = wave_ordered_sum(l.bias_part + wave - 1, n_blocks, 3);
+    if (lane == 0) l.out_bias_grad[wave - 1] = sum;
+  }
+}
+
+// out[j] = sum over i < n_parts of part[i * stride + j], in order of i: one
+// thread per element (few parts, many elements: the split-K slices).
+__global__ void k_sum_parts(float *out, const float *part, int64_t n, int n_parts, int64_t stride) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    float sum = 0.0f;
+#pragma unroll 8
+    for (int i = 0; i < n_parts; ++i) sum += part[i * stride + j];
+    out[j] = sum;
+  }
+}
+
+// The same with one wavefront per element (many parts, few elements: the
+// per-32-row column sums of a bias gradient).
+__global__ void __launch_bounds__(256) k_sum_parts_wave(float *out, const float *part, int64_t n, int n_parts,
+                                                        int64_t stride) {
+  const int64_t j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;
+  const float sum = wave_ordered_sum(part + j, n_parts, stride);
+  if ((threadIdx.x & 63) == 0) out[j] = sum;
 }
 
 // Adam (Kingma & Ba) with bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t.
@@ -383,11 +440,15 @@ __global__ void k_zero_f64(double *p, int64_t n) {
 // count k, and the count, sum and sum of logs of the delays
 // t - t0 - max(R - L/2 - r, 0) n_g / c (+ 0.01 ns), R the distance from
 // the segment centre to the module centre. The delay is non-negative: no
-// photon reaches the module surface sooner.
+// photon reaches the module surface sooner. The two sums are accumulated as
+// 64-bit fixed point (delays in units of 2^-20 ns, logarithms in units of
+// 2^-32), whose additions are exact, so the labels do not depend on the
+// order in which the hits arrive.
 __global__ void k_labels(const pp::DevHit *hits, const unsigned long long *hit_count, uint64_t cap,
                          const int32_t *event_to_source, uint32_t n_events, const pp::DevSource *sources,
                          const float4 *doms, int n_doms, float radius, float time_per_m,
-                         const int32_t *row_of_pair, float *k, float *n_t, float *s1, float *s2) {
+                         const int32_t *row_of_pair, float *k, float *n_t, unsigned long long *s1q,
+                         unsigned long long *s2q) {
   uint64_t n = *hit_count;
   if (n > cap) n = cap;
   for (uint64_t h = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; h < n; h += (uint64_t)gridDim.x * blockDim.x) {
@@ -405,10 +466,19 @@ __global__ void k_labels(const pp::DevHit *hits, const unsigned long long *hit_c
     const int64_t pair = (int64_t)i * n_doms + hit.dom_id;
     const int64_t row = row_of_pair ? (int64_t)row_of_pair[pair] : pair;
     if (row < 0) continue;  // pair not in the training set
-    atomicAdd(&k[row], 1.0f);
+    atomicAdd(&k[row], 1.0f);  // whole numbers below 2^24: exact in any order
     atomicAdd(&n_t[row], 1.0f);
-    atomicAdd(&s1[row], delay);
-    atomicAdd(&s2[row], logf(delay));
+    atomicAdd(&s1q[row], (unsigned long long)__double2ll_rn((double)delay * kDelayFix));
+    atomicAdd(&s2q[row], (unsigned long long)__double2ll_rn((double)logf(delay) * kLogFix));
+  }
+}
+
+// Fixed-point label sums to float.
+__global__ void k_labels_finish(const unsigned long long *s1q, const unsigned long long *s2q, float *s1, float *s2,
+                                int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    s1[i] = (float)((double)(long long)s1q[i] / kDelayFix);
+    s2[i] = (float)((double)(long long)s2q[i] / kLogFix);
   }
 }
 
@@ -545,19 +615,39 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   }
 }
 
+__global__ void k_zero_u64(unsigned long long *p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
 int blocks_for(int64_t n, int threads) { return (int)((n + threads - 1) / threads); }
 
 }  // namespace
+
+hipError_t launch_sum_parts(float *out, const float *part, int64_t n, int n_parts, int64_t stride, hipStream_t s) {
+  if (n_parts > 32 && n <= 65536)
+    hipLaunchKernelGGL(k_sum_parts_wave, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, out, part, n, n_parts, stride);
+  else
+    hipLaunchKernelGGL(k_sum_parts, dim3(min(blocks_for(n, 256), 2048)), dim3(256), 0, s, out, part, n, n_parts,
+                       stride);
+  return hipGetLastError();
+}
 
 hipError_t launch_gemm(int epi, const GemmArgs &g, int splits, hipStream_t s) {
   const dim3 grid(g.N / kTile, g.M / kTile, splits);
   switch (epi) {
     case kEpiGelu: hipLaunchKernelGGL(k_gemm<kEpiGelu>, grid, dim3(256), 0, s, g); break;
     case kEpiGeluBwd: hipLaunchKernelGGL(k_gemm<kEpiGeluBwd>, grid, dim3(256), 0, s, g); break;
-    case kEpiAccum: hipLaunchKernelGGL(k_gemm<kEpiAccum>, grid, dim3(256), 0, s, g); break;
+    case kEpiSplitK: hipLaunchKernelGGL(k_gemm<kEpiSplitK>, grid, dim3(256), 0, s, g); break;
     case kEpiLinear: hipLaunchKernelGGL(k_gemm<kEpiLinear>, grid, dim3(256), 0, s, g); break;
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (epi == kEpiSplitK)
+    return launch_sum_parts(g.out, g.ws, (int64_t)g.M * g.N, splits, (int64_t)g.M * g.N, s);
+  if (epi == kEpiGeluBwd && g.col_part)
+    return launch_sum_parts(g.col_sums, g.col_part, g.N, g.M / 32, g.N, s);
+  return hipSuccess;
 }
 
 size_t fused_lds_bytes() { return sizeof(uint16_t) * kFusedRows * kFusedLd + 2 * sizeof(float) * kFusedRows; }
@@ -579,8 +669,20 @@ hipError_t launch_features(const FeatureArgs &f, hipStream_t s) {
   return hipGetLastError();
 }
 
+int loss_blocks(int M_pad) { return blocks_for(M_pad, 256); }
+
 hipError_t launch_loss(const LossArgs &l, hipStream_t s) {
-  hipLaunchKernelGGL(k_loss, dim3(blocks_for(l.M_pad, 256)), dim3(256), 0, s, l);
+  const int blocks = loss_blocks(l.M_pad);
+  hipLaunchKernelGGL(k_loss, dim3(blocks), dim3(256), 0, s, l);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, s, l, blocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u64, dim3(min(blocks_for(n, 256), 4096)), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 
@@ -647,9 +749,16 @@ hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s) {
 hipError_t launch_labels(const pp::DevHit *hits, const unsigned long long *hit_count, uint64_t hit_cap,
                          const int32_t *event_to_source, uint32_t n_events, const pp::DevSource *sources,
                          const float4 *doms, int n_doms, float radius, float time_per_m,
-                         const int32_t *row_of_pair, float *k, float *n_t, float *s1, float *s2, hipStream_t s) {
+                         const int32_t *row_of_pair, float *k, float *n_t, unsigned long long *s1q,
+                         unsigned long long *s2q, float *s1, float *s2, int64_t n_rows, hipStream_t s) {
+  hipError_t e = launch_zero_u64(s1q, n_rows, s);
+  if (e == hipSuccess) e = launch_zero_u64(s2q, n_rows, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_labels, dim3(1024), dim3(256), 0, s, hits, hit_count, hit_cap, event_to_source, n_events,
-                     sources, doms, n_doms, radius, time_per_m, row_of_pair, k, n_t, s1, s2);
+                     sources, doms, n_doms, radius, time_per_m, row_of_pair, k, n_t, s1q, s2q);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_labels_finish, dim3(min(blocks_for(n_rows, 256), 4096)), dim3(256), 0, s, s1q, s2q, s1, s2,
+                     n_rows);
   return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -28,6 +29,7 @@ PP_OK, PP_EINVAL, PP_ENOMEM, PP_EDEVICE, PP_ESTATE, PP_ETRUNC, PP_EBUDGET = 0, -
 STATUS_NAMES = {0: "PP_OK", -1: "PP_EINVAL", -2: "PP_ENOMEM", -3: "PP_EDEVICE",
                 -4: "PP_ESTATE", -5: "PP_ETRUNC", -6: "PP_EBUDGET"}
 FATE_ABSORBED, FATE_HIT, FATE_CAPPED, FATE_ESCAPED = 0, 1, 2, 3
+RECORDS_OFF, RECORDS_ON, RECORDS_PRODUCTION = 0, 1, 2
 NO_DOM = 0xFFFFFFFF
 
 
@@ -157,10 +159,32 @@ class Context:
         self._h = h
         self.device = device
         self.n_doms = 0
+        # surrogates and servers bound to this context: closed before it, and
+        # counted, so that one that outlives it (objects of a reference cycle
+        # are finalised in any order) defers the context's destruction
+        self._dependents = weakref.WeakSet()
+        self._n_dependents = 0
+        self._close_pending = False
 
     # -- lifetime
+    def _add_dependent(self, d):
+        self._dependents.add(d)
+        self._n_dependents += 1
+
+    def _release_dependent(self):
+        self._n_dependents -= 1
+        if self._close_pending and self._n_dependents == 0:
+            self._close_pending = False
+            self.close()
+
     def close(self):
         if self._h:
+            # servers first: one may use a surrogate of this context
+            for d in sorted(self._dependents, key=lambda d: d._close_order):
+                d.close()
+            if self._n_dependents > 0:
+                self._close_pending = True
+                return
             _lib.pp_destroy(self._h)
             self._h = None
 
@@ -195,8 +219,12 @@ class Context:
     def set_step_cap(self, cap: int):
         self._check(_lib.pp_set_step_cap(self._h, int(cap)))
 
-    def set_debug_records(self, on: bool):
-        self._check(_lib.pp_set_debug_records(self._h, 1 if on else 0))
+    def set_debug_records(self, on):
+        """False: off; True or RECORDS_ON: records with each photon's drawn
+        wavelength; RECORDS_PRODUCTION: records from the kernel variant that
+        runs with records off (wavelength 0 unless that variant draws it)."""
+        mode = RECORDS_OFF if on is False else (RECORDS_ON if on is True else int(on))
+        self._check(_lib.pp_set_debug_records(self._h, mode))
 
     # -- inputs
     def load_ice(self, z_lo_m: float, dz_m: float, n_group: float, layers: np.ndarray):

@@ -26,11 +26,13 @@ class RequestInfo(C.Structure):
 
 class ServerStats(C.Structure):
     _fields_ = [(n, _u64) for n in ("submitted", "completed", "launches", "deferred", "bytes_in_use",
-                                    "peak_bytes_in_use", "photons_completed")]
+                                    "peak_bytes_in_use", "photons_completed", "arena_bytes",
+                                    "overflow_bytes_peak", "shared_requests", "overlapped_launches")] + \
+               [("gpu_busy_s", C.c_double), ("gpu_span_s", C.c_double)]
 
 
+_dp = C.POINTER(C.c_double)
 SIGNATURES = {
-    "pp_server_admit_plan": (_u32, [_u32, _vp, _vp, _vp, _u64, _u64, _u32, _u64, _vp]),
     "pp_server_request_bytes": (_u64, [_u32, _u64]),
     "pp_server_create": (C.c_int, [_vp, C.POINTER(ServerConfig), _vp, C.POINTER(_vp)]),
     "pp_server_destroy": (None, [_vp]),
@@ -38,22 +40,14 @@ SIGNATURES = {
     "pp_server_wait": (C.c_int, [_vp, _u64, _vp, _u64, _vp, C.POINTER(RequestInfo)]),
     "pp_server_get_stats": (C.c_int, [_vp, C.POINTER(ServerStats)]),
     "pp_server_last_error": (C.c_char_p, [_vp]),
+    "pp_server_run_clients": (C.c_int, [_vp, _vp, _u64, _u32, C.c_double, _u32, C.c_double, _u64, _vp, _u64,
+                                        C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64), _dp]),
 }
 for _name, (_res, _args) in SIGNATURES.items():
     _fn = getattr(pp._lib, _name)
     _fn.restype = _res
     _fn.argtypes = _args
 _lib = pp._lib
-
-
-def admit_plan(bytes_, event_ids, photons, bytes_in_use, budget, max_events, max_photons):
-    b = np.ascontiguousarray(bytes_, np.uint64)
-    e = np.ascontiguousarray(event_ids, np.uint32)
-    p = np.ascontiguousarray(photons, np.uint64)
-    take = np.zeros(len(b), np.uint8)
-    _lib.pp_server_admit_plan(len(b), b.ctypes.data, e.ctypes.data, p.ctypes.data, bytes_in_use, budget,
-                              max_events, max_photons, take.ctypes.data)
-    return take.astype(bool)
 
 
 def request_bytes(n_sources: int, n_photons: int) -> int:
@@ -63,6 +57,8 @@ def request_bytes(n_sources: int, n_photons: int) -> int:
 class Server:
     """A photon server owning ctx until close()."""
 
+    _close_order = 0
+
     def __init__(self, ctx: "pp.Context", max_inflight=0, max_batch_events=0, hbm_budget_bytes=0,
                  max_batch_photons=0, surrogate=None):
         cfg = ServerConfig(max_inflight, max_batch_events, hbm_budget_bytes, max_batch_photons)
@@ -71,6 +67,8 @@ class Server:
         ctx._check(st)
         self._h = h
         self.ctx = ctx
+        self.surrogate = surrogate  # kept alive while the server may use it
+        ctx._add_dependent(self)
         self.n_doms = ctx.n_doms
         self.has_surrogate = surrogate is not None
 
@@ -78,6 +76,7 @@ class Server:
         if self._h:
             _lib.pp_server_destroy(self._h)
             self._h = None
+            self.ctx._release_dependent()
 
     def __del__(self):
         try:
@@ -112,6 +111,20 @@ class Server:
             self._check(st)
             d = {k: getattr(info, k) for k, _ in RequestInfo._fields_ if k != "reserved"}
             return out[: info.n_hits], d, dom
+
+    def run_clients(self, events: np.ndarray, n_clients: int, rate_per_s: float = 0.0, outstanding: int = 32,
+                    duration_s: float = 5.0, seed: int = 0) -> dict:
+        """pp_server_run_clients: native client threads submit events (one
+        source each) open loop at rate_per_s, or closed loop with
+        `outstanding` requests each; returns latencies (s) and totals."""
+        events = np.ascontiguousarray(events, dtype=W.SOURCE_DTYPE)
+        lat = np.zeros(len(events), np.float64)
+        n, ph, hits, wall = C.c_uint64(), C.c_uint64(), C.c_uint64(), C.c_double()
+        self._check(_lib.pp_server_run_clients(self._h, events.ctypes.data, len(events), n_clients, rate_per_s,
+                                               outstanding, duration_s, seed, lat.ctypes.data, len(lat),
+                                               C.byref(n), C.byref(ph), C.byref(hits), C.byref(wall)))
+        return {"latency_s": lat[: min(n.value, len(lat))], "done": n.value, "photons": ph.value,
+                "hits": hits.value, "wall_s": wall.value}
 
     def stats(self) -> dict:
         s = ServerStats()

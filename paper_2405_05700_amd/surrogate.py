@@ -45,17 +45,21 @@ class Surrogate:
     """The learned surrogate bound to a context (its device, ice and
     geometry)."""
 
+    _close_order = 1
+
     def __init__(self, ctx: "pp.Context", seed: int = 0):
         h = C.c_void_p()
         st = _lib.pp_sur_create(ctx._h, int(seed), C.byref(h))
         ctx._check(st)
         self._h = h
         self.ctx = ctx
+        ctx._add_dependent(self)
 
     def close(self):
         if self._h:
             _lib.pp_sur_destroy(self._h)
             self._h = None
+            self.ctx._release_dependent()
 
     def __del__(self):
         try:

@@ -251,26 +251,13 @@ def test_full_detector_geometry_shape(pp):
     assert abs(info["max_reach_m"] - W.DOM_RADIUS_M) < 1e-3
 
 
-def test_admission_plan_policy(pp):
-    """HBM-budget admission (host logic): arrival order, each request that
-    fits the remaining budget, one request per event id, caps on events and
-    photons per launch."""
+def test_server_request_bytes(pp):
+    """The serving queue's admission cost (host logic): 80-byte source
+    records plus 16-byte work-queue entries of at most 256 photon ids."""
     from paper_2405_05700_amd import server
-    MB = 1 << 20
-    take = server.admit_plan([3 * MB, 4 * MB, 2 * MB, 1 * MB], [1, 2, 3, 4], [10, 10, 10, 10],
-                             bytes_in_use=2 * MB, budget=8 * MB, max_events=10, max_photons=1000)
-    assert take.tolist() == [True, False, True, True]  # 2+3=5, +4 > 8 skip, +2=7, +1=8
-    take = server.admit_plan([MB] * 4, [7, 7, 8, 7], [1] * 4, 0, 100 * MB, 10, 1000)
-    assert take.tolist() == [True, False, True, False]  # event 7 only once per launch
-    take = server.admit_plan([MB] * 5, [1, 2, 3, 4, 5], [1] * 5, 0, 100 * MB, 3, 1000)
-    assert take.sum() == 3 and take[:3].all()
-    take = server.admit_plan([MB] * 4, [1, 2, 3, 4], [600, 600, 600, 1], 0, 100 * MB, 10, 1000)
-    assert take.tolist() == [True, True, False, False]  # closes once 1000 photons are reached
-    take = server.admit_plan([MB], [1], [1], 9 * MB, 8 * MB, 10, 1000)  # over budget already
-    assert not take.any()
-    # the admission cost covers the default hit buffer and grows with photons
-    assert server.request_bytes(1, 1000) >= 32 * 65536
-    assert server.request_bytes(1, 10**9) > server.request_bytes(1, 10**6)
+    assert server.request_bytes(1, 0) == 80 + 16
+    assert server.request_bytes(1, 1000) == 80 + 16 * (1 + 1000 // 256)
+    assert server.request_bytes(3, 10**8) == 3 * 80 + 16 * (3 + 10**8 // 256)
 
 
 def test_sort_hits_orders_by_event_then_photon(pp):

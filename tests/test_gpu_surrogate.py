@@ -2,9 +2,25 @@
 
 Features, labels, forward outputs and gradients of the BF16/FP32-accumulate
 network are compared with oracle/mlp_oracle.py fed the same bf16-rounded
-features and weights. Tolerances follow from bf16 rounding (2^-9 relative
-per stored activation): a few percent on gradient tensors, checked as
-relative Frobenius error and cosine similarity.
+features and weights, so the only differences are the kernel's own
+roundings: each stored activation and each backward operand is rounded to
+bf16 (relative error at most u = 2^-9 ~ 1.95e-3) and every sum is FP32.
+
+Tolerances, from u:
+* forward: the predicted mean is exp of the output, and the output's error
+  is a sum of many independent roundings of both signs, so the typical
+  (median) relative error of the mean stays below one unit u: FWD_MEDIAN =
+  2e-3. The tail, where one output's inputs cancel, gets ten units: FWD_P99
+  = 2e-2.
+* loss: a sum of 4096 per-row terms whose rounding errors mostly cancel:
+  LOSS_REL = 5e-3 (2.5 u).
+* gradients: each element of a gradient tensor sums products of two
+  rounded operands (2 u each) over the rows; with no cancellation that is
+  at most 2 u relative, and the cancellation between rows of opposite sign
+  measured on these sets stays below a factor 5, so the relative Frobenius
+  error per tensor is held to GRAD_REL = 2e-2 (10 u) and its cosine to the
+  oracle's gradient to GRAD_COS = 0.9995 (an angle below 1.8 degrees).
+A 3% error in one tensor, or a missing term, fails these.
 """
 import sys
 
@@ -14,6 +30,10 @@ import pytest
 from paper_2405_05700_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+FWD_MEDIAN, FWD_P99 = 2e-3, 2e-2
+LOSS_REL = 5e-3
+GRAD_REL, GRAD_COS = 2e-2, 0.9995
 
 
 def say(*a):
@@ -134,7 +154,7 @@ def test_forward_and_gradients_match_oracle(mods, small_set):
     mu_ref = nph * rows["mu_base"] * np.exp(Y[:, 0])
     rel = np.abs(mu_gpu - mu_ref) / mu_ref
     say("forward: median rel", np.median(rel), "p99", np.quantile(rel, 0.99))
-    assert np.median(rel) < 0.02 and np.quantile(rel, 0.99) < 0.1
+    assert np.median(rel) < FWD_MEDIAN and np.quantile(rel, 0.99) < FWD_P99
     # loss and gradients over 4096 rows
     first, count = 0, 4096
     loss, grad = sur.loss_grad(first, count)
@@ -145,7 +165,7 @@ def test_forward_and_gradients_match_oracle(mods, small_set):
                                        rows["n_t"][sl], rows["s1"][sl], rows["s2"][sl])
     g_ref = flatten(M, M.backward(params, cache, dY)).astype(np.float64)
     say("loss gpu", loss, "oracle", loss_ref)
-    assert abs(loss - loss_ref) <= 0.02 * abs(loss_ref) + 1e-6
+    assert abs(loss - loss_ref) <= LOSS_REL * abs(loss_ref) + 1e-6
     o = 0
     for li, (n_out, n_in) in enumerate(M.LAYER_SHAPES):
         for part, size in (("W", n_out * n_in), ("b", n_out)):
@@ -154,7 +174,7 @@ def test_forward_and_gradients_match_oracle(mods, small_set):
             err = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
             cos = a @ r / max(np.linalg.norm(a) * np.linalg.norm(r), 1e-30)
             say(f"grad layer {li} {part}: rel {err:.4f} cos {cos:.6f}")
-            assert err < 0.06 and cos > 0.998, (li, part, err, cos)
+            assert err < GRAD_REL and cos > GRAD_COS, (li, part, err, cos)
 
 
 def test_fused_expected_hits_equal_pair_sums(mods):
@@ -243,7 +263,7 @@ def test_far_pair_sampling_follows_rule_and_oracle(mods):
                                        weight=wt[:count].astype(float))
     g_ref = flatten(M, M.backward(params, cache, dY)).astype(np.float64)
     say("weighted loss gpu", loss, "oracle", loss_ref)
-    assert abs(loss - loss_ref) <= 0.02 * abs(loss_ref) + 1e-6
+    assert abs(loss - loss_ref) <= LOSS_REL * abs(loss_ref) + 1e-6
     o = 0
     for li, (n_out, n_in) in enumerate(M.LAYER_SHAPES):
         for part, size in (("W", n_out * n_in), ("b", n_out)):
@@ -251,7 +271,8 @@ def test_far_pair_sampling_follows_rule_and_oracle(mods):
             o += size
             err = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
             cos = a @ r / max(np.linalg.norm(a) * np.linalg.norm(r), 1e-30)
-            assert err < 0.06 and cos > 0.998, (li, part, err, cos)
+            say(f"weighted grad layer {li} {part}: rel {err:.4f} cos {cos:.6f}")
+            assert err < GRAD_REL and cos > GRAD_COS, (li, part, err, cos)
     # a shuffled epoch with lr = 0 visits every weighted row once
     l_all, _ = sur.loss_grad(0, P)
     losses = sur.train(epochs=2, batch_size=512, lr=0.0)
@@ -399,3 +420,47 @@ def test_training_beats_the_untrained_baseline(mods):
     e_base = np.abs(exp_base[bright] - counts[bright]) / counts[bright]
     say("modules", int(bright.sum()), "median rel error trained", np.median(e_tr), "baseline", np.median(e_base))
     assert bright.sum() >= 5 and np.median(e_tr) < np.median(e_base)
+
+
+def test_labels_training_and_sums_are_bit_reproducible(mods):
+    """The same recipe gives the same network, bit for bit: labels built
+    from two propagations whose hits arrive in different orders (different
+    launch shapes) are identical, two training runs from the same start on
+    them end in identical parameters and epoch losses, and so in identical
+    per-pair predictions. Every sum on the way is formed in a fixed order or
+    in exact fixed point."""
+    pp, surrogate, M = mods
+    det = W.full_detector(n_sources=1, photons_per_source=1)
+    w = det.with_sources(W.near_module_segments(det, 24, 300_000, seed=5))
+    runs = []
+    for launch in ({}, {"block_size": 256, "chunk_size": 64, "refill_interval": 2}):
+        ctx = pp.Context(0, seed=0)
+        ctx.load_workload(w)
+        ctx.set_launch_config(**launch)
+        b = ctx.submit(w.sources)
+        ctx.propagate(b)
+        sur = surrogate.Surrogate(ctx, seed=3)
+        sur.set_training_set(b)
+        runs.append((ctx, b, sur))
+    (ctx1, b1, s1), (ctx2, b2, s2) = runs
+    P = s1.training_size()
+    assert P == s2.training_size() == len(w.sources) * len(w.doms)
+    r1, r2 = s1.training_rows(0, P), s2.training_rows(0, P)
+    assert r1["k"].sum() > 500
+    for key in r1:
+        assert np.array_equal(r1[key].view(np.uint32), r2[key].view(np.uint32)), key
+    l1 = s1.train(epochs=2, batch_size=4096, lr=1e-3)
+    l2 = s2.train(epochs=2, batch_size=4096, lr=1e-3)
+    say("epoch losses", l1, l2)
+    assert np.array_equal(l1.view(np.uint32), l2.view(np.uint32))
+    p1, p2 = s1.get_params(), s2.get_params()
+    assert np.array_equal(p1.view(np.uint32), p2.view(np.uint32))
+    # per-pair predictions of the two networks are identical; the per-module
+    # sums add pairs with atomics, so only their last bits may differ
+    assert np.array_equal(s1.predict_pairs(b1, len(w.sources)), s2.predict_pairs(b2, len(w.sources)))
+    e1 = s1.expected_hits(b1).cpu().numpy()
+    e3 = s2.expected_hits(b2).cpu().numpy()
+    assert np.allclose(e1, e3, rtol=1e-12, atol=0)
+    for ctx, b, sur in runs:
+        sur.close()
+        ctx.close()
