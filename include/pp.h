@@ -370,6 +370,34 @@ pp_status pp_graph_capture(pp_context *ctx, uint64_t batch, void *hip_stream);
  * with the captured configuration. PP_ESTATE if no graph is held. */
 pp_status pp_graph_launch(pp_context *ctx, uint64_t batch, void *hip_stream);
 
+/* Propagation that allocates nothing, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc. It submits, propagates and counts in one call, with
+ * the same kernel and therefore the same hits as pp_submit + pp_propagate +
+ * pp_fetch_hits_device on the same sources.
+ *   sources, n_sources: light sources in host memory, as for pp_submit (same
+ *     validation); at most PP_STATIC_MAX_SOURCES of them.
+ *   dev_hits, hit_cap: caller-owned device buffer of hit_cap pp_hit records;
+ *     the hits are written there, in unspecified order.
+ *   n_total: receives the number of hits. PP_ETRUNC if it exceeds hit_cap:
+ *     then hit_cap of the hits are written (which ones is unspecified) and
+ *     the call can be repeated with a larger buffer for the same hits.
+ *   stats: if non-NULL, receives the counters of the propagation and the
+ *     launch used; kernel_ms is 0 (the call records no events).
+ * The sources, the work queue and the counters live in a fixed 16 MiB device
+ * array that the library holds on each GPU it runs on until the process
+ * ends; no hipMalloc, hipFree or other allocating routine is called. The
+ * call runs on hip_stream and synchronises it before returning. Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (from
+ * several threads or contexts) race and must be serialised by the caller.
+ * PP_ESTATE if ice or geometry is missing or debug records are on (they need
+ * per-photon memory); PP_EINVAL on bad sources, more than
+ * PP_STATIC_MAX_SOURCES sources, or a photon count whose work queue cannot
+ * fit the array even in chunks of 2^31 photon ids. */
+#define PP_STATIC_MAX_SOURCES 32768u
+pp_status pp_propagate_static(pp_context *ctx, const pp_source *sources, uint32_t n_sources, pp_hit *dev_hits,
+                              uint64_t hit_cap, uint64_t *n_total, pp_stats *stats, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -685,6 +685,12 @@ pp_status pp_create(int hip_device, uint64_t seed, pp_context **out) {
       return PP_EDEVICE;
     }
     ctx->n_cu = prop.multiProcessorCount;
+    e = static_scratch_setup(hip_device);
+    if (e != hipSuccess) {
+      g_create_error = std::string("scratch of pp_propagate_static: ") + hipGetErrorString(e);
+      delete ctx;
+      return PP_EDEVICE;
+    }
   }
   *out = ctx;
   return PP_OK;

@@ -120,6 +120,9 @@ void fill_args(const pp_context *ctx, const LaunchShape &shape, pp::PropagateArg
 void split_chunks(const std::vector<pp::DevSource> &src, uint64_t n_photons, uint32_t chunk,
                   std::vector<pp::DevChunk> *out);
 bool wants_wavelength(const pp_context *ctx);
+// Looks up the device address of pp_propagate_static's scratch array on the
+// current device (once per device).
+hipError_t static_scratch_setup(int device);
 // Expected hits of every (source, module) pair of a batch that need not be
 // registered with the context (host records b.src, device records b.d_src),
 // source-major into host memory out (b.src.size() x n_doms floats).

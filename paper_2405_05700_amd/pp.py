@@ -104,7 +104,9 @@ SIGNATURES = {
     "pp_graph_launch": (C.c_int, [_vp, _u64, _vp]),
     "pp_set_chromatic": (C.c_int, [_vp, C.POINTER(_Chromatic)]),
     "pp_set_acceptance": (C.c_int, [_vp, C.POINTER(_Acceptance)]),
+    "pp_propagate_static": (C.c_int, [_vp, _vp, _u32, _vp, _u64, C.POINTER(_u64), C.POINTER(_Stats), _vp]),
 }
+STATIC_MAX_SOURCES = 32768
 
 
 def load_library(path: str = _LIB_PATH):
@@ -365,6 +367,21 @@ class Context:
 
     def graph_launch(self, batch: int, stream=None):
         self._check(_lib.pp_graph_launch(self._h, batch, _stream_handle(stream)))
+
+    def propagate_static(self, sources: np.ndarray, dev_hits, stream=None):
+        """pp_propagate_static: propagates the sources with no device
+        allocation into dev_hits (a CUDA tensor of >= 32 bytes per hit);
+        returns (n_total, stats). n_total may exceed the buffer's capacity
+        (then only that many hits were written)."""
+        sources = np.ascontiguousarray(sources, dtype=W.SOURCE_DTYPE)
+        cap = dev_hits.numel() * dev_hits.element_size() // HIT_DTYPE.itemsize
+        tot = C.c_uint64()
+        s = _Stats()
+        self._check(_lib.pp_propagate_static(self._h, _ptr(sources) if len(sources) else None, len(sources),
+                                             C.c_void_p(dev_hits.data_ptr()) if cap else None, cap,
+                                             C.byref(tot), C.byref(s), _stream_handle(stream)),
+                    allow=(PP_OK, PP_ETRUNC))
+        return tot.value, {k: getattr(s, k) for k, _ in _Stats._fields_}
 
     def stats(self, batch: int) -> dict:
         s = _Stats()

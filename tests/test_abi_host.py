@@ -113,6 +113,33 @@ def test_call_order_and_device_errors(pp):
         pp.Context(-2)
 
 
+def test_static_propagation_argument_checks(pp):
+    """pp_propagate_static checks its arguments and the call order before it
+    touches a device: on a host-only context it reports the first problem."""
+    import ctypes as C
+    w = W.tiny_point_source(100)
+    ctx = host_ctx(pp)
+    src = np.ascontiguousarray(w.sources, dtype=W.SOURCE_DTYPE)
+    tot = C.c_uint64(123)
+    f = pp._lib.pp_propagate_static
+    assert f(None, None, 0, None, 0, C.byref(tot), None, None) == pp.PP_EINVAL
+    assert f(ctx._h, None, 0, None, 0, None, None, None) == pp.PP_EINVAL      # n_total missing
+    assert f(ctx._h, None, 1, None, 0, C.byref(tot), None, None) == pp.PP_EINVAL  # sources missing
+    assert f(ctx._h, src.ctypes.data, 1, None, 5, C.byref(tot), None, None) == pp.PP_EINVAL  # hits missing
+    assert f(ctx._h, src.ctypes.data, 1, None, 0, C.byref(tot), None, None) == pp.PP_ESTATE  # no ice yet
+    assert tot.value == 0
+    ctx.load_workload(w)
+    ctx.set_debug_records(True)
+    assert f(ctx._h, src.ctypes.data, 1, None, 0, C.byref(tot), None, None) == pp.PP_ESTATE
+    assert b"records" in pp._lib.pp_last_error(ctx._h)
+    ctx.set_debug_records(False)
+    many = np.repeat(src, pp.STATIC_MAX_SOURCES + 1)
+    assert f(ctx._h, many.ctypes.data, len(many), None, 0, C.byref(tot), None, None) == pp.PP_EINVAL
+    assert b"at most 32768" in pp._lib.pp_last_error(ctx._h)
+    assert f(ctx._h, src.ctypes.data, 1, None, 0, C.byref(tot), None, None) == pp.PP_EDEVICE
+    ctx.close()
+
+
 def test_ice_validation(pp):
     w = W.tiny_point_source(10)
     ctx = host_ctx(pp)
