@@ -73,7 +73,9 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=2,
+                    help="untimed steps first (0: none, as in the profiles, whose averages then cover only the "
+                         "timed launches)")
     ap.add_argument("--sources", type=int, default=1000)
     ap.add_argument("--photons-per-source", type=int, default=100_000)
     ap.add_argument("--block-size", type=int, default=0)
@@ -478,7 +480,8 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    n_hits = ctx.hit_count(batch)  # grows the hit buffer once if needed (not timed)
+    if args.warmup > 0:
+        ctx.hit_count(batch)  # grows the hit buffer once if needed (not timed)
     torch.cuda.synchronize()
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -493,6 +496,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
+    n_hits = ctx.hit_count(batch)  # the default buffer (photons / 64) holds this workload's hits
     kernel_ms = [a.elapsed_time(b) for a, b in ev]
     progress(f"timed {args.steps} steps: {1e3 * elapsed / args.steps:.2f} ms per step")
     st = ctx.stats(batch)

@@ -318,10 +318,12 @@ pp_status pp_fetch_hits_device(pp_context *ctx, uint64_t batch, void *dev_out, u
  * dev_counts on hip_stream, from the batch's hits on the device. The work on
  * hip_stream waits for the batch's propagation, whatever stream that ran on.
  * The counts cover every hit: if the hit buffer could have overflowed
- * (fewer slots than photons) and pp_hit_count has not been called since the
- * propagation, the call first checks the count as pp_hit_count does (so it
- * synchronises the batch's stream, and reruns the batch on overflow);
- * otherwise it does not synchronise. */
+ * (fewer slots than photons), the call first checks the count as
+ * pp_hit_count does (so it synchronises the batch's stream, and reruns the
+ * batch on overflow), unless a propagation of this batch has already been
+ * found to fit its buffer with the same ice, geometry, step cap, optics and
+ * acceptance (the hits are then the same); otherwise it does not
+ * synchronise. */
 pp_status pp_dom_counts(pp_context *ctx, uint64_t batch, uint32_t *dev_counts, void *hip_stream);
 
 /* Per-module sums of hit weights: writes n_doms doubles into device memory

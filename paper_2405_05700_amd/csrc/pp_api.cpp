@@ -566,16 +566,18 @@ pp_status complete_hits(pp_context *ctx, Batch &b, uint64_t *n_total) {
   }
   *n_total = cnt[pp::kHitCount];
   b.hits_complete = true;
+  b.fits_gen = ctx->results_gen;
   return PP_OK;
 }
 
 // Makes the batch's complete hit buffer visible to work enqueued next on
-// stream: if the buffer could have overflowed and its count has not been
-// checked since the propagation, checks it (synchronising the batch's stream
-// and rerunning on overflow); then orders stream after the propagation.
+// stream: if the buffer could have overflowed and no propagation of the
+// batch under the same results-affecting state has been checked to fit it,
+// checks the count (synchronising the batch's stream and rerunning on
+// overflow); then orders stream after the propagation.
 pp_status hits_ready_on(pp_context *ctx, Batch &b, hipStream_t stream) {
   if (!b.propagated) return fail(ctx, PP_ESTATE, "batch not propagated");
-  if (!b.hits_complete && b.hit_cap < b.n_photons) {
+  if (!b.hits_complete && b.hit_cap < b.n_photons && b.fits_gen != ctx->results_gen) {
     uint64_t n = 0;
     pp_status st = complete_hits(ctx, b, &n);
     if (st != PP_OK) return st;
@@ -739,11 +741,13 @@ pp_status pp_set_step_cap(pp_context *ctx, uint64_t step_cap) {
   if (!ctx) return PP_EINVAL;
   if (step_cap > (1ull << 31)) return fail(ctx, PP_EINVAL, "step_cap above 2^31");
   ctx->step_cap = step_cap;
+  ++ctx->results_gen;
   return PP_OK;
 }
 
 pp_status pp_set_chromatic(pp_context *ctx, const pp_chromatic *c) {
   if (!ctx) return PP_EINVAL;
+  ++ctx->results_gen;
   if (!c) {
     ctx->chroma = pp_chromatic{};
     return PP_OK;
@@ -757,6 +761,7 @@ pp_status pp_set_chromatic(pp_context *ctx, const pp_chromatic *c) {
 
 pp_status pp_set_acceptance(pp_context *ctx, const pp_acceptance *acc) {
   if (!ctx) return PP_EINVAL;
+  ++ctx->results_gen;
   if (!acc) {
     ctx->acc_table.clear();
     ctx->acc_poly.clear();
@@ -836,6 +841,7 @@ pp_status pp_load_ice(pp_context *ctx, const pp_ice_header *h, const pp_ice_laye
   ctx->layers = std::move(L);
   ctx->bounds = std::move(B);
   ctx->ice_loaded = true;
+  ++ctx->results_gen;
   return PP_OK;
 }
 
@@ -874,6 +880,7 @@ pp_status pp_load_geometry(pp_context *ctx, const pp_dom *doms, uint32_t n, floa
     if ((st = upload(ctx, &ctx->d_doms_by_id, by_id)) != PP_OK) return st;
   }
   ctx->geo_loaded = true;
+  ++ctx->results_gen;
   return PP_OK;
 }
 

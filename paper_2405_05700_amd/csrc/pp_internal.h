@@ -35,6 +35,10 @@ struct Batch {
   pp::Records rec{};
   bool propagated = false, rec_valid = false, rec_wavelength = false;
   bool hits_complete = false;  // hit count checked against the buffer since the last propagation
+  // results generation of the context in which a propagation's hits were
+  // found to fit the buffer (0: never). Hits depend only on the sources and
+  // on that state, so a later propagation in the same generation fits too.
+  uint64_t fits_gen = 0;
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t ev_use = nullptr;  // after the last other enqueued work that reads the batch's buffers
@@ -52,6 +56,9 @@ struct pp_context {
   std::string err;
   pp_launch_config cfg{};
   uint64_t step_cap = ppi::kDefaultStepCap;
+  // bumped by every call that can change what a propagation produces (ice,
+  // geometry, step cap, optics, acceptance)
+  uint64_t results_gen = 1;
   bool records = false;
   bool records_wavelength = false;  // records from the wavelength-drawing kernel variant
   int n_cu = 0;

@@ -230,9 +230,14 @@ bool launch(pp_server *s, Slot &slot) {
       const Request &r = s->reqs[s->resident.front()];
       bool ok = true;
       for (uint32_t ev : r.events) ok = ok && !seen.count(ev);
-      if (!take.empty() && ((r.chunks && r.chunk_pos != first_chunk + n_chunks) ||
-                            (!r.dev.empty() && r.src_pos != first_src + n_src)))
-        ok = false;  // a ring wrapped: the run ends here
+      // The run must be one window of each ring: a request that does not
+      // follow on directly, or that starts again at the ring's first
+      // record, begins the next launch.
+      if (r.chunks && n_chunks &&
+          (r.chunk_pos != first_chunk + n_chunks || r.chunk_pos % s->chunk_ring.cap == 0))
+        ok = false;
+      if (!r.dev.empty() && n_src && (r.src_pos != first_src + n_src || r.src_pos % s->src_ring.cap == 0))
+        ok = false;
       if (!ok) break;
       if (take.empty() || n_chunks == 0) first_chunk = r.chunk_pos;
       if (take.empty() || n_src == 0) first_src = r.src_pos;

@@ -228,7 +228,7 @@ def evaluate(ctx, det, members, n_sets: int = 4, truth_photons: int = 400_000_00
     graded_all = sum(len(S["graded"]) for S in sets[1:])
     n_fb = sum(int((S["spread"][S["graded"]] >= tau).sum()) for S in sets[1:])
     t_plain, t_hyb = legs["plain"]["kernel_s"], t_sur + legs["fallback"]["kernel_s"]
-    # truth-selected fallback: an upper bound no real run reaches (it needs the truth)
+    # fallback for exactly the modules the truth puts outside 2% (no real run can choose so)
     t_upper = t_sur
     for S in sets[1:]:
         g = S["graded"]
@@ -246,4 +246,4 @@ def evaluate(ctx, det, members, n_sets: int = 4, truth_photons: int = 400_000_00
             "accuracy": {"surrogate_plus_mc": errors(lambda S: S["fallback_est"]),
                          "plain_mc": errors(lambda S: S["plain_est"]),
                          "surrogate_alone": errors(lambda S: S["mean"][S["graded"]])},
-            "speedup_upper_bound_truth_selected": t_plain / t_upper if t_upper > 0 else None}
+            "speedup_truth_selected_fallback": t_plain / t_upper if t_upper > 0 else None}

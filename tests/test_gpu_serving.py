@@ -138,29 +138,30 @@ def test_served_events_match_the_oracle(mods):
 
 
 def test_small_queue_defers_and_bounds_memory(mods):
-    """A 16 KiB budget: the device queue holds 256 work-queue entries, fewer
-    than the 48 events need at once (418), so admissions are deferred until
-    launches free ring space; the queue bytes held never exceed the rings,
-    the arena and any overflow buffer fit the budget, and results stay those
-    of solo runs."""
+    """A 16 KiB budget: the device queue holds 256 work-queue entries and 24
+    events of 40 000 photons need 157 each, so no two fit at once: each
+    admission waits for the launch before it to free ring space. The queue
+    bytes held never exceed the rings, the arena and any overflow buffer fit
+    the budget, and results stay those of solo runs."""
     pp, server, surrogate = mods
-    w = events(48, seed=10, cap=20_000)
-    entries = int(np.ceil(w.sources["n_photons"] / 256).sum())
+    base = events(1, seed=10)
+    src = W.cherenkov_segments(24, 40_000, seed=10, first_event_id=2000)
+    w = base.with_sources(src)
     budget = 16 * 1024
     ctx = pp.Context(0, seed=0)
     ctx.load_workload(w)
     srv = server.Server(ctx, max_inflight=2, hbm_budget_bytes=budget)
     st0 = srv.stats()
     assert st0["arena_bytes"] <= budget
-    assert entries > 256
+    assert 2 * int(np.ceil(40_000 / 256)) > 256
     res = run_clients(srv, w, n_clients=8, jitter_s=0.0)
     st = srv.stats()
     srv.close()
     say("small queue", budget, st)
-    assert st["completed"] == 48 and st["deferred"] > 0
+    assert st["completed"] == 24 and st["deferred"] > 0 and st["launches"] == 24
     assert st["peak_bytes_in_use"] <= 256 * 16 + 64 * 80
     assert st["arena_bytes"] + st["overflow_bytes_peak"] <= budget
-    for i in (0, 11, 23, 47):
+    for i in (0, 11, 23):
         assert (res[i][0] == alone_hits(pp, w, i)).all()
 
 
