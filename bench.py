@@ -116,6 +116,8 @@ def parse():
     ap.add_argument("--serve-saturation-seconds", type=float, default=5.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter scaling)")
+    ap.add_argument("--only-uneven", action="store_true",
+                    help="only run the batched uneven events and print their figures (for profiling)")
     return ap.parse_args()
 
 
@@ -459,6 +461,9 @@ def main():
     import torch
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.only_uneven:
+        print(json.dumps(uneven_rate()), flush=True)
         return
     from paper_2405_05700_amd import pp
     from paper_2405_05700_amd import workloads as W

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpp.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("pp_api.cpp", "pp_kernels.hip", "sur_api.cpp",
                                             "sur_kernels.hip", "srv_api.cpp", "pp_static.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("pp_device.h", "pp_internal.h", "sur_device.h")] + \
+HEADERS = [os.path.join(CSRC, f) for f in ("pp_device.h", "pp_internal.h", "sur_device.h", "gelu_cdf_table.h")] + \
           [os.path.join(ROOT, "include", f) for f in ("pp.h", "pp_surrogate.h", "pp_server.h")]
 ARCH = "gfx950"
 
