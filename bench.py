@@ -118,6 +118,9 @@ def parse():
                     help="only run a plain device copy of known size (for HBM counter scaling)")
     ap.add_argument("--only-uneven", action="store_true",
                     help="only run the batched uneven events and print their figures (for profiling)")
+    ap.add_argument("--only-inference", action="store_true",
+                    help="only time the surrogate's fused inference over 1e5 segments x 5160 modules, with "
+                         "untrained weights (for profiling)")
     return ap.parse_args()
 
 
@@ -221,6 +224,35 @@ def uneven_rate():
             "kernel_ms_autotuned": ms_tuned, "photons_per_s_autotuned": n / (ms_tuned / 1e3),
             "autotune_gain": ms_default / ms_tuned,
             "graph_replay_ms": ms_graph, "photons_per_s_graph": n / (ms_graph / 1e3)}
+
+
+def inference_rate(n_sources: int):
+    """The surrogate's fused inference alone: per-module expected hits of
+    n_sources full-detector segments x 5160 modules (numpy seed 303) with
+    untrained weights (seed 1; the work does not depend on the weights), one
+    warm-up and three timed calls."""
+    import torch
+    from paper_2405_05700_amd import pp, surrogate
+    from paper_2405_05700_amd import workloads as W
+    w = W.full_detector(n_sources=n_sources, photons_per_source=1, seed=303)
+    ctx = pp.Context(0, seed=0)
+    ctx.load_workload(w)
+    sur = surrogate.Surrogate(ctx, seed=1)
+    b = ctx.submit(w.sources)
+    sur.expected_hits(b)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        sur.expected_hits(b)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    sur.close()
+    ctx.close()
+    pairs = n_sources * len(w.doms)
+    t = sorted(ts)[1]
+    return {"pairs": pairs, "infer_s_median": t, "pairs_per_s": pairs / t,
+            "tflops": pairs * INFER_FLOP_PER_PAIR / t / 1e12, "frac": pairs * INFER_FLOP_PER_PAIR / t / PEAK_BF16_FLOPS}
 
 
 def cpu_model():
@@ -464,6 +496,9 @@ def main():
         return
     if args.only_uneven:
         print(json.dumps(uneven_rate()), flush=True)
+        return
+    if args.only_inference:
+        print(json.dumps(inference_rate(args.sur_infer_sources)), flush=True)
         return
     from paper_2405_05700_amd import pp
     from paper_2405_05700_amd import workloads as W
