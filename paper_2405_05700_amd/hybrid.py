@@ -14,7 +14,8 @@ error 1/sqrt(n), so 2500 hits give the 2% error; over many modules 68.3% of
 such estimates fall within 2% of the truth and 95.4% within 4%. The
 surrogate's answer for a module is accepted when it is at least as good in
 that sense: the fallback rule is calibrated on held-out modules with a known
-truth so that the accepted ones meet both fractions.
+truth so that the accepted ones meet both fractions and none of them is off
+by more than 10% (five standard errors of such an estimate).
 """
 from __future__ import annotations
 
@@ -24,6 +25,7 @@ import numpy as np
 
 HITS_FOR_2PCT = 2500
 WITHIN_2PCT, WITHIN_4PCT = 0.683, 0.954  # Gaussian one- and two-sigma coverage
+MAX_ACCEPTED = 0.10                      # five standard errors of a 2% Monte Carlo estimate
 
 
 def cluster_light(members, batch: int, n_sources: int, cluster_of_source: np.ndarray, n_clusters: int):
@@ -56,14 +58,17 @@ def within_fractions(rel: np.ndarray):
 
 def calibrate_threshold(spread: np.ndarray, rel: np.ndarray) -> float:
     """Largest spread threshold t such that the modules with spread < t
-    reach both Monte Carlo coverages (68.3% within 2%, 95.4% within 4%).
-    rel: their relative errors against the truth. 0 if none does."""
+    reach both Monte Carlo coverages (68.3% within 2%, 95.4% within 4%) and
+    none of them is off by more than MAX_ACCEPTED (five of Monte Carlo's
+    standard errors). rel: their relative errors against the truth. 0 if
+    none does."""
     order = np.argsort(spread, kind="stable")
     s, a = spread[order], np.abs(rel[order])
     n = np.arange(1, len(s) + 1)
     ok2 = np.cumsum(a <= 0.02) >= WITHIN_2PCT * n
     ok4 = np.cumsum(a <= 0.04) >= WITHIN_4PCT * n
-    good = np.nonzero(ok2 & ok4)[0]
+    ok_max = np.maximum.accumulate(a) <= MAX_ACCEPTED
+    good = np.nonzero(ok2 & ok4 & ok_max)[0]
     if len(good) == 0:
         return 0.0
     k = good[-1]  # the first k + 1 modules in spread order pass

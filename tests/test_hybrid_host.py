@@ -21,6 +21,12 @@ def test_threshold_keeps_the_largest_prefix_that_matches_monte_carlo():
     assert H.calibrate_threshold(np.array([0.01]), np.array([0.5])) == 0.0
     # 2 of 3 within 2% is below 68.3%, but all within 4%: only the first passes
     assert H.calibrate_threshold(np.array([0.1, 0.2, 0.3]), np.array([0.0, 0.03, 0.03])) == 0.2
+    # coverage alone would accept all 40, but one of them is 12% off: the
+    # threshold stops below it
+    sp = np.arange(40) / 40.0
+    rel = np.zeros(40)
+    rel[30] = 0.12
+    assert H.calibrate_threshold(sp, rel) == sp[30]
 
 
 def test_spread_is_the_members_relative_standard_deviation():
