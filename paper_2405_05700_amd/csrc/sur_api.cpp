@@ -28,29 +28,26 @@ struct pp_surrogate {
   // training set; with pair selection (far_stride > 1) each row is the pair
   // pair_of_row[row] with loss weight w[row], else row = pair and weight 1
   int64_t P = 0, P_pad = 0;
-  uint16_t *X = nullptr, *XT = nullptr;
+  uint16_t *X = nullptr;
   float *mu_base = nullptr, *nph = nullptr, *k = nullptr, *n_t = nullptr, *s1 = nullptr, *s2 = nullptr;
   float near_m = INFINITY;
   uint32_t far_stride = 1;
   float cut_m = INFINITY;  // inference distance cut
   int64_t *pair_of_row = nullptr;
   float *w = nullptr;
-  // minibatch work buffers (capacity Mcap rows)
+  // minibatch work buffers (capacity Mcap rows): bf16 feature-major copies
+  // of the inputs, activations and output gradients for the weight
+  // gradients, and the fixed-order reduction parts (per 32-row block: bias
+  // column sums and loss; per K slice: weight-gradient partials, capacity
+  // ws_splits slices)
   int64_t Mcap = 0;
-  float *Z[4] = {};
-  uint16_t *H[4] = {}, *HT[4] = {};
-  float *Y = nullptr;
-  uint16_t *dY = nullptr, *dYT = nullptr, *dZ[2] = {}, *dZT = nullptr;
-  double *d_loss = nullptr;
-  // fixed-order reductions: split-K partials of the weight gradients,
-  // per-32-row column sums of the bias gradients, per-workgroup loss parts
-  float *ws = nullptr, *col_part = nullptr, *bias_part = nullptr;
+  uint16_t *XT = nullptr, *HT[4] = {}, *dYT = nullptr, *dZT[4] = {};
+  float *col_part = nullptr;
   double *loss_part = nullptr;
+  float *ws = nullptr;
+  int ws_splits = 0;
+  double *d_loss = nullptr;
   double *epoch_loss = nullptr;  // device accumulator while training, else null
-  // shuffled minibatch staging (capacity Gcap rows) and shuffle state
-  int64_t Gcap = 0;
-  uint16_t *gX = nullptr, *gXT = nullptr;
-  float *g_lab[7] = {};  // mu_base, nph, k, n_t, s1, s2, w
   uint64_t shuffle_seed = 0;
   uint64_t epochs_done = 0;
   // inference buffers (capacity Icap rows; photons per source, capacity
@@ -63,7 +60,6 @@ struct pp_surrogate {
 namespace {
 
 constexpr int64_t kInferRows = 1 << 21;  // pairs per inference chunk
-constexpr int kMaxSplits = 64;            // K slices of a weight-gradient GEMM
 
 int64_t round64(int64_t n) { return (n + 63) / 64 * 64; }
 
@@ -92,177 +88,122 @@ OnExit<F> on_exit(F f) {
   return OnExit<F>{f};
 }
 
-pp_status gemm(pp_context *ctx, int epi, const uint16_t *A, int64_t lda, const uint16_t *B, int64_t ldb, int M,
-               int N, int K, int splits, const float *bias, float *Z, uint16_t *H, uint16_t *HT, int64_t ldt,
-               const float *Zin, float *out, hipStream_t st, float *col_sums = nullptr, float *ws = nullptr,
-               float *col_part = nullptr) {
-  sur::GemmArgs g{};
-  g.A = A;
-  g.lda = lda;
-  g.B = B;
-  g.ldb = ldb;
-  g.M = M;
-  g.N = N;
-  g.K = K;
-  splits = std::max(1, std::min(splits, K / 32));
-  g.k_chunk = ((K + splits - 1) / splits + 31) / 32 * 32;
-  splits = (K + g.k_chunk - 1) / g.k_chunk;
-  g.bias = bias;
-  g.Z = Z;
-  g.H = H;
-  g.HT = HT;
-  g.ldt = ldt;
-  g.Zin = Zin;
-  g.out = out;
-  g.ws = ws;
-  g.col_sums = col_sums;
-  g.col_part = col_sums ? col_part : nullptr;
-  PP_HIP(ctx, sur::launch_gemm(epi, g, splits, st));
-  return PP_OK;
-}
-
 const float *bias_ptr(const pp_surrogate *s, int l) { return s->theta + sur::b_offset(l); }
 const uint16_t *wb_ptr(const pp_surrogate *s, int l) { return s->wb + sur::wb_offset(l); }
 const uint16_t *wt_ptr(const pp_surrogate *s, int l) { return s->wt + sur::wb_offset(l); }
 
-pp_status ensure_work(pp_surrogate *s, int64_t M) {
-  if (M <= s->Mcap) return PP_OK;
-  pp_context *ctx = s->ctx;
-  pp_status st;
-  for (int l = 0; l < 4; ++l) {
-    if ((st = dalloc(ctx, &s->Z[l], M * sur::kHidden)) != PP_OK) return st;
-    if ((st = dalloc(ctx, &s->H[l], M * sur::kHidden)) != PP_OK) return st;
-    if ((st = dalloc(ctx, &s->HT[l], M * sur::kHidden)) != PP_OK) return st;
-  }
-  if ((st = dalloc(ctx, &s->Y, M * sur::kOutPad)) != PP_OK) return st;
-  if ((st = dalloc(ctx, &s->dY, M * sur::kOutPad)) != PP_OK) return st;
-  if ((st = dalloc(ctx, &s->dYT, M * sur::kOutPad)) != PP_OK) return st;
-  if ((st = dalloc(ctx, &s->dZ[0], M * sur::kHidden)) != PP_OK) return st;
-  if ((st = dalloc(ctx, &s->dZ[1], M * sur::kHidden)) != PP_OK) return st;
-  if ((st = dalloc(ctx, &s->dZT, M * sur::kHidden)) != PP_OK) return st;
-  if ((st = dalloc(ctx, &s->col_part, (M / 32) * sur::kHidden)) != PP_OK) return st;
-  if ((st = dalloc(ctx, &s->loss_part, sur::loss_blocks(static_cast<int>(M)))) != PP_OK) return st;
-  if ((st = dalloc(ctx, &s->bias_part, 3 * static_cast<int64_t>(sur::loss_blocks(static_cast<int>(M))))) != PP_OK)
-    return st;
-  if (!s->ws && (st = dalloc(ctx, &s->ws, int64_t{kMaxSplits} * sur::kHidden * sur::kHidden)) != PP_OK) return st;
-  s->Mcap = M;
-  return PP_OK;
+// K slices of the weight gradients over M minibatch rows: kWgradSplits, or
+// one per 32-row block when there are fewer.
+int wgrad_splits(int64_t M) {
+  return static_cast<int>(std::min<int64_t>(sur::kWgradSplits, M / sur::kTrainRows));
 }
 
-// One minibatch as the network sees it: features row-major and transposed,
-// and the per-row labels.
-struct Rows {
-  const uint16_t *X, *XT;
-  int64_t ld_XT;
-  const float *mu_base, *nph, *k, *n_t, *s1, *s2;
-  const float *w;  // null: weight 1
-};
-
-// Training rows [first, first + count) in stored order.
-Rows slice_rows(const pp_surrogate *s, int64_t first) {
-  return Rows{s->X + first * sur::kInPad, s->XT + first, s->P_pad, s->mu_base + first, s->nph + first,
-              s->k + first, s->n_t + first, s->s1 + first, s->s2 + first, s->w ? s->w + first : nullptr};
+pp_status ensure_work(pp_surrogate *s, int64_t M) {
+  pp_context *ctx = s->ctx;
+  pp_status st;
+  if (M > s->Mcap) {
+    if ((st = dalloc(ctx, &s->XT, M * sur::kInPad)) != PP_OK) return st;
+    for (int l = 0; l < 4; ++l) {
+      if ((st = dalloc(ctx, &s->HT[l], M * sur::kHidden)) != PP_OK) return st;
+      if ((st = dalloc(ctx, &s->dZT[l], M * sur::kHidden)) != PP_OK) return st;
+    }
+    if ((st = dalloc(ctx, &s->dYT, M * sur::kOutPad)) != PP_OK) return st;
+    if ((st = dalloc(ctx, &s->col_part, (M / sur::kTrainRows) * sur::kBiasCols)) != PP_OK) return st;
+    if ((st = dalloc(ctx, &s->loss_part, M / sur::kTrainRows)) != PP_OK) return st;
+    s->Mcap = M;
+  }
+  const int splits = wgrad_splits(M);
+  if (splits > s->ws_splits) {
+    if ((st = dalloc(ctx, &s->ws, int64_t{splits} * sur::wb_count())) != PP_OK) return st;
+    s->ws_splits = splits;
+  }
+  return PP_OK;
 }
 
 pp_status check_rows(pp_surrogate *s, int64_t first, int64_t count) {
-  if (first % 64 != 0 || count <= 0 || first + count > s->P)
-    return fail(s->ctx, PP_EINVAL, "rows [%lld, %lld) invalid: start must be a multiple of 64 within %lld pairs",
-                (long long)first, (long long)(first + count), (long long)s->P);
+  if (count <= 0 || first < 0 || first + count > s->P)
+    return fail(s->ctx, PP_EINVAL, "rows [%lld, %lld) invalid: must lie within %lld pairs", (long long)first,
+                (long long)(first + count), (long long)s->P);
+  if (count > (int64_t{1} << 30)) return fail(s->ctx, PP_EINVAL, "at most 2^30 rows per pass");
   return PP_OK;
 }
 
-// Forward, loss and backward over count rows of r (padded to a multiple of
-// 64 with zero rows); leaves the gradient in s->grad and the summed loss in
-// s->d_loss.
-pp_status forward_backward(pp_surrogate *s, const Rows &r, int64_t count, hipStream_t st) {
+// One pass over the minibatch of training rows (mul (first + i) + add) mod P,
+// i < count: forward, loss and backward, the gradient left in s->grad and the
+// loss sum in s->d_loss (and added to s->epoch_loss if set); with adam, also
+// the Adam step with step size lr. Three launches on stream st.
+pp_status train_pass(pp_surrogate *s, uint64_t mul, uint64_t add, int64_t first, int64_t count, bool adam,
+                     float lr, hipStream_t st) {
   pp_context *ctx = s->ctx;
-  const int M = static_cast<int>(round64(count));
+  using namespace sur;
+  const int64_t M = round64(count);
   pp_status rc = ensure_work(s, M);
   if (rc != PP_OK) return rc;
-  using namespace sur;
-  const uint16_t *X = r.X;
-  const uint16_t *XT = r.XT;
-  // forward
-  const uint16_t *in = X;
-  int64_t ld_in = kInPad;
+  TrainArgs t{};
+  t.X = s->X;
+  t.mu_base = s->mu_base;
+  t.nph = s->nph;
+  t.k = s->k;
+  t.n_t = s->n_t;
+  t.s1 = s->s1;
+  t.s2 = s->s2;
+  t.w = s->w;
+  t.P = static_cast<uint64_t>(s->P);
+  t.mul = mul;
+  t.add = add;
+  t.first = first;
+  t.count = static_cast<int>(count);
+  t.M = static_cast<int>(M);
+  t.inv_norm = 1.0f / static_cast<float>(count);
+  for (int l = 0; l < kLayers; ++l) {
+    t.wb[l] = wb_ptr(s, l);
+    t.wt[l] = wt_ptr(s, l);
+    t.b[l] = bias_ptr(s, l);
+  }
+  t.XT = s->XT;
+  t.dYT = s->dYT;
   for (int l = 0; l < 4; ++l) {
-    if ((rc = gemm(ctx, kEpiGelu, in, ld_in, wb_ptr(s, l), in_dim(l), M, kHidden, in_dim(l), 1, bias_ptr(s, l),
-                   s->Z[l], s->H[l], s->HT[l], M, nullptr, nullptr, st)) != PP_OK)
-      return rc;
-    in = s->H[l];
-    ld_in = kHidden;
+    t.HT[l] = s->HT[l];
+    t.dZT[l] = s->dZT[l];
   }
-  if ((rc = gemm(ctx, kEpiLinear, s->H[3], kHidden, wb_ptr(s, 4), kHidden, M, kOutPad, kHidden, 1, bias_ptr(s, 4),
-                 nullptr, nullptr, nullptr, 0, nullptr, s->Y, st)) != PP_OK)
-    return rc;
-  // loss and output gradient
-  LossArgs la{};
-  la.Y = s->Y;
-  la.mu_base = r.mu_base;
-  la.nph = r.nph;
-  la.k = r.k;
-  la.n_t = r.n_t;
-  la.s1 = r.s1;
-  la.s2 = r.s2;
-  la.w = r.w;
-  la.M_real = static_cast<int>(count);
-  la.M_pad = M;
-  la.inv_norm = 1.0f / static_cast<float>(count);
-  la.dY = s->dY;
-  la.dYT = s->dYT;
-  la.loss_sum = s->d_loss;
-  la.loss_epoch = s->epoch_loss;
-  la.out_bias_grad = s->grad + b_offset(4);
-  la.loss_part = s->loss_part;
-  la.bias_part = s->bias_part;
-  PP_HIP(ctx, launch_loss(la, st));
-  // backward: every gradient element is written once (no accumulation)
-  const int splits = std::min(kMaxSplits, std::max(1, M / 512));
-  // output layer
-  if ((rc = gemm(ctx, kEpiSplitK, s->dYT, M, s->HT[3], M, kOutPad, kHidden, M, splits, nullptr, nullptr, nullptr,
-                 nullptr, 0, nullptr, s->grad + w_offset(4), st, nullptr, s->ws)) != PP_OK)
-    return rc;
-  // dZ3 = (dY . W4) * gelu'(Z3), and db3 = column sums of dZ3
-  if ((rc = gemm(ctx, kEpiGeluBwd, s->dY, kOutPad, wt_ptr(s, 4), kOutPad, M, kHidden, kOutPad, 1, nullptr,
-                 nullptr, s->dZ[1], s->dZT, M, s->Z[3], nullptr, st, s->grad + b_offset(3), nullptr, s->col_part)) !=
-      PP_OK)
-    return rc;
-  int cur = 1;
-  for (int l = 3; l >= 0; --l) {
-    // dW_l = dZ_l^T . H_{l-1} (X for l = 0); db_l came with dZ_l
-    const uint16_t *prevT = l > 0 ? s->HT[l - 1] : XT;
-    const int64_t ld_prevT = l > 0 ? M : r.ld_XT;
-    if ((rc = gemm(ctx, kEpiSplitK, s->dZT, M, prevT, ld_prevT, kHidden, in_dim(l), M, splits, nullptr, nullptr,
-                   nullptr, nullptr, 0, nullptr, s->grad + w_offset(l), st, nullptr, s->ws)) != PP_OK)
-      return rc;
-    if (l == 0) break;
-    // dZ_{l-1} = (dZ_l . W_l) * gelu'(Z_{l-1}), and its column sums db_{l-1}
-    if ((rc = gemm(ctx, kEpiGeluBwd, s->dZ[cur], kHidden, wt_ptr(s, l), kHidden, M, kHidden, kHidden, 1, nullptr,
-                   nullptr, s->dZ[1 - cur], s->dZT, M, s->Z[l - 1], nullptr, st, s->grad + b_offset(l - 1), nullptr,
-                   s->col_part)) != PP_OK)
-      return rc;
-    cur = 1 - cur;
+  t.col_part = s->col_part;
+  t.loss_part = s->loss_part;
+  PP_HIP(ctx, launch_train_rows(t, st));
+  WgradArgs g{};
+  g.A[0] = s->dZT[0];
+  g.B[0] = s->XT;
+  for (int l = 1; l < 4; ++l) {
+    g.A[l] = s->dZT[l];
+    g.B[l] = s->HT[l - 1];
   }
-  return PP_OK;
-}
-
-pp_status adam_step(pp_surrogate *s, float lr, hipStream_t st) {
-  s->adam_t += 1;
-  const float c1 = 1.0f - std::pow(0.9f, static_cast<float>(s->adam_t));
-  const float c2 = 1.0f - std::pow(0.999f, static_cast<float>(s->adam_t));
-  PP_HIP(s->ctx, sur::launch_adam(s->theta, s->grad, s->adam_m, s->adam_v, sur::param_count(), lr, c1, c2, st));
-  PP_HIP(s->ctx, sur::launch_pack_weights(s->theta, s->wb, s->wt, st));
-  return PP_OK;
-}
-
-pp_status ensure_gather(pp_surrogate *s, int64_t M) {
-  if (M <= s->Gcap) return PP_OK;
-  pp_status st;
-  if ((st = dalloc(s->ctx, &s->gX, M * sur::kInPad)) != PP_OK) return st;
-  if ((st = dalloc(s->ctx, &s->gXT, M * sur::kInPad)) != PP_OK) return st;
-  for (auto &p : s->g_lab)
-    if ((st = dalloc(s->ctx, &p, M)) != PP_OK) return st;
-  s->Gcap = M;
+  g.A[4] = s->dYT;
+  g.B[4] = s->HT[3];
+  g.M = static_cast<int>(M);
+  g.splits = wgrad_splits(M);
+  g.ws = s->ws;
+  PP_HIP(ctx, launch_wgrad(g, st));
+  AdamArgs a{};
+  a.theta = s->theta;
+  a.grad = s->grad;
+  a.m = s->adam_m;
+  a.v = s->adam_v;
+  a.wb = s->wb;
+  a.wt = s->wt;
+  a.ws = s->ws;
+  a.splits = g.splits;
+  a.col_part = s->col_part;
+  a.loss_part = s->loss_part;
+  a.n_blocks = static_cast<int>(M / kTrainRows);
+  a.loss_sum = s->d_loss;
+  a.loss_epoch = s->epoch_loss;
+  a.adam = adam ? 1 : 0;
+  if (adam) {
+    s->adam_t += 1;
+    a.lr = lr;
+    a.c1 = 1.0f - std::pow(0.9f, static_cast<float>(s->adam_t));
+    a.c2 = 1.0f - std::pow(0.999f, static_cast<float>(s->adam_t));
+  }
+  PP_HIP(ctx, launch_reduce_adam(a, st));
   return PP_OK;
 }
 
@@ -273,43 +214,6 @@ uint64_t gcd64(uint64_t a, uint64_t b) {
     b = t;
   }
   return a;
-}
-
-// Gathers rows p(first .. first + count) of the epoch's permutation
-// p(r) = (mul r + add) mod P into the staging buffers.
-pp_status gather_rows(pp_surrogate *s, uint64_t mul, uint64_t add, int64_t first, int64_t count, Rows *out,
-                      hipStream_t st) {
-  const int64_t M = round64(count);
-  pp_status rc = ensure_gather(s, M);
-  if (rc != PP_OK) return rc;
-  sur::GatherArgs g{};
-  g.X = s->X;
-  g.mu_base = s->mu_base;
-  g.nph = s->nph;
-  g.k = s->k;
-  g.n_t = s->n_t;
-  g.s1 = s->s1;
-  g.s2 = s->s2;
-  g.w = s->w;
-  g.P = static_cast<uint64_t>(s->P);
-  g.mul = mul;
-  g.add = add;
-  g.first = first;
-  g.count = static_cast<int>(count);
-  g.M = static_cast<int>(M);
-  g.gX = s->gX;
-  g.gXT = s->gXT;
-  g.g_mu_base = s->g_lab[0];
-  g.g_nph = s->g_lab[1];
-  g.g_k = s->g_lab[2];
-  g.g_n_t = s->g_lab[3];
-  g.g_s1 = s->g_lab[4];
-  g.g_s2 = s->g_lab[5];
-  g.g_w = s->g_lab[6];
-  PP_HIP(s->ctx, sur::launch_gather(g, st));
-  *out = Rows{s->gX,         s->gXT,        M,           s->g_lab[0], s->g_lab[1], s->g_lab[2],
-              s->g_lab[3],   s->g_lab[4],   s->g_lab[5], s->w ? s->g_lab[6] : nullptr};
-  return PP_OK;
 }
 
 // He-uniform initialisation (fan-in of the real inputs), zero biases, zero
@@ -485,14 +389,12 @@ void pp_sur_destroy(pp_surrogate *s) {
   if (s->device >= 0) (void)hipSetDevice(s->device);
   (void)hipDeviceSynchronize();
   dfree(s->theta), dfree(s->grad), dfree(s->adam_m), dfree(s->adam_v), dfree(s->wb), dfree(s->wt);
-  dfree(s->doms_by_id), dfree(s->X), dfree(s->XT), dfree(s->mu_base), dfree(s->nph);
+  dfree(s->doms_by_id), dfree(s->X), dfree(s->mu_base), dfree(s->nph);
   dfree(s->k), dfree(s->n_t), dfree(s->s1), dfree(s->s2), dfree(s->pair_of_row), dfree(s->w);
-  for (int l = 0; l < 4; ++l) dfree(s->Z[l]), dfree(s->H[l]), dfree(s->HT[l]);
-  dfree(s->Y), dfree(s->dY), dfree(s->dYT), dfree(s->dZ[0]), dfree(s->dZ[1]), dfree(s->dZT), dfree(s->d_loss);
-  dfree(s->ws), dfree(s->col_part), dfree(s->bias_part), dfree(s->loss_part);
+  dfree(s->XT), dfree(s->dYT), dfree(s->d_loss);
+  for (int l = 0; l < 4; ++l) dfree(s->HT[l]), dfree(s->dZT[l]);
+  dfree(s->ws), dfree(s->col_part), dfree(s->loss_part);
   dfree(s->i_mu), dfree(s->i_src_nph);
-  dfree(s->gX), dfree(s->gXT);
-  for (auto &p : s->g_lab) dfree(p);
   delete s;
 }
 
@@ -583,7 +485,7 @@ pp_status pp_sur_set_training_set(pp_surrogate *s, uint64_t batch) {
   }
   s->P_pad = round64(s->P);
   const int64_t R = s->P_pad;
-  if ((st = dalloc(ctx, &s->X, R * sur::kInPad)) != PP_OK || (st = dalloc(ctx, &s->XT, R * sur::kInPad)) != PP_OK ||
+  if ((st = dalloc(ctx, &s->X, R * sur::kInPad)) != PP_OK ||
       (st = dalloc(ctx, &s->mu_base, R)) != PP_OK || (st = dalloc(ctx, &s->nph, R)) != PP_OK ||
       (st = dalloc(ctx, &s->k, R)) != PP_OK || (st = dalloc(ctx, &s->n_t, R)) != PP_OK ||
       (st = dalloc(ctx, &s->s1, R)) != PP_OK || (st = dalloc(ctx, &s->s2, R)) != PP_OK)
@@ -598,8 +500,6 @@ pp_status pp_sur_set_training_set(pp_surrogate *s, uint64_t batch) {
   f.n_pairs = s->P;
   f.pair_of_row = s->pair_of_row;
   f.X = s->X;
-  f.XT = s->XT;
-  f.ldxt = R;
   f.mu_base = s->mu_base;
   f.nph = s->nph;
   PP_HIP(ctx, sur::launch_features(f, nullptr));
@@ -686,7 +586,7 @@ pp_status pp_sur_loss_grad(pp_surrogate *s, uint64_t first, uint64_t count, doub
   pp_status st = need_device(s->ctx);
   if (st != PP_OK) return st;
   if ((st = check_rows(s, static_cast<int64_t>(first), static_cast<int64_t>(count))) != PP_OK) return st;
-  if ((st = forward_backward(s, slice_rows(s, static_cast<int64_t>(first)), static_cast<int64_t>(count), nullptr)) !=
+  if ((st = train_pass(s, 1, 0, static_cast<int64_t>(first), static_cast<int64_t>(count), false, 0.0f, nullptr)) !=
       PP_OK)
     return st;
   PP_HIP(s->ctx, hipDeviceSynchronize());
@@ -704,10 +604,9 @@ pp_status pp_sur_train_step(pp_surrogate *s, uint64_t first, uint64_t count, flo
   pp_status st = need_device(s->ctx);
   if (st != PP_OK) return st;
   if ((st = check_rows(s, static_cast<int64_t>(first), static_cast<int64_t>(count))) != PP_OK) return st;
-  if ((st = forward_backward(s, slice_rows(s, static_cast<int64_t>(first)), static_cast<int64_t>(count), nullptr)) !=
+  if ((st = train_pass(s, 1, 0, static_cast<int64_t>(first), static_cast<int64_t>(count), true, lr, nullptr)) !=
       PP_OK)
     return st;
-  if ((st = adam_step(s, lr, nullptr)) != PP_OK) return st;
   PP_HIP(s->ctx, hipDeviceSynchronize());
   if (loss) {
     double l = 0;
@@ -723,7 +622,8 @@ pp_status pp_sur_train(pp_surrogate *s, uint32_t epochs, uint32_t batch_size, fl
   pp_context *ctx = s->ctx;
   pp_status st = need_device(ctx);
   if (st != PP_OK) return st;
-  if (batch_size == 0 || batch_size % 64 != 0) return fail(ctx, PP_EINVAL, "batch_size must be a positive multiple of 64");
+  if (batch_size == 0 || batch_size % 64 != 0 || batch_size > (1u << 30))
+    return fail(ctx, PP_EINVAL, "batch_size must be a positive multiple of 64, at most 2^30");
   if (!(lr >= 0.0f) || !(lr_final >= 0.0f) || !std::isfinite(lr) || !std::isfinite(lr_final))
     return fail(ctx, PP_EINVAL, "learning rates must be finite and non-negative");
   if (s->P == 0) return fail(ctx, PP_ESTATE, "no training set");
@@ -751,13 +651,10 @@ pp_status pp_sur_train(pp_surrogate *s, uint32_t epochs, uint32_t batch_size, fl
     PP_HIP(ctx, sur::launch_zero_f64(d_epoch, 1, stream));
     for (int64_t first = 0; first < s->P; first += batch_size, ++step) {
       const int64_t count = std::min<int64_t>(batch_size, s->P - first);
-      Rows r;
-      if ((st = gather_rows(s, mul, add, first, count, &r, stream)) != PP_OK) break;
-      if ((st = forward_backward(s, r, count, stream)) != PP_OK) break;
       // cosine decay from lr to lr_final over this call's steps
       const double c = 0.5 * (1.0 + std::cos(M_PI * static_cast<double>(step) / total_steps));
       const float lr_t = static_cast<float>(lr_final + (lr - lr_final) * c);
-      if ((st = adam_step(s, lr_t, stream)) != PP_OK) break;
+      if ((st = train_pass(s, mul, add, first, count, true, lr_t, stream)) != PP_OK) break;
     }
     if (st != PP_OK) break;
     if (epoch_loss) {

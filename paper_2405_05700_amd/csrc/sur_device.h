@@ -37,34 +37,6 @@ __host__ __device__ constexpr int64_t wb_offset(int l) {
 }
 __host__ __device__ constexpr int64_t wb_count() { return wb_offset(kLayers); }
 
-enum Epilogue {
-  kEpiGelu = 0,     // z = acc + bias; store z (f32) unless null, gelu(z) as bf16 and its transpose unless null
-  kEpiGeluBwd = 1,  // dz = acc * gelu'(z_saved); store bf16 and its transpose
-  kEpiSplitK = 2,   // out (f32) = acc summed over the K slices: each slice stores its partial in ws, then
-                    // a reduction adds them in slice order
-  kEpiLinear = 4,   // out (f32, ld N) = acc + bias
-};
-
-struct GemmArgs {
-  // C[M x N] = A[M x K] * B[N x K]^T ; A, B bf16 with K contiguous
-  const uint16_t *A;
-  int64_t lda;
-  const uint16_t *B;
-  int64_t ldb;
-  int M, N, K;
-  int k_chunk;  // K range per grid.z slice
-  const float *bias;
-  float *Z;          // f32 M x N (ld N)
-  uint16_t *H;       // bf16 M x N (ld N)
-  uint16_t *HT;      // bf16 N x M (ld ldt)
-  int64_t ldt;
-  const float *Zin;  // saved pre-activation for kEpiGeluBwd (ld N)
-  float *out;        // kEpiSplitK: f32 M x N (ld N)
-  float *ws;         // kEpiSplitK: f32 splits x M x N partials
-  float *col_sums;   // kEpiGeluBwd: column sums of the stored bf16 output (bias gradient), may be null;
-  float *col_part;   //   formed from per-32-row partials (M / 32 x N, f32) in row order
-};
-
 struct FeatureArgs {
   const pp::DevSource *sources;
   const float *src_nph;       // photons per source
@@ -82,38 +54,6 @@ struct FeatureArgs {
   float *mu_base; // per pair, may be null
   float *nph;     // photons of the pair's source, may be null
   float *r_out;   // distance per pair, may be null
-};
-
-struct LossArgs {
-  const float *Y;        // f32 M x 64 (ld 64)
-  const float *mu_base, *nph, *k, *n_t, *s1, *s2;  // per row
-  const float *w;        // loss weight per row, null: 1
-  int M_real, M_pad;
-  float inv_norm;        // 1 / number of pairs averaged over
-  uint16_t *dY;          // bf16 M_pad x 64
-  uint16_t *dYT;         // bf16 64 x M_pad
-  double *loss_sum;      // set to the loss summed over the rows
-  double *loss_epoch;    // also accumulated into, if not null
-  float *out_bias_grad;  // set to the column sums of the stored bf16 dY (output-layer bias gradient), may be null
-  double *loss_part;     // per-workgroup partials (loss_blocks(M_pad) of each)
-  float *bias_part;      //   (3 per workgroup)
-};
-int loss_blocks(int M_pad);
-
-// Copies training rows p(r) = (mul * r + add) mod P, r in [first, first + count),
-// into dense minibatch buffers (row i of the batch = row p(first + i)); rows
-// [count, M) of the batch are zero. mul is coprime to P, so p is a permutation.
-struct GatherArgs {
-  const uint16_t *X;                                // bf16 P_pad x 64
-  const float *mu_base, *nph, *k, *n_t, *s1, *s2;   // per training row
-  const float *w;                                   // per training row, may be null
-  uint64_t P, mul, add;
-  int64_t first;
-  int count, M;
-  uint16_t *gX;    // bf16 M x 64
-  uint16_t *gXT;   // bf16 64 x M
-  float *g_mu_base, *g_nph, *g_k, *g_n_t, *g_s1, *g_s2;
-  float *g_w;      // written only if w is not null
 };
 
 // Training-pair selection: a (source, module) pair is kept if the module
@@ -137,12 +77,7 @@ struct SelectArgs {
 };
 hipError_t launch_select(const SelectArgs &a, bool scatter, hipStream_t s);
 
-hipError_t launch_gemm(int epi, const GemmArgs &g, int splits, hipStream_t s);
-hipError_t launch_gather(const GatherArgs &g, hipStream_t s);
 hipError_t launch_features(const FeatureArgs &f, hipStream_t s);
-hipError_t launch_loss(const LossArgs &l, hipStream_t s);
-hipError_t launch_adam(float *theta, const float *grad, float *m, float *v, int64_t n, float lr,
-                       float c1, float c2, hipStream_t s);
 hipError_t launch_pack_weights(const float *theta, uint16_t *w_bf16, uint16_t *wt_bf16, hipStream_t s);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s);
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
@@ -152,6 +87,78 @@ hipError_t launch_labels(const pp::DevHit *hits, const unsigned long long *hit_c
                          const int32_t *row_of_pair, float *k, float *n_t, unsigned long long *s1q,
                          unsigned long long *s2q, float *s1, float *s2, int64_t n_rows, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s);
+
+// One training minibatch in three launches.
+//
+// launch_train_rows: kTrainRows minibatch rows per workgroup. Row i < count
+// of the minibatch is training row (mul (first + i) + add) mod P (mul
+// coprime to P: a permutation); rows count..M-1 are zero and carry no loss.
+// Forward, loss and backward down to dZ_0 run with the rows' activations in
+// LDS; what the weight gradients need leaves as bf16 with the minibatch row
+// contiguous, and each workgroup stores its loss sum and the column sums of
+// its dZ_l and dY rows (the bias gradients' parts).
+// launch_wgrad: dW_l = dZ_l^T H_{l-1} (dY for the output layer, X for the
+// first), every layer in one launch; K slice s (the 32-row blocks s,
+// s + splits, ...) stores its partial product.
+// launch_reduce_adam: per parameter, the partials added in slice order (the
+// bias parts in row-block order), the gradient stored, then (if adam) the
+// Adam step and the bf16 weight copies.
+constexpr int kTrainRows = 32;                    // minibatch rows per workgroup of the row pass
+constexpr int kTrainLd = kHidden + 8;             // LDS row stride (elements) of activations and GELU'
+constexpr int kDyLd = kOutPad + 8;                // LDS row stride of the output gradient
+constexpr int kBiasCols = 4 * kHidden + kOutPad;  // bias-gradient columns per row block: dZ_0..dZ_3, then dY
+constexpr int kWgradSplits = 16;                  // K slices of the weight gradients (at most)
+
+// Tiles of layer l's weight gradient: 128 x 128, or the layer's whole
+// extent where it is 64 (inputs of layer 0, outputs of the last), and
+// their running offset.
+__host__ __device__ constexpr int wgrad_tm(int l) { return out_dim(l) < 128 ? out_dim(l) : 128; }
+__host__ __device__ constexpr int wgrad_tn(int l) { return in_dim(l) < 128 ? in_dim(l) : 128; }
+__host__ __device__ constexpr int wgrad_tiles(int l) { return (out_dim(l) / wgrad_tm(l)) * (in_dim(l) / wgrad_tn(l)); }
+__host__ __device__ constexpr int wgrad_tile_offset(int l) {
+  int o = 0;
+  for (int j = 0; j < l; ++j) o += wgrad_tiles(j);
+  return o;
+}
+
+struct TrainArgs {
+  const uint16_t *X;                               // bf16 training features, 64 per row
+  const float *mu_base, *nph, *k, *n_t, *s1, *s2;  // labels per training row
+  const float *w;                                  // loss weight per training row, null: 1
+  uint64_t P, mul, add;
+  int64_t first;
+  int count, M;                    // real rows; M = count rounded up to a multiple of 64
+  float inv_norm;                  // 1 / count
+  const uint16_t *wb[kLayers];     // bf16 W (out x in)
+  const uint16_t *wt[kLayers];     // bf16 W^T (in x out)
+  const float *b[kLayers];
+  uint16_t *XT, *HT[4], *dYT, *dZT[4];  // bf16, feature-major with the minibatch row contiguous (ld M)
+  float *col_part;                 // (M / kTrainRows) x kBiasCols
+  double *loss_part;               // M / kTrainRows
+};
+struct WgradArgs {
+  const uint16_t *A[kLayers];  // dZ_l^T (out x M); dY^T for the output layer
+  const uint16_t *B[kLayers];  // H_{l-1}^T (in x M); X^T for the first layer
+  int M, splits;               // splits <= M / kTrainRows
+  float *ws;                   // layer l: splits x out x in partials from ws + splits * wb_offset(l)
+};
+struct AdamArgs {
+  float *theta, *grad, *m, *v;
+  uint16_t *wb, *wt;
+  const float *ws;
+  int splits;
+  const float *col_part;
+  const double *loss_part;
+  int n_blocks;                // row blocks of the bias and loss parts
+  double *loss_sum;            // set to the minibatch loss (weighted sum over rows)
+  double *loss_epoch;          // also added to, if not null
+  int adam;                    // 0: gradient only
+  float lr, c1, c2;            // Adam step size and bias corrections 1 - beta^t
+};
+size_t train_lds_bytes();
+hipError_t launch_train_rows(const TrainArgs &a, hipStream_t s);
+hipError_t launch_wgrad(const WgradArgs &g, hipStream_t s);
+hipError_t launch_reduce_adam(const AdamArgs &a, hipStream_t s);
 
 // Fused inference over pairs [f.first_pair, f.first_pair + f.n_pairs):
 // features, the five layers and the expected hits, kFusedRows pairs per

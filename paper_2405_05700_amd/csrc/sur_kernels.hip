@@ -2,15 +2,12 @@
 // BF16 with FP32 accumulation on the matrix cores, its backward pass, loss,
 // Adam, and the features / labels / reductions around it.
 //
-// GEMM: C[M x N] = A[M x K] * B[N x K]^T with both operands K-contiguous
-// bf16. A workgroup of four wavefronts computes a 64 x 64 tile; each
-// wavefront a 32 x 32 quarter as 2 x 2 v_mfma_f32_16x16x32_bf16 tiles. The
-// weights (at most 128 KB per layer) stay in L2, so operand fragments are
-// loaded straight into VGPRs, 16 bytes per lane per fragment. Epilogues fuse
-// the bias, GELU and its derivative, the transposed copies the next GEMM
-// needs, and split-K partials. Every sum that gradients or labels depend on
-// is formed in a fixed order (partials reduced in order, or exact
-// fixed-point atomics), so training is bit-reproducible.
+// Matrix products use v_mfma_f32_16x16x32_bf16. The weights (at most 128 KB
+// per layer) stay in L2, so their fragments are loaded straight into VGPRs,
+// 16 bytes per lane per fragment; activations are staged in LDS. Every sum
+// that gradients or labels depend on is formed in a fixed order (partials
+// reduced in order, or exact fixed-point atomics), so training is
+// bit-reproducible.
 
 #include "sur_device.h"
 #include "gelu_cdf_table.h"
@@ -20,6 +17,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
   uint32_t u = __float_as_uint(f);
@@ -32,68 +30,16 @@ __device__ __forceinline__ bf16x8 load8(const uint16_t *p) {
   return __builtin_bit_cast(bf16x8, v);
 }
 
-// Standard normal CDF Phi(z) = erfc(-z / sqrt 2) / 2 from the rational
-// approximation of Abramowitz & Stegun 7.1.26: for x >= 0,
-// erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),
-// t = 1 / (1 + p x), absolute error <= 1.5e-7 (far below the bf16 rounding
-// of every stored activation). Also returns e = exp(-z^2 / 2), which the
-// GELU derivative reuses.
-__device__ __forceinline__ float norm_cdf(float z, float &e) {
-  const float x = fabsf(z) * 0.70710678118654752f;
-  const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f, x, 1.0f));
-  float q = __builtin_fmaf(t, 1.061405429f, -1.453152027f);
-  q = __builtin_fmaf(t, q, 1.421413741f);
-  q = __builtin_fmaf(t, q, -0.284496736f);
-  q = __builtin_fmaf(t, q, 0.254829592f);
-  e = __builtin_amdgcn_exp2f(z * z * -0.72134752044448170f);  // exp(-z^2 / 2) = 2^(-z^2 log2(e) / 2)
-  const float lower = 0.5f * t * q * e;                       // Phi(-|z|)
-  return z >= 0.0f ? 1.0f - lower : lower;
-}
-
-// GELU(z) = z Phi(z) = z / 2 + H(z^2) / 2 with H(u) = sqrt(u) erf(sqrt(u / 2)),
-// an entire function of u: H / 2 is a degree-12 polynomial in
-// x = min(u / 12.5 - 1, 1), which covers |z| <= 5; beyond, erf(|z| / sqrt 2)
-// = 1 - O(6e-7) and H grows as |z|, added as max(|z| - 5, 0) / 2. The
-// coefficients and the FP32 error bound (|error| <= 3.4e-6 for all z) come
-// from gelu_poly.py beside this file. No transcendental and no branch:
-// 19 full-rate operations, where the rational form of erfc needs a
-// reciprocal and an exponential.
-__device__ __forceinline__ float gelu(float z) {
-  const float x = fminf(__builtin_fmaf(z * z, 0.08f, -1.0f), 1.0f);
-  float h = -0.012713938f;
-  h = __builtin_fmaf(h, x, 0.026097981f);
-  h = __builtin_fmaf(h, x, -0.011562989f);
-  h = __builtin_fmaf(h, x, 0.015651802f);
-  h = __builtin_fmaf(h, x, -0.05995361f);
-  h = __builtin_fmaf(h, x, 0.08401806f);
-  h = __builtin_fmaf(h, x, -0.08555572f);
-  h = __builtin_fmaf(h, x, 0.096760295f);
-  h = __builtin_fmaf(h, x, -0.112569965f);
-  h = __builtin_fmaf(h, x, 0.13914998f);
-  h = __builtin_fmaf(h, x, -0.23469144f);
-  h = __builtin_fmaf(h, x, 0.8883197f);
-  h = __builtin_fmaf(h, x, 1.7670473f);
-  h = __builtin_fmaf(0.5f, fmaxf(fabsf(z) - 5.0f, 0.0f), h);
-  return __builtin_fmaf(0.5f, z, h);
-}
-
 // GELU for the fused inference kernel: z Phi(z) with Phi linear between the
 // 1025 nodes of a table in LDS (gelu_table.py beside this file derives it
 // and bounds the error: |error| <= 5.3e-6 for all z, 2^-12 relative where
-// |GELU| > 0.01). Eight full-rate operations and one 8-byte LDS read, where
-// the polynomial takes nineteen; t = N (z >= 6) lands on the last node,
-// whose difference is 0, and a NaN converts to index 0.
+// |GELU| > 0.01). Eight full-rate operations and one 8-byte LDS read;
+// t = N (z >= 6) lands on the last node, whose difference is 0, and a NaN
+// converts to index 0.
 __device__ __forceinline__ float gelu_table(float z, const float2 *cdf) {
   const float t = __builtin_amdgcn_fmed3f(__builtin_fmaf(z, kCdfA, kCdfB), 0.0f, (float)kCdfN);
   const float2 e = cdf[(uint32_t)t];
   return z * __builtin_fmaf(__builtin_amdgcn_fractf(t), e.y, e.x);
-}
-
-// Its derivative Phi(z) + z phi(z), from the rational form above.
-__device__ __forceinline__ float gelu_grad(float z) {
-  float e;
-  const float cdf = norm_cdf(z, e);
-  return __builtin_fmaf(z * e, 0.39894228040143268f, cdf);
 }
 
 // Digamma for x > 0: recurrence psi(x) = psi(x + 1) - 1/x up to x >= 6, then
@@ -110,93 +56,140 @@ __device__ __forceinline__ float digamma(float x) {
   return r + logf(x) - 0.5f / x - t;
 }
 
-template <int EPI>
-__global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row0 = blockIdx.y * kTile + (wave >> 1) * 32;
-  const int col0 = blockIdx.x * kTile + (wave & 1) * 32;
-  const int kbeg = blockIdx.z * g.k_chunk;
-  const int kend = min(g.K, kbeg + g.k_chunk);
-  const int lr = lane & 15, lk = (lane >> 4) * 8;
-  f32x4 acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
-  const uint16_t *a0 = g.A + (int64_t)(row0 + lr) * g.lda + lk;
-  const uint16_t *a1 = a0 + 16 * g.lda;
-  const uint16_t *b0 = g.B + (int64_t)(col0 + lr) * g.ldb + lk;
-  const uint16_t *b1 = b0 + 16 * g.ldb;
-  // The operands of step k + 32 are loaded before the products of step k,
-  // so one step of loads is always in flight (the last step reloads its own
-  // operands, which stay in bounds).
-  bf16x8 va0 = load8(a0 + kbeg), va1 = load8(a1 + kbeg);
-  bf16x8 vb0 = load8(b0 + kbeg), vb1 = load8(b1 + kbeg);
-  for (int k = kbeg; k < kend; k += 32) {
-    const int kn = k + 32 < kend ? k + 32 : k;
-    const bf16x8 na0 = load8(a0 + kn), na1 = load8(a1 + kn);
-    const bf16x8 nb0 = load8(b0 + kn), nb1 = load8(b1 + kn);
-    acc00 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va0, vb0, acc00, 0, 0, 0);
-    acc01 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va0, vb1, acc01, 0, 0, 0);
-    acc10 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va1, vb0, acc10, 0, 0, 0);
-    acc11 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va1, vb1, acc11, 0, 0, 0);
-    va0 = na0, va1 = na1, vb0 = nb0, vb1 = nb1;
+// Workgroup barrier that orders LDS accesses only: global loads issued
+// before it stay in flight (the kernels that use it pass nothing between
+// wavefronts through global memory).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ bf16x8 lds_load8(const uint16_t *p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(p));
+}
+
+// Weight gradients of all five layers in one launch. Block (tile, slice) =
+// (blockIdx.x / splits, blockIdx.x % splits), the tiles of layer 0 first.
+// Slice s takes the minibatch's 32-row blocks s, s + splits, s + 2 splits,
+// ...; the row pass wrote block b from its workgroup b, and consecutive
+// workgroups are dispatched to the eight XCDs in turn, so with splits a
+// multiple of 8 a slice reads only blocks written on the XCD it runs on,
+// from that XCD's L2 where they are still resident.
+//
+// A tile of TM x TN: each 32-row step stages the A rows (TM x 32) and B rows
+// (TN x 32) in LDS (row stride 40 elements: the 16 rows a fragment read
+// touches fall on distinct banks), and each wavefront multiplies its
+// TM / 2 x TN / 2 quarter from there. The global loads run kWgradDepth steps
+// ahead in VGPRs; the LDS stage is double-buffered. Each block stores its
+// slice's partial product; the reduction adds the slices in order.
+constexpr int kWgradLd = 40;
+constexpr int kWgradDepth = 4;
+
+// acc[i][j] += A rows 16 i .. (from a) x B rows 16 j .. (from b) over one
+// 32-wide K step staged in LDS (a, b: this lane's fragment addresses).
+template <int MI, int NI>
+__device__ __forceinline__ void wgrad_products(f32x4 (&acc)[MI][NI], const uint16_t *a, const uint16_t *b) {
+  bf16x8 af[MI], bf[NI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i) af[i] = lds_load8(a + i * 16 * kWgradLd);
+#pragma unroll
+  for (int j = 0; j < NI; ++j) bf[j] = lds_load8(b + j * 16 * kWgradLd);
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+}
+
+template <int TM, int TN>
+__device__ __forceinline__ void wgrad_block(const WgradArgs &g, int l, int t, int s, uint16_t *stage) {
+  constexpr int L = (TM + TN) * 4 / 256;  // 16-byte chunks per thread per step
+  constexpr int kStage = (TM + TN) * kWgradLd;
+  constexpr int D = kWgradDepth, MI = TM / 32, NI = TN / 32;
+  static_assert((TM + TN) * 4 % 256 == 0, "whole chunks per thread");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wr = wave >> 1, wc = wave & 1;
+  const int n_in = in_dim(l), n_out = out_dim(l);
+  const int col_tiles = n_in / TN;
+  const int r0 = (t / col_tiles) * TM, c0 = (t % col_tiles) * TN;
+  const int n_blk = g.M / kTrainRows;
+  const int n = (n_blk - s + g.splits - 1) / g.splits;  // this slice's steps
+  // this thread's chunks: row c / 4 of the stage (A rows, then B rows), part c % 4
+  const uint16_t *src[L];
+  int dst[L];
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    const int c = tid + 256 * q, row = c >> 2, part = c & 3;
+    src[q] = (row < TM ? g.A[l] + (int64_t)(r0 + row) * g.M : g.B[l] + (int64_t)(c0 + row - TM) * g.M) + part * 8;
+    dst[q] = row * kWgradLd + part * 8;
   }
-  // Output layout of a 16 x 16 tile: lane holds rows 4 (lane / 16) + r,
-  // r = 0..3, of column lane % 16.
-  const f32x4 accs[4] = {acc00, acc01, acc10, acc11};
-  float csum[2] = {0.0f, 0.0f};  // kEpiGeluBwd: this lane's part of the column sums of the wave's 32 rows
+  f32x4 acc[MI][NI];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int i = t >> 1, j = t & 1;
-    const int col = col0 + j * 16 + lr;
-    const int rbase = row0 + i * 16 + (lane >> 4) * 4;
-    const f32x4 v = accs[t];
-    if (EPI == kEpiGelu) {
-      const float b = g.bias[col];
-      uint16_t h[4];
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float z = v[r] + b;
-        const int64_t idx = (int64_t)(rbase + r) * g.N + col;
-        if (g.Z) g.Z[idx] = z;
-        h[r] = f2bf(gelu(z));
-        g.H[idx] = h[r];
-      }
-      if (g.HT) {
-        const uint2 packed = make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
-        *reinterpret_cast<uint2 *>(g.HT + (int64_t)col * g.ldt + rbase) = packed;
-      }
-    } else if (EPI == kEpiGeluBwd) {
-      uint16_t h[4];
+    for (int j = 0; j < NI; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+  const int fr = (lane & 15) * kWgradLd + (lane >> 4) * 8;
+  // The ring is four named register sets, each step written out for its
+  // set, so every index is static and the sets stay in VGPRs.
+  static_assert(D == 4, "the ring below has four sets");
+  u32x4 ra[L], rb[L], rc[L], rd[L];  // native vectors: a uint4 struct would be copied through memory
+#define WGRAD_LOAD(R, J)                                                                \
+  {                                                                                     \
+    const int64_t k0_ = (int64_t)(s + (J) * g.splits) * kTrainRows;                     \
+    _Pragma("unroll") for (int q = 0; q < L; ++q) R[q] = *reinterpret_cast<const u32x4 *>(src[q] + k0_); \
+  }
+  // step j: its rows (in R) to LDS stage j & 1, the set reloaded with step
+  // j + D, then the products. Stage j & 1 was last read by step j - 2,
+  // which every wavefront finished before the barrier of step j - 1.
+#define WGRAD_STEP(R, J)                                                                \
+  {                                                                                     \
+    const int j_ = (J);                                                                 \
+    uint16_t *st_ = stage + (j_ & 1) * kStage;                                          \
+    _Pragma("unroll") for (int q = 0; q < L; ++q) *reinterpret_cast<u32x4 *>(st_ + dst[q]) = R[q]; \
+    if (j_ + D < n) WGRAD_LOAD(R, j_ + D);                                              \
+    lds_barrier();                                                                      \
+    wgrad_products<MI, NI>(acc, st_ + wr * (TM / 2) * kWgradLd + fr, st_ + (TM + wc * (TN / 2)) * kWgradLd + fr); \
+  }
+  if (0 < n) WGRAD_LOAD(ra, 0);
+  if (1 < n) WGRAD_LOAD(rb, 1);
+  if (2 < n) WGRAD_LOAD(rc, 2);
+  if (3 < n) WGRAD_LOAD(rd, 3);
+  // whole rounds of the ring, then the last n % D steps
+  int j0 = 0;
+  for (; j0 + D <= n; j0 += D) {
+    WGRAD_STEP(ra, j0);
+    WGRAD_STEP(rb, j0 + 1);
+    WGRAD_STEP(rc, j0 + 2);
+    WGRAD_STEP(rd, j0 + 3);
+  }
+  if (j0 < n) WGRAD_STEP(ra, j0);
+  if (j0 + 1 < n) WGRAD_STEP(rb, j0 + 1);
+  if (j0 + 2 < n) WGRAD_STEP(rc, j0 + 2);
+#undef WGRAD_STEP
+#undef WGRAD_LOAD
+  float *part = g.ws + (int64_t)g.splits * wb_offset(l) + (int64_t)s * n_out * n_in;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t idx = (int64_t)(rbase + r) * g.N + col;
-        h[r] = f2bf(v[r] * gelu_grad(g.Zin[idx]));
-        g.H[idx] = h[r];
-        csum[j] += __uint_as_float((uint32_t)h[r] << 16);
-      }
-      const uint2 packed = make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
-      *reinterpret_cast<uint2 *>(g.HT + (int64_t)col * g.ldt + rbase) = packed;
-    } else if (EPI == kEpiSplitK) {
-      // this K slice's partial product; a reduction in slice order follows
-      float *part = g.ws + (int64_t)blockIdx.z * g.M * g.N;
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) part[(int64_t)(rbase + r) * g.N + col] = v[r];
-    } else if (EPI == kEpiLinear) {
-      const float b = g.bias[col];
+    for (int jn = 0; jn < NI; ++jn) {
+      const int col = c0 + wc * (TN / 2) + jn * 16 + (lane & 15);
+      const int rbase = r0 + wr * (TM / 2) + i * 16 + (lane >> 4) * 4;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) g.out[(int64_t)(rbase + r) * g.N + col] = v[r] + b;
+      for (int r = 0; r < 4; ++r) part[(int64_t)(rbase + r) * n_in + col] = acc[i][jn][r];
     }
-  }
-  if (EPI == kEpiGeluBwd && g.col_part) {
-    // lanes l, l + 16, l + 32, l + 48 hold the same column: sum them into
-    // the column sum of the wave's 32 rows, stored for the block of rows
-    // (a reduction over the row blocks in order follows)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      float cs = csum[j];
-      cs += __shfl_xor(cs, 16, 64);
-      cs += __shfl_xor(cs, 32, 64);
-      if (lane < 16) g.col_part[(int64_t)(row0 / 32) * g.N + col0 + j * 16 + lane] = cs;
-    }
-  }
+}
+
+__global__ void __launch_bounds__(256) k_wgrad(const WgradArgs g) {
+  __shared__ __align__(16) uint16_t stage[2 * 256 * kWgradLd];
+  const int s = (int)(blockIdx.x % (unsigned)g.splits);
+  int t = (int)(blockIdx.x / (unsigned)g.splits), l = 0;
+  while (l + 1 < kLayers && t >= wgrad_tile_offset(l + 1)) ++l;
+  t -= wgrad_tile_offset(l);
+  if (l == 0)
+    wgrad_block<wgrad_tm(0), wgrad_tn(0)>(g, l, t, s, stage);
+  else if (l == kLayers - 1)
+    wgrad_block<wgrad_tm(kLayers - 1), wgrad_tn(kLayers - 1)>(g, l, t, s, stage);
+  else
+    wgrad_block<128, 128>(g, l, t, s, stage);
 }
 
 constexpr double kDelayFix = 1048576.0;     // 2^20 per ns
@@ -300,64 +293,33 @@ __global__ void k_features(const FeatureArgs f, int64_t n_rows) {
   if (f.r_out) f.r_out[t] = R;
 }
 
-// Poisson + gamma negative log-likelihood per row and its gradient with
-// respect to the three outputs (log mu / mu_base, log kappa, log theta/tau0).
-__global__ void __launch_bounds__(256) k_loss(const LossArgs l) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  double part = 0.0;
-  float bsum[3] = {0.0f, 0.0f, 0.0f};
-  if (m < l.M_pad) {
-    float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
-    if (m < l.M_real) {
-      const float *y = l.Y + (int64_t)m * kOutPad;
-      const float y1 = fminf(fmaxf(y[1], -8.0f), 8.0f), y2 = fminf(fmaxf(y[2], -8.0f), 8.0f);
-      const float mu = l.nph[m] * l.mu_base[m] * expf(y[0]);
-      const float kappa = expf(y1), theta = kTau0Ns * expf(y2);
-      const float k = l.k[m], nt = l.n_t[m], s1 = l.s1[m], s2 = l.s2[m];
-      const float log_mu = logf(mu);
-      const float pois = mu - (k > 0.0f ? k * log_mu : 0.0f);
-      const float gam = nt > 0.0f ? nt * (lgammaf(kappa) + kappa * logf(theta)) - (kappa - 1.0f) * s2 + s1 / theta
-                                  : 0.0f;
-      const float wt = l.w ? l.w[m] : 1.0f;
-      part = (double)wt * ((double)pois + (double)kTimeWeight * gam);
-      const float scale = wt * l.inv_norm;
-      g0 = (mu - k) * scale;
-      if (nt > 0.0f) {
-        g1 = kTimeWeight * kappa * (nt * (digamma(kappa) + logf(theta)) - s2) * scale;
-        g2 = kTimeWeight * (nt * kappa - s1 / theta) * scale;
-        if (y[1] != y1) g1 = 0.0f;  // clamped: no gradient through the clamp
-        if (y[2] != y2) g2 = 0.0f;
-      }
-    }
-    uint16_t *row = l.dY + (int64_t)m * kOutPad;
-    row[0] = f2bf(g0);
-    row[1] = f2bf(g1);
-    row[2] = f2bf(g2);
-    for (int q = kOutReal; q < kOutPad; ++q) row[q] = 0;
-    l.dYT[m] = f2bf(g0);
-    l.dYT[(int64_t)l.M_pad + m] = f2bf(g1);
-    l.dYT[2 * (int64_t)l.M_pad + m] = f2bf(g2);
-    for (int q = kOutReal; q < kOutPad; ++q) l.dYT[(int64_t)q * l.M_pad + m] = 0;
-    bsum[0] = __uint_as_float((uint32_t)row[0] << 16);
-    bsum[1] = __uint_as_float((uint32_t)row[1] << 16);
-    bsum[2] = __uint_as_float((uint32_t)row[2] << 16);
+// Poisson + gamma negative log-likelihood of one row (times its weight)
+// and its gradient with respect to the three outputs (log mu / mu_base,
+// log kappa, log theta/tau0), scaled by weight / count.
+struct RowLoss {
+  double part;
+  float g0, g1, g2;
+};
+__device__ __forceinline__ RowLoss row_loss(float y0, float y1_raw, float y2_raw, float mu_base, float nph,
+                                            float k, float nt, float s1, float s2, float wt, float inv_norm) {
+  RowLoss o{0.0, 0.0f, 0.0f, 0.0f};
+  const float y1 = fminf(fmaxf(y1_raw, -8.0f), 8.0f), y2 = fminf(fmaxf(y2_raw, -8.0f), 8.0f);
+  const float mu = nph * mu_base * expf(y0);
+  const float kappa = expf(y1), theta = kTau0Ns * expf(y2);
+  const float log_mu = logf(mu);
+  const float pois = mu - (k > 0.0f ? k * log_mu : 0.0f);
+  const float gam =
+      nt > 0.0f ? nt * (lgammaf(kappa) + kappa * logf(theta)) - (kappa - 1.0f) * s2 + s1 / theta : 0.0f;
+  o.part = (double)wt * ((double)pois + (double)kTimeWeight * gam);
+  const float scale = wt * inv_norm;
+  o.g0 = (mu - k) * scale;
+  if (nt > 0.0f) {
+    o.g1 = kTimeWeight * kappa * (nt * (digamma(kappa) + logf(theta)) - s2) * scale;
+    o.g2 = kTimeWeight * (nt * kappa - s1 / theta) * scale;
+    if (y1_raw != y1) o.g1 = 0.0f;  // clamped: no gradient through the clamp
+    if (y2_raw != y2) o.g2 = 0.0f;
   }
-  __shared__ double red[256];
-  __shared__ float bred[3][256];
-  red[threadIdx.x] = part;
-  for (int q = 0; q < 3; ++q) bred[q][threadIdx.x] = bsum[q];
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      red[threadIdx.x] += red[threadIdx.x + o];
-      for (int q = 0; q < 3; ++q) bred[q][threadIdx.x] += bred[q][threadIdx.x + o];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    l.loss_part[blockIdx.x] = red[0];
-    for (int q = 0; q < 3; ++q) l.bias_part[3 * blockIdx.x + q] = bred[q][0];
-  }
+  return o;
 }
 
 // Sum of part[i * stride] over i < n in a fixed order by one wavefront: lane
@@ -374,54 +336,73 @@ __device__ __forceinline__ T wave_ordered_sum(const T *part, int n, int64_t stri
   return sum;
 }
 
-// The workgroups' loss and output-bias-gradient partials, summed in a fixed
-// order: wavefront 0 the loss, wavefronts 1..3 the three bias entries.
-__global__ void __launch_bounds__(256) k_loss_reduce(const LossArgs l, int n_blocks) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (wave == 0) {
-    const double sum = wave_ordered_sum(l.loss_part, n_blocks, 1);
-    if (lane == 0) {
-      *l.loss_sum = sum;
-      if (l.loss_epoch) *l.loss_epoch += sum;
+// Stores gradient element i and, with adam, takes the Adam step (Kingma &
+// Ba, beta1 0.9, beta2 0.999, eps 1e-8, bias corrections c1, c2); returns
+// the parameter's new value.
+__device__ __forceinline__ float grad_step(const AdamArgs &a, int64_t i, float g) {
+  a.grad[i] = g;
+  float th = a.theta[i];
+  if (a.adam) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float mi = b1 * a.m[i] + (1.0f - b1) * g;
+    const float vi = b2 * a.v[i] + (1.0f - b2) * g * g;
+    a.m[i] = mi;
+    a.v[i] = vi;
+    th -= a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + eps);
+    a.theta[i] = th;
+  }
+  return th;
+}
+
+constexpr int kWeightBlocks = (int)((wb_count() / 4 + 255) / 256);
+constexpr int kBiasBlocks = kBiasCols / 4;
+static_assert(wb_count() % 4 == 0 && w_offset(1) % 4 == 0 && wb_offset(1) % 4 == 0,
+              "every layer's weights start on a 16-byte boundary");
+
+// Blocks [0, kWeightBlocks): four consecutive weight elements per thread
+// (of one row of one layer), their K-slice partials added in slice order,
+// then the step and the bf16 copies in both layouts. The next kBiasBlocks:
+// one bias element per wavefront, its row-block parts added by
+// wave_ordered_sum. The last block: the loss.
+__global__ void __launch_bounds__(256) k_reduce_adam(const AdamArgs a) {
+  const int bid = blockIdx.x;
+  if (bid < kWeightBlocks) {
+    const int64_t t = ((int64_t)bid * 256 + threadIdx.x) * 4;
+    if (t >= wb_count()) return;
+    int l = 0;
+    while (l + 1 < kLayers && t >= wb_offset(l + 1)) ++l;
+    const int64_t e = t - wb_offset(l);
+    const int n_in = in_dim(l), n_out = out_dim(l);
+    const int64_t n = (int64_t)n_out * n_in;
+    const float4 *p = reinterpret_cast<const float4 *>(a.ws + (int64_t)a.splits * wb_offset(l) + e);
+    float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int q = 0; q < a.splits; ++q) {
+      const float4 v = p[q * (n / 4)];
+      g.x += v.x, g.y += v.y, g.z += v.z, g.w += v.w;
     }
-  } else if (l.out_bias_grad) {
-    const float sum = wave_ordered_sum(l.bias_part + wave - 1, n_blocks, 3);
-    if (lane == 0) l.out_bias_grad[wave - 1] = sum;
-  }
-}
-
-// out[j] = sum over i < n_parts of part[i * stride + j], in order of i: one
-// thread per element (few parts, many elements: the split-K slices).
-__global__ void k_sum_parts(float *out, const float *part, int64_t n, int n_parts, int64_t stride) {
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    float sum = 0.0f;
-#pragma unroll 8
-    for (int i = 0; i < n_parts; ++i) sum += part[i * stride + j];
-    out[j] = sum;
-  }
-}
-
-// The same with one wavefront per element (many parts, few elements: the
-// per-32-row column sums of a bias gradient).
-__global__ void __launch_bounds__(256) k_sum_parts_wave(float *out, const float *part, int64_t n, int n_parts,
-                                                        int64_t stride) {
-  const int64_t j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= n) return;
-  const float sum = wave_ordered_sum(part + j, n_parts, stride);
-  if ((threadIdx.x & 63) == 0) out[j] = sum;
-}
-
-// Adam (Kingma & Ba) with bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t.
-__global__ void k_adam(float *theta, const float *grad, float *m, float *v, int64_t n, float lr, float c1,
-                       float c2) {
-  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float g = grad[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * g;
-    const float vi = b2 * v[i] + (1.0f - b2) * g * g;
-    m[i] = mi;
-    v[i] = vi;
-    theta[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    const int64_t i = w_offset(l) + e;
+    const float th[4] = {grad_step(a, i, g.x), grad_step(a, i + 1, g.y), grad_step(a, i + 2, g.z),
+                         grad_step(a, i + 3, g.w)};
+    if (a.adam) {
+      const uint16_t h[4] = {f2bf(th[0]), f2bf(th[1]), f2bf(th[2]), f2bf(th[3])};
+      *reinterpret_cast<uint2 *>(a.wb + t) = make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
+      const int64_t o = e / n_in, c = e % n_in;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) a.wt[wb_offset(l) + (c + k) * n_out + o] = h[k];
+    }
+  } else if (bid < kWeightBlocks + kBiasBlocks) {
+    const int j = (bid - kWeightBlocks) * 4 + (int)(threadIdx.x >> 6);
+    const float g = wave_ordered_sum(a.col_part + j, a.n_blocks, kBiasCols);
+    if ((threadIdx.x & 63) == 0) {
+      const int l = j < 4 * kHidden ? j / kHidden : 4, f = j < 4 * kHidden ? j % kHidden : j - 4 * kHidden;
+      grad_step(a, b_offset(l) + f, g);
+    }
+  } else if (threadIdx.x < 64) {
+    const double sum = wave_ordered_sum(a.loss_part, a.n_blocks, 1);
+    if (threadIdx.x == 0) {
+      *a.loss_sum = sum;
+      if (a.loss_epoch) *a.loss_epoch += sum;
+    }
   }
 }
 
@@ -509,9 +490,6 @@ __global__ void k_labels_finish(const unsigned long long *s1q, const unsigned lo
 // first output gives the expected hits, which go to the per-module sums with
 // one atomic per pair.
 
-__device__ __forceinline__ bf16x8 lds_load8(const uint16_t *p) {
-  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(p));
-}
 
 __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
   typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -632,6 +610,295 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   }
 }
 
+// ---------------------------------------------------------------------------
+// Training, row pass. A workgroup of eight wavefronts owns kTrainRows = 32
+// rows of the minibatch and keeps their activations in LDS through the
+// forward and the backward pass, computed transposed as in inference
+// (wavefront w: features 32 w .. + 32 of all 32 rows, 2 x 2 MFMA tiles; two
+// wavefronts per SIMD, so one's memory waits overlap the other's work):
+//   forward  H_l^T = GELU(W_l H_{l-1}^T + b_l), GELU and its derivative
+//            both from tables in LDS, the derivative kept in LDS as FP16
+//            for the backward pass;
+//   output   Y (first 16 outputs; three are used), then the loss and dY per
+//            row;
+//   backward dZ_{l-1}^T = (W_l^T dZ_l^T) * GELU'(Z_{l-1}), from dY down to
+//            dZ_0.
+// Each layer's weight fragments are loaded into VGPRs before the previous
+// layer's epilogue, so their L2 latency overlaps it; the barriers order LDS
+// only, so those loads stay in flight across them. After each layer the
+// workgroup copies the layer's output from LDS to a feature-major global
+// array, where the weight-gradient pass reads it; the copies of dY and dZ_l
+// also sum each column over the 32 rows (the bias-gradient parts).
+constexpr int kTrainThreads = 512;
+constexpr int kWaveFeat = kHidden / (kTrainThreads / 64);  // output features per wavefront
+constexpr int kFT = kWaveFeat / 16;                         // 16-feature MFMA tiles per wavefront
+
+__device__ __forceinline__ uint32_t pack_f16(float lo, float hi) {
+  typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  const f32x2 v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));  // round to nearest even
+}
+
+__device__ __forceinline__ float f16_half(uint32_t u, int hi) {
+  const uint16_t h = (uint16_t)(hi ? u >> 16 : u);
+  return (float)__builtin_bit_cast(_Float16, h);
+}
+
+__device__ __forceinline__ float bf_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// The wavefront's weight fragments of one layer: rows
+// kWaveFeat w + 16 ft + lane % 16 of W (LDA elements per row),
+// k = 32 s + 8 (lane / 16) .. + 8, s < S.
+struct WFrags {
+  bf16x8 v[kHidden / 32][kFT];
+};
+
+template <int S, int LDA>
+__device__ __forceinline__ void load_w(WFrags &w, const uint16_t *__restrict__ W, int lane, int wave) {
+  const uint16_t *wrow = W + (int64_t)(wave * kWaveFeat + (lane & 15)) * LDA + (lane >> 4) * 8;
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int ft = 0; ft < kFT; ++ft) w.v[s][ft] = load8(wrow + ft * 16 * LDA + s * 32);
+}
+
+// acc[ft][pt] = W[kWaveFeat w + 16 ft + .., k] . act[16 pt + .., k] over
+// k < 32 S: the wavefront's output features against the workgroup's 32
+// rows, the activations from LDS (ld_in elements per row).
+template <int S>
+__device__ __forceinline__ void rows_mma(f32x4 (&acc)[kFT][2], const WFrags &w, const uint16_t *s_in, int ld_in,
+                                         int lane) {
+  const uint16_t *hrow = s_in + (lane & 15) * ld_in + (lane >> 4) * 8;
+#pragma unroll
+  for (int ft = 0; ft < kFT; ++ft) acc[ft][0] = acc[ft][1] = f32x4{0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const bf16x8 h0 = lds_load8(hrow + s * 32), h1 = lds_load8(hrow + 16 * ld_in + s * 32);
+#pragma unroll
+    for (int ft = 0; ft < kFT; ++ft) {
+      acc[ft][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.v[s][ft], h0, acc[ft][0], 0, 0, 0);
+      acc[ft][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.v[s][ft], h1, acc[ft][1], 0, 0, 0);
+    }
+  }
+}
+
+// GELU(z) and GELU'(z) from the two tables interleaved in LDS as
+// (Phi_i, dPhi_i, G_i, dG_i): the same map and interpolation as
+// gelu_table(), so the forward activations equal inference's.
+__device__ __forceinline__ void gelu_and_grad(float z, const float4 *tab, float &h, float &g) {
+  const float t = __builtin_amdgcn_fmed3f(__builtin_fmaf(z, kCdfA, kCdfB), 0.0f, (float)kCdfN);
+  const float4 e = tab[(uint32_t)t];
+  const float f = __builtin_amdgcn_fractf(t);
+  h = z * __builtin_fmaf(f, e.y, e.x);
+  g = __builtin_fmaf(f, e.w, e.z);
+}
+
+// Forward epilogue: z = acc + b (the layer's biases from LDS); GELU(z) as
+// bf16 over the layer's input in s_act, GELU'(z) as FP16 into s_gp. A lane
+// holds features f0 .. f0 + 3 of one row, written as one 8-byte store each.
+__device__ __forceinline__ void fwd_epilogue(const f32x4 (&acc)[kFT][2], const float *s_b, const float4 *tab,
+                                             uint16_t *s_act, uint16_t *s_gp, int lane, int wave) {
+  const int l16 = lane & 15;
+#pragma unroll
+  for (int ft = 0; ft < kFT; ++ft) {
+    const int f0 = wave * kWaveFeat + ft * 16 + 4 * (lane >> 4);
+    const float4 b = *reinterpret_cast<const float4 *>(s_b + f0);
+#pragma unroll
+    for (int pt = 0; pt < 2; ++pt) {
+      const f32x4 v = acc[ft][pt];
+      float h[4], g[4];
+      gelu_and_grad(v[0] + b.x, tab, h[0], g[0]);
+      gelu_and_grad(v[1] + b.y, tab, h[1], g[1]);
+      gelu_and_grad(v[2] + b.z, tab, h[2], g[2]);
+      gelu_and_grad(v[3] + b.w, tab, h[3], g[3]);
+      const int o = (pt * 16 + l16) * kTrainLd + f0;
+      *reinterpret_cast<uint2 *>(s_act + o) = make_uint2(pack_bf16(h[0], h[1]), pack_bf16(h[2], h[3]));
+      *reinterpret_cast<uint2 *>(s_gp + o) = make_uint2(pack_f16(g[0], g[1]), pack_f16(g[2], g[3]));
+    }
+  }
+}
+
+// Backward epilogue: dZ = acc * GELU'(Z) (from s_gp), as bf16 into s_act.
+__device__ __forceinline__ void bwd_epilogue(const f32x4 (&acc)[kFT][2], const uint16_t *s_gp, uint16_t *s_act,
+                                             int lane, int wave) {
+  const int l16 = lane & 15;
+#pragma unroll
+  for (int ft = 0; ft < kFT; ++ft) {
+    const int f0 = wave * kWaveFeat + ft * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int pt = 0; pt < 2; ++pt) {
+      const f32x4 v = acc[ft][pt];
+      const int o = (pt * 16 + l16) * kTrainLd + f0;
+      const uint2 g = *reinterpret_cast<const uint2 *>(s_gp + o);
+      *reinterpret_cast<uint2 *>(s_act + o) =
+          make_uint2(pack_bf16(v[0] * f16_half(g.x, 0), v[1] * f16_half(g.x, 1)),
+                     pack_bf16(v[2] * f16_half(g.y, 0), v[3] * f16_half(g.y, 1)));
+    }
+  }
+}
+
+// Copies the workgroup's kTrainRows x n_cols bf16 tile in LDS (ld elements
+// per row) to the feature-major dst (column c at dst + c * M + i0). Four
+// consecutive lanes share a column, each taking 8 rows as one 16-byte
+// store, so a store instruction covers 16 columns' 64-byte runs. If col_sum
+// is not null it also gets each column's sum over the rows: each lane adds
+// its 8 rows in order, then the four lanes combine pairwise.
+__device__ __forceinline__ void store_columns(const uint16_t *s, int ld, int n_cols, uint16_t *dst, int64_t M,
+                                              int64_t i0, float *col_sum) {
+  static_assert(kTrainRows == 32, "four lanes of 8 rows per column");
+  const int part = threadIdx.x & 3;
+#pragma unroll
+  for (int c0 = 0; c0 < kHidden; c0 += kTrainThreads / 4) {
+    const int c = c0 + (int)(threadIdx.x >> 2);
+    if (c0 >= n_cols) break;  // uniform
+    const bool live = c < n_cols;
+    uint32_t w[4];
+    float sum = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 8; r += 2) {
+      const uint16_t lo = live ? s[(8 * part + r) * ld + c] : 0, hi = live ? s[(8 * part + r + 1) * ld + c] : 0;
+      w[r / 2] = lo | ((uint32_t)hi << 16);
+      sum += bf_to_f(lo);
+      sum += bf_to_f(hi);
+    }
+    if (live)
+      *reinterpret_cast<uint4 *>(dst + (int64_t)c * M + i0 + 8 * part) = make_uint4(w[0], w[1], w[2], w[3]);
+    if (col_sum) {
+      sum += __shfl_xor(sum, 1, 64);  // addition is commutative: both lanes get the same value
+      sum += __shfl_xor(sum, 2, 64);
+      if (live && part == 0) col_sum[c] = sum;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a) {
+  extern __shared__ __align__(16) uint16_t lds[];
+  float4 *s_tab = reinterpret_cast<float4 *>(lds);                      // kCdfN + 1 table entries
+  uint16_t *s_act = lds + (kCdfN + 1) * 8;                               // kTrainRows x kTrainLd bf16
+  uint16_t *s_gp = s_act + kTrainRows * kTrainLd;                        // 4 layers x kTrainRows x kTrainLd FP16
+  uint16_t *s_dy = s_gp + 4 * kTrainRows * kTrainLd;                     // kTrainRows x kDyLd bf16
+  float *s_lab = reinterpret_cast<float *>(s_dy + kTrainRows * kDyLd);   // kTrainRows x 8
+  double *s_loss = reinterpret_cast<double *>(s_lab + kTrainRows * 8);  // kTrainRows
+  float *s_bias = reinterpret_cast<float *>(s_loss + kTrainRows);        // 4 x kHidden hidden biases, kOutPad output
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int blk = blockIdx.x;
+  const int64_t i0 = (int64_t)blk * kTrainRows;
+  float *col_part = a.col_part + (int64_t)blk * kBiasCols;
+  constexpr int kLayerLds = kTrainRows * kTrainLd;
+  constexpr int kS = kHidden / 32, kS0 = kInPad / 32, kSOut = kOutPad / 32;
+  static_assert(kS0 <= kS && kSOut <= kS, "weight fragments fit the hidden layers' buffer");
+
+  WFrags w;
+  load_w<kS0, kInPad>(w, a.wb[0], lane, wave);
+  // the rows: thread -> (row, 16-byte chunk of its 64 features); chunks
+  // 0..6 also fetch one label each
+  if (tid < kTrainRows * 8) {
+    const int r = tid >> 3, c = tid & 7;
+    const int64_t i = i0 + r;
+    const bool real = i < a.count;
+    const uint64_t p = real ? (a.mul * (uint64_t)(a.first + i) + a.add) % a.P : 0;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (real) v = *reinterpret_cast<const uint4 *>(a.X + p * kInPad + c * 8);
+    *reinterpret_cast<uint4 *>(s_act + r * kTrainLd + c * 8) = v;
+    float x = 0.0f;
+    if (real) switch (c) {
+        case 0: x = a.mu_base[p]; break;
+        case 1: x = a.nph[p]; break;
+        case 2: x = a.k[p]; break;
+        case 3: x = a.n_t[p]; break;
+        case 4: x = a.s1[p]; break;
+        case 5: x = a.s2[p]; break;
+        case 6: x = a.w ? a.w[p] : 1.0f; break;
+        default: break;
+      }
+    s_lab[r * 8 + c] = x;
+  }
+  for (int q = tid; q < kTrainRows * kDyLd / 8; q += kTrainThreads)
+    reinterpret_cast<uint4 *>(s_dy)[q] = make_uint4(0, 0, 0, 0);
+  for (int q = tid; q <= kCdfN; q += kTrainThreads) {
+    const float2 cdf = kCdfTable[q], grad = kGeluGradTable[q];
+    s_tab[q] = make_float4(cdf.x, cdf.y, grad.x, grad.y);
+  }
+  // the biases live in LDS: a global load in an epilogue would make its
+  // wait cover the weight loads issued before it as well
+  for (int q = tid; q < 4 * kHidden + kOutPad; q += kTrainThreads)
+    s_bias[q] = q < 4 * kHidden ? a.b[q / kHidden][q % kHidden] : a.b[4][q - 4 * kHidden];
+  lds_barrier();
+  store_columns(s_act, kTrainLd, kInPad, a.XT, a.M, i0, nullptr);
+
+  // forward
+  f32x4 acc[kFT][2];
+  rows_mma<kS0>(acc, w, s_act, kTrainLd, lane);
+  load_w<kS, kHidden>(w, a.wb[1], lane, wave);
+  lds_barrier();  // every wavefront has read the layer's input
+  fwd_epilogue(acc, s_bias, s_tab, s_act, s_gp, lane, wave);
+  lds_barrier();  // the layer's output is complete
+  store_columns(s_act, kTrainLd, kHidden, a.HT[0], a.M, i0, nullptr);
+  // unrolled: straight-line code lets the compiler count the loads in
+  // flight exactly, so each product waits only for its own fragments
+#pragma unroll
+  for (int l = 1; l < 4; ++l) {
+    rows_mma<kS>(acc, w, s_act, kTrainLd, lane);
+    if (l < 3)
+      load_w<kS, kHidden>(w, a.wb[l + 1], lane, wave);
+    else
+      load_w<kSOut, kOutPad>(w, a.wt[4], lane, wave);  // the first backward product
+    lds_barrier();
+    fwd_epilogue(acc, s_bias + l * kHidden, s_tab, s_act, s_gp + l * kLayerLds, lane, wave);
+    lds_barrier();
+    store_columns(s_act, kTrainLd, kHidden, a.HT[l], a.M, i0, nullptr);
+  }
+
+  // output layer (outputs 0..15 of W4) for rows 16 w .. + 16, w = 0, 1; lane
+  // l < 16 then holds outputs 0..3 of row 16 w + l and takes its loss
+  if (wave < 2) {
+    const int l16 = lane & 15, kq = (lane >> 4) * 8;
+    const uint16_t *wrow = a.wb[4] + (int64_t)l16 * kHidden + kq;
+    const uint16_t *hrow = s_act + (wave * 16 + l16) * kTrainLd + kq;
+    bf16x8 wa[kS];
+#pragma unroll
+    for (int s = 0; s < kS; ++s) wa[s] = load8(wrow + s * 32);
+    f32x4 o = {0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < kS; ++s)
+      o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], lds_load8(hrow + s * 32), o, 0, 0, 0);
+    if (lane < 16) {
+      const int r = wave * 16 + lane;
+      const float *L = s_lab + r * 8;
+      RowLoss q{0.0, 0.0f, 0.0f, 0.0f};
+      if (i0 + r < a.count)
+        q = row_loss(o[0] + s_bias[4 * kHidden], o[1] + s_bias[4 * kHidden + 1], o[2] + s_bias[4 * kHidden + 2],
+                     L[0], L[1], L[2], L[3], L[4], L[5], L[6], a.inv_norm);
+      s_loss[r] = q.part;
+      *reinterpret_cast<uint2 *>(s_dy + r * kDyLd) = make_uint2(pack_bf16(q.g0, q.g1), pack_bf16(q.g2, 0.0f));
+    }
+  }
+  lds_barrier();
+  if (tid == 0) {
+    double sum = 0.0;
+    for (int r = 0; r < kTrainRows; ++r) sum += s_loss[r];
+    a.loss_part[blk] = sum;
+  }
+  store_columns(s_dy, kDyLd, kOutPad, a.dYT, a.M, i0, col_part + 4 * kHidden);
+
+  // backward; every read of H_3 in s_act happened before the barrier above
+  rows_mma<kSOut>(acc, w, s_dy, kDyLd, lane);  // dH_3^T = W_4^T dY^T
+  load_w<kS, kHidden>(w, a.wt[3], lane, wave);
+  bwd_epilogue(acc, s_gp + 3 * kLayerLds, s_act, lane, wave);
+  lds_barrier();
+  store_columns(s_act, kTrainLd, kHidden, a.dZT[3], a.M, i0, col_part + 3 * kHidden);
+#pragma unroll
+  for (int l = 3; l >= 1; --l) {
+    rows_mma<kS>(acc, w, s_act, kTrainLd, lane);  // dH_{l-1}^T = W_l^T dZ_l^T
+    if (l > 1) load_w<kS, kHidden>(w, a.wt[l - 1], lane, wave);
+    lds_barrier();
+    bwd_epilogue(acc, s_gp + (l - 1) * kLayerLds, s_act, lane, wave);
+    lds_barrier();
+    store_columns(s_act, kTrainLd, kHidden, a.dZT[l - 1], a.M, i0, col_part + (l - 1) * kHidden);
+  }
+}
+
 __global__ void k_zero_u64(unsigned long long *p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0;
@@ -641,30 +908,30 @@ int blocks_for(int64_t n, int threads) { return (int)((n + threads - 1) / thread
 
 }  // namespace
 
-hipError_t launch_sum_parts(float *out, const float *part, int64_t n, int n_parts, int64_t stride, hipStream_t s) {
-  if (n_parts > 32 && n <= 65536)
-    hipLaunchKernelGGL(k_sum_parts_wave, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, out, part, n, n_parts, stride);
-  else
-    hipLaunchKernelGGL(k_sum_parts, dim3(min(blocks_for(n, 256), 2048)), dim3(256), 0, s, out, part, n, n_parts,
-                       stride);
+size_t train_lds_bytes() {
+  return sizeof(float4) * (kCdfN + 1) + sizeof(uint16_t) * (5 * kTrainRows * kTrainLd + kTrainRows * kDyLd) +
+         sizeof(float) * kTrainRows * 8 + sizeof(double) * kTrainRows + sizeof(float) * (4 * kHidden + kOutPad);
+}
+
+hipError_t launch_train_rows(const TrainArgs &a, hipStream_t s) {
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_train_rows),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     static_cast<int>(train_lds_bytes()));
+  if (attr != hipSuccess) return attr;
+  if (a.M <= 0 || a.M % 64 != 0 || a.count > a.M) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_train_rows, dim3((unsigned)(a.M / kTrainRows)), dim3(kTrainThreads), train_lds_bytes(), s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_gemm(int epi, const GemmArgs &g, int splits, hipStream_t s) {
-  const dim3 grid(g.N / kTile, g.M / kTile, splits);
-  switch (epi) {
-    case kEpiGelu: hipLaunchKernelGGL(k_gemm<kEpiGelu>, grid, dim3(256), 0, s, g); break;
-    case kEpiGeluBwd: hipLaunchKernelGGL(k_gemm<kEpiGeluBwd>, grid, dim3(256), 0, s, g); break;
-    case kEpiSplitK: hipLaunchKernelGGL(k_gemm<kEpiSplitK>, grid, dim3(256), 0, s, g); break;
-    case kEpiLinear: hipLaunchKernelGGL(k_gemm<kEpiLinear>, grid, dim3(256), 0, s, g); break;
-  }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (epi == kEpiSplitK)
-    return launch_sum_parts(g.out, g.ws, (int64_t)g.M * g.N, splits, (int64_t)g.M * g.N, s);
-  if (epi == kEpiGeluBwd && g.col_part)
-    return launch_sum_parts(g.col_sums, g.col_part, g.N, g.M / 32, g.N, s);
-  return hipSuccess;
+hipError_t launch_wgrad(const WgradArgs &g, hipStream_t s) {
+  if (g.M <= 0 || g.M % kTrainRows != 0 || g.splits <= 0 || g.splits > g.M / kTrainRows) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_wgrad, dim3((unsigned)(wgrad_tile_offset(kLayers) * g.splits)), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_adam(const AdamArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_adam, dim3(kWeightBlocks + kBiasBlocks + 1), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 size_t fused_lds_bytes() {
@@ -688,63 +955,9 @@ hipError_t launch_features(const FeatureArgs &f, hipStream_t s) {
   return hipGetLastError();
 }
 
-int loss_blocks(int M_pad) { return blocks_for(M_pad, 256); }
-
-hipError_t launch_loss(const LossArgs &l, hipStream_t s) {
-  const int blocks = loss_blocks(l.M_pad);
-  hipLaunchKernelGGL(k_loss, dim3(blocks), dim3(256), 0, s, l);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, s, l, blocks);
-  return hipGetLastError();
-}
-
 hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_u64, dim3(min(blocks_for(n, 256), 4096)), dim3(256), 0, s, p, n);
-  return hipGetLastError();
-}
-
-// One thread per (batch row, feature column); columns 64..69 carry the labels.
-__global__ void __launch_bounds__(256) k_gather(const GatherArgs g) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t i = t / 72, c = t % 72;
-  if (i >= g.M) return;
-  const bool real = i < g.count;
-  const uint64_t r = (uint64_t)(g.first + i);
-  const uint64_t p = real ? (g.mul * r + g.add) % g.P : 0;
-  if (c < kInPad) {
-    const uint16_t v = real ? g.X[p * kInPad + c] : (uint16_t)0;
-    g.gX[i * kInPad + c] = v;
-    g.gXT[c * (int64_t)g.M + i] = v;
-    return;
-  }
-  const float *src;
-  float *dst;
-  switch (c - kInPad) {
-    case 0: src = g.mu_base, dst = g.g_mu_base; break;
-    case 1: src = g.nph, dst = g.g_nph; break;
-    case 2: src = g.k, dst = g.g_k; break;
-    case 3: src = g.n_t, dst = g.g_n_t; break;
-    case 4: src = g.s1, dst = g.g_s1; break;
-    case 5: src = g.s2, dst = g.g_s2; break;
-    case 6:
-      if (!g.w) return;
-      src = g.w, dst = g.g_w;
-      break;
-    default: return;
-  }
-  dst[i] = real ? src[p] : 0.0f;
-}
-
-hipError_t launch_gather(const GatherArgs &g, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather, dim3(blocks_for((int64_t)g.M * 72, 256)), dim3(256), 0, s, g);
-  return hipGetLastError();
-}
-
-hipError_t launch_adam(float *theta, const float *grad, float *m, float *v, int64_t n, float lr, float c1,
-                       float c2, hipStream_t s) {
-  hipLaunchKernelGGL(k_adam, dim3(min(blocks_for(n, 256), 1024)), dim3(256), 0, s, theta, grad, m, v, n, lr, c1, c2);
   return hipGetLastError();
 }
 

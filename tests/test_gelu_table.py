@@ -1,9 +1,11 @@
-"""The table GELU of the fused inference kernel: the table compiled into
-sur_kernels.hip (gelu_cdf_table.h) is the one gelu_table.py derives, its
-nodes hold the standard normal CDF to float32 rounding, and the kernel's FP32
-interpolation stays within 5.3e-6 of GELU(z) = z Phi(z) (scipy's erf) for
-every z, and within 2^-12 relative where |GELU| > 0.01 (an eighth of the
-bf16 rounding the stored activation then takes)."""
+"""The table GELU of the surrogate kernels: the tables compiled into
+sur_kernels.hip (gelu_cdf_table.h) are the ones gelu_table.py derives, their
+nodes hold the standard normal CDF and the GELU derivative to float32
+rounding, the kernel's FP32 interpolation stays within 5.3e-6 of
+GELU(z) = z Phi(z) (scipy's erf) for every z, and within 2^-12 relative
+where |GELU| > 0.01 (an eighth of the bf16 rounding the stored activation
+then takes), and the derivative's within 1.4e-5 of Phi(z) + z phi(z) (a
+seventeenth of the FP16 rounding it is then stored with)."""
 import importlib.util
 import os
 import re
@@ -22,19 +24,27 @@ def load_generator():
     return mod
 
 
-def compiled_table():
+def compiled_tables():
     src = open(os.path.join(CSRC, "gelu_cdf_table.h")).read()
-    pairs = re.findall(r"\{(-?[0-9.e+-]+)f, (-?[0-9.e+-]+)f\}", src)
+    cdf_src, grad_src = src.split("kGeluGradTable")
+    pat = r"\{(-?[0-9.e+-]+)f, (-?[0-9.e+-]+)f\}"
     a = float(re.search(r"kCdfA = ([0-9.e+-]+)f", src).group(1))
     b = float(re.search(r"kCdfB = ([0-9.e+-]+)f", src).group(1))
-    return np.array(pairs, np.float64).astype(np.float32), np.float32(a), np.float32(b)
+    return (np.array(re.findall(pat, cdf_src), np.float64).astype(np.float32),
+            np.array(re.findall(pat, grad_src), np.float64).astype(np.float32), np.float32(a), np.float32(b))
+
+
+def compiled_table():
+    tab, _, a, b = compiled_tables()
+    return tab, a, b
 
 
 def test_compiled_table_is_the_generated_one():
     g = load_generator()
-    tab, a, b = compiled_table()
-    assert tab.shape == (g.N + 1, 2)
+    tab, grad, a, b = compiled_tables()
+    assert tab.shape == (g.N + 1, 2) and grad.shape == (g.N + 1, 2)
     assert np.array_equal(tab, g.table())
+    assert np.array_equal(grad, g.grad_table())
     assert (a, b) == g.mapping()
 
 
@@ -57,3 +67,17 @@ def test_fp32_interpolation_error_bound():
     assert err.max() <= 5.3e-6
     big = np.abs(exact) > 1e-2
     assert (err[big] / np.abs(exact[big])).max() < 2.0 ** -12
+
+
+def test_derivative_table():
+    g = load_generator()
+    _, grad, a, b = compiled_tables()
+    zn = (np.arange(g.N + 1) - np.float64(b)) / np.float64(a)
+    exact_n = 0.5 * special.erfc(-zn / np.sqrt(2.0)) + zn * np.exp(-0.5 * zn * zn) / np.sqrt(2.0 * np.pi)
+    assert np.allclose(grad[:, 0], exact_n, rtol=2 ** -23, atol=1e-30)
+    assert grad[-1, 1] == 0.0
+    z = np.concatenate([np.linspace(-12.0, 12.0, 2_400_001), [-6.0, 6.0, 0.0, -0.7518, 0.8025]])
+    zd = z.astype(np.float32).astype(np.float64)
+    exact = 0.5 * special.erfc(-zd / np.sqrt(2.0)) + zd * np.exp(-0.5 * zd * zd) / np.sqrt(2.0 * np.pi)
+    err = np.abs(g.interp_f32(z, grad).astype(np.float64) - exact)
+    assert err.max() <= 1.4e-5
