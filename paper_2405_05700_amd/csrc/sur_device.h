@@ -29,7 +29,15 @@ __host__ __device__ constexpr int64_t w_offset(int l) {
 }
 __host__ __device__ constexpr int64_t b_offset(int l) { return w_offset(l) + (int64_t)out_dim(l) * in_dim(l); }
 __host__ __device__ constexpr int64_t param_count() { return w_offset(kLayers); }
-// bf16 weight copies: W (out x in) and W^T (in x out), layer after layer.
+// bf16 weight copies: W (out x in) and W^T (in x out), layer after layer,
+// each matrix tile-major: the 16 x 32 tile (rows 16 t .., columns 32 s ..)
+// of a matrix with K columns is 512 elements at (t (K / 32) + s) 512,
+// lane-major inside (lane l: row l % 16, columns 8 (l / 16) .. + 8), the
+// operand layout of v_mfma_f32_16x16x32_bf16. A wavefront's fragment load
+// then reads 1 KB contiguous: whole cache lines.
+__host__ __device__ constexpr int64_t frag_offset(int r, int k, int K) {
+  return ((int64_t)(r / 16) * (K / 32) + k / 32) * 512 + ((r % 16) + 16 * ((k % 32) / 8)) * 8 + k % 8;
+}
 __host__ __device__ constexpr int64_t wb_offset(int l) {
   int64_t o = 0;
   for (int j = 0; j < l; ++j) o += (int64_t)out_dim(j) * in_dim(j);
@@ -129,8 +137,8 @@ struct TrainArgs {
   int64_t first;
   int count, M;                    // real rows; M = count rounded up to a multiple of 64
   float inv_norm;                  // 1 / count
-  const uint16_t *wb[kLayers];     // bf16 W (out x in)
-  const uint16_t *wt[kLayers];     // bf16 W^T (in x out)
+  const uint16_t *wb[kLayers];     // bf16 W (out x in), tile-major (frag_offset)
+  const uint16_t *wt[kLayers];     // bf16 W^T (in x out), tile-major
   const float *b[kLayers];
   uint16_t *XT, *HT[4], *dYT, *dZT[4];  // bf16, feature-major with the minibatch row contiguous (ld M)
   float *col_part;                 // (M / kTrainRows) x kBiasCols
@@ -167,7 +175,7 @@ constexpr int kFusedRows = 128;
 constexpr int kFusedLd = kHidden + 8;  // LDS row stride of the activations (bf16); the pad spreads rows over banks
 struct FusedArgs {
   FeatureArgs f;                 // the pair set (its output pointers are unused)
-  const uint16_t *w[kLayers];    // bf16 weights, out x in
+  const uint16_t *w[kLayers];    // bf16 weights, out x in, tile-major (frag_offset)
   const float *b[kLayers];       // biases
   double *dom_sums;              // += expected hits per module (atomically: the last bits vary), may be null
   float *pair_mu;                // expected hits of pair first_pair + i at i, may be null

@@ -385,10 +385,11 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const AdamArgs a) {
                          grad_step(a, i + 3, g.w)};
     if (a.adam) {
       const uint16_t h[4] = {f2bf(th[0]), f2bf(th[1]), f2bf(th[2]), f2bf(th[3])};
-      *reinterpret_cast<uint2 *>(a.wb + t) = make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
-      const int64_t o = e / n_in, c = e % n_in;
+      const int o = (int)(e / n_in), c = (int)(e % n_in);  // c % 4 == 0: the four share one lane's 8 columns
+      *reinterpret_cast<uint2 *>(a.wb + wb_offset(l) + frag_offset(o, c, n_in)) =
+          make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
 #pragma unroll
-      for (int k = 0; k < 4; ++k) a.wt[wb_offset(l) + (c + k) * n_out + o] = h[k];
+      for (int k = 0; k < 4; ++k) a.wt[wb_offset(l) + frag_offset(c + k, o, n_out)] = h[k];
     }
   } else if (bid < kWeightBlocks + kBiasBlocks) {
     const int j = (bid - kWeightBlocks) * 4 + (int)(threadIdx.x >> 6);
@@ -406,7 +407,8 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const AdamArgs a) {
   }
 }
 
-// bf16 copies of every weight matrix: W (out x in) and W^T (in x out).
+// bf16 copies of every weight matrix: W (out x in) and W^T (in x out),
+// tile-major.
 __global__ void k_pack_weights(const float *theta, uint16_t *wb, uint16_t *wt) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= wb_count()) return;
@@ -416,8 +418,8 @@ __global__ void k_pack_weights(const float *theta, uint16_t *wb, uint16_t *wt) {
   const int n_in = in_dim(l), n_out = out_dim(l);
   const int o = (int)(e / n_in), i = (int)(e % n_in);
   const uint16_t h = f2bf(theta[w_offset(l) + e]);
-  wb[t] = h;
-  wt[wb_offset(l) + (int64_t)i * n_out + o] = h;
+  wb[wb_offset(l) + frag_offset(o, i, n_in)] = h;
+  wt[wb_offset(l) + frag_offset(i, o, n_out)] = h;
 }
 
 __global__ void k_zero_f32(float *p, int64_t n) {
@@ -504,7 +506,7 @@ __device__ __forceinline__ void fused_hidden_layer(uint16_t *lds_h, const uint16
                                                    int wave) {
   const int fg = wave;
   const int l16 = lane & 15, kq = (lane >> 4) * 8;
-  const uint16_t *wrow = w + (int64_t)(fg * 64 + l16) * LDW + kq;
+  const uint16_t *wfrag = w + lane * 8;  // + 512 (tile index): this lane's 16 bytes of a tile
   const uint16_t *hrow = lds_h + l16 * kFusedLd + kq;
   f32x4 acc[4][8];
 #pragma unroll
@@ -515,7 +517,7 @@ __device__ __forceinline__ void fused_hidden_layer(uint16_t *lds_h, const uint16
   for (int k = 0; k < K; k += 32) {
     bf16x8 wa[4], hb[8];
 #pragma unroll
-    for (int ft = 0; ft < 4; ++ft) wa[ft] = load8(wrow + ft * 16 * LDW + k);
+    for (int ft = 0; ft < 4; ++ft) wa[ft] = load8(wfrag + ((fg * 4 + ft) * (LDW / 32) + k / 32) * 512);
 #pragma unroll
     for (int pt = 0; pt < 8; ++pt) hb[pt] = lds_load8(hrow + pt * 16 * kFusedLd + k);
 #pragma unroll
@@ -584,13 +586,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 
   // output layer, first output only: W4 rows 0..15 against pair tiles 2w and 2w + 1
   const int l16 = lane & 15, kq = (lane >> 4) * 8;
-  const uint16_t *wrow = a.w[4] + (int64_t)l16 * kHidden + kq;
+  const uint16_t *wfrag = a.w[4] + lane * 8;  // tile 0: rows 0..15
   const uint16_t *h0 = lds_h + (2 * wave * 16 + l16) * kFusedLd + kq;
   const uint16_t *h1 = h0 + 16 * kFusedLd;
   f32x4 o0 = {0, 0, 0, 0}, o1 = o0;
 #pragma unroll
   for (int k = 0; k < kHidden; k += 32) {
-    const bf16x8 wa = load8(wrow + k);
+    const bf16x8 wa = load8(wfrag + (k / 32) * 512);
     o0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, lds_load8(h0 + k), o0, 0, 0, 0);
     o1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, lds_load8(h1 + k), o1, 0, 0, 0);
   }
@@ -656,11 +658,11 @@ struct WFrags {
 
 template <int S, int LDA>
 __device__ __forceinline__ void load_w(WFrags &w, const uint16_t *__restrict__ W, int lane, int wave) {
-  const uint16_t *wrow = W + (int64_t)(wave * kWaveFeat + (lane & 15)) * LDA + (lane >> 4) * 8;
+  const uint16_t *wfrag = W + lane * 8;  // + 512 (tile index): this lane's 16 bytes of a tile
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
-    for (int ft = 0; ft < kFT; ++ft) w.v[s][ft] = load8(wrow + ft * 16 * LDA + s * 32);
+    for (int ft = 0; ft < kFT; ++ft) w.v[s][ft] = load8(wfrag + ((wave * kFT + ft) * (LDA / 32) + s) * 512);
 }
 
 // acc[ft][pt] = W[kWaveFeat w + 16 ft + .., k] . act[16 pt + .., k] over
@@ -789,8 +791,10 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
   constexpr int kS = kHidden / 32, kS0 = kInPad / 32, kSOut = kOutPad / 32;
   static_assert(kS0 <= kS && kSOut <= kS, "weight fragments fit the hidden layers' buffer");
 
-  WFrags w;
-  load_w<kS0, kInPad>(w, a.wb[0], lane, wave);
+  // two fragment sets: each layer's weights are loaded two layers ahead
+  WFrags fa, fb;
+  load_w<kS0, kInPad>(fa, a.wb[0], lane, wave);
+  load_w<kS, kHidden>(fb, a.wb[1], lane, wave);
   // the rows: thread -> (row, 16-byte chunk of its 64 features); chunks
   // 0..6 also fetch one label each
   if (tid < kTrainRows * 8) {
@@ -829,36 +833,40 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
 
   // forward
   f32x4 acc[kFT][2];
-  rows_mma<kS0>(acc, w, s_act, kTrainLd, lane);
-  load_w<kS, kHidden>(w, a.wb[1], lane, wave);
+  rows_mma<kS0>(acc, fa, s_act, kTrainLd, lane);
+  load_w<kS, kHidden>(fa, a.wb[2], lane, wave);
   lds_barrier();  // every wavefront has read the layer's input
   fwd_epilogue(acc, s_bias, s_tab, s_act, s_gp, lane, wave);
   lds_barrier();  // the layer's output is complete
   store_columns(s_act, kTrainLd, kHidden, a.HT[0], a.M, i0, nullptr);
-  // unrolled: straight-line code lets the compiler count the loads in
-  // flight exactly, so each product waits only for its own fragments
-#pragma unroll
-  for (int l = 1; l < 4; ++l) {
-    rows_mma<kS>(acc, w, s_act, kTrainLd, lane);
-    if (l < 3)
-      load_w<kS, kHidden>(w, a.wb[l + 1], lane, wave);
-    else
-      load_w<kSOut, kOutPad>(w, a.wt[4], lane, wave);  // the first backward product
-    lds_barrier();
-    fwd_epilogue(acc, s_bias + l * kHidden, s_tab, s_act, s_gp + l * kLayerLds, lane, wave);
-    lds_barrier();
-    store_columns(s_act, kTrainLd, kHidden, a.HT[l], a.M, i0, nullptr);
-  }
+  rows_mma<kS>(acc, fb, s_act, kTrainLd, lane);
+  load_w<kS, kHidden>(fb, a.wb[3], lane, wave);
+  lds_barrier();
+  fwd_epilogue(acc, s_bias + kHidden, s_tab, s_act, s_gp + kLayerLds, lane, wave);
+  lds_barrier();
+  store_columns(s_act, kTrainLd, kHidden, a.HT[1], a.M, i0, nullptr);
+  rows_mma<kS>(acc, fa, s_act, kTrainLd, lane);
+  load_w<kSOut, kOutPad>(fa, a.wt[4], lane, wave);  // the first backward product
+  lds_barrier();
+  fwd_epilogue(acc, s_bias + 2 * kHidden, s_tab, s_act, s_gp + 2 * kLayerLds, lane, wave);
+  lds_barrier();
+  store_columns(s_act, kTrainLd, kHidden, a.HT[2], a.M, i0, nullptr);
+  rows_mma<kS>(acc, fb, s_act, kTrainLd, lane);
+  load_w<kS, kHidden>(fb, a.wt[3], lane, wave);
+  lds_barrier();
+  fwd_epilogue(acc, s_bias + 3 * kHidden, s_tab, s_act, s_gp + 3 * kLayerLds, lane, wave);
+  lds_barrier();
+  store_columns(s_act, kTrainLd, kHidden, a.HT[3], a.M, i0, nullptr);
 
   // output layer (outputs 0..15 of W4) for rows 16 w .. + 16, w = 0, 1; lane
   // l < 16 then holds outputs 0..3 of row 16 w + l and takes its loss
   if (wave < 2) {
     const int l16 = lane & 15, kq = (lane >> 4) * 8;
-    const uint16_t *wrow = a.wb[4] + (int64_t)l16 * kHidden + kq;
+    const uint16_t *wfrag = a.wb[4] + lane * 8;  // tile 0: rows 0..15
     const uint16_t *hrow = s_act + (wave * 16 + l16) * kTrainLd + kq;
     bf16x8 wa[kS];
 #pragma unroll
-    for (int s = 0; s < kS; ++s) wa[s] = load8(wrow + s * 32);
+    for (int s = 0; s < kS; ++s) wa[s] = load8(wfrag + s * 512);
     f32x4 o = {0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < kS; ++s)
@@ -875,28 +883,37 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
     }
   }
   lds_barrier();
-  if (tid == 0) {
-    double sum = 0.0;
-    for (int r = 0; r < kTrainRows; ++r) sum += s_loss[r];
-    a.loss_part[blk] = sum;
+  if (wave == 0) {  // the rows' losses summed by a fixed butterfly over lanes 0..31
+    static_assert(kTrainRows == 32, "one loss per lane of half a wavefront");
+    double sum = lane < kTrainRows ? s_loss[lane] : 0.0;
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    if (lane == 0) a.loss_part[blk] = sum;
   }
   store_columns(s_dy, kDyLd, kOutPad, a.dYT, a.M, i0, col_part + 4 * kHidden);
 
   // backward; every read of H_3 in s_act happened before the barrier above
-  rows_mma<kSOut>(acc, w, s_dy, kDyLd, lane);  // dH_3^T = W_4^T dY^T
-  load_w<kS, kHidden>(w, a.wt[3], lane, wave);
+  rows_mma<kSOut>(acc, fa, s_dy, kDyLd, lane);  // dH_3^T = W_4^T dY^T
+  load_w<kS, kHidden>(fa, a.wt[2], lane, wave);
   bwd_epilogue(acc, s_gp + 3 * kLayerLds, s_act, lane, wave);
   lds_barrier();
   store_columns(s_act, kTrainLd, kHidden, a.dZT[3], a.M, i0, col_part + 3 * kHidden);
-#pragma unroll
-  for (int l = 3; l >= 1; --l) {
-    rows_mma<kS>(acc, w, s_act, kTrainLd, lane);  // dH_{l-1}^T = W_l^T dZ_l^T
-    if (l > 1) load_w<kS, kHidden>(w, a.wt[l - 1], lane, wave);
-    lds_barrier();
-    bwd_epilogue(acc, s_gp + (l - 1) * kLayerLds, s_act, lane, wave);
-    lds_barrier();
-    store_columns(s_act, kTrainLd, kHidden, a.dZT[l - 1], a.M, i0, col_part + (l - 1) * kHidden);
-  }
+  rows_mma<kS>(acc, fb, s_act, kTrainLd, lane);  // dH_2^T = W_3^T dZ_3^T
+  load_w<kS, kHidden>(fb, a.wt[1], lane, wave);
+  lds_barrier();
+  bwd_epilogue(acc, s_gp + 2 * kLayerLds, s_act, lane, wave);
+  lds_barrier();
+  store_columns(s_act, kTrainLd, kHidden, a.dZT[2], a.M, i0, col_part + 2 * kHidden);
+  rows_mma<kS>(acc, fa, s_act, kTrainLd, lane);  // dH_1^T = W_2^T dZ_2^T
+  lds_barrier();
+  bwd_epilogue(acc, s_gp + kLayerLds, s_act, lane, wave);
+  lds_barrier();
+  store_columns(s_act, kTrainLd, kHidden, a.dZT[1], a.M, i0, col_part + kHidden);
+  rows_mma<kS>(acc, fb, s_act, kTrainLd, lane);  // dH_0^T = W_1^T dZ_1^T
+  lds_barrier();
+  bwd_epilogue(acc, s_gp, s_act, lane, wave);
+  lds_barrier();
+  store_columns(s_act, kTrainLd, kHidden, a.dZT[0], a.M, i0, col_part);
 }
 
 __global__ void k_zero_u64(unsigned long long *p, int64_t n) {
