@@ -791,43 +791,54 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
   constexpr int kS = kHidden / 32, kS0 = kInPad / 32, kSOut = kOutPad / 32;
   static_assert(kS0 <= kS && kSOut <= kS, "weight fragments fit the hidden layers' buffer");
 
+  // Loads in the order they are needed: the rows and labels, the tables and
+  // biases (then copied to LDS), and last the first two layers' weights, so
+  // that waiting for the rows does not wait for the weights as well (loads
+  // complete in issue order).
+  uint4 xrow = make_uint4(0, 0, 0, 0);
+  float lab = 0.0f;
+  const int gr = tid >> 3, gc = tid & 7;  // gather: row, 16-byte chunk of its 64 features (and label gc)
+  if (tid < kTrainRows * 8 && i0 + gr < a.count) {
+    const uint64_t p = (a.mul * (uint64_t)(a.first + i0 + gr) + a.add) % a.P;
+    xrow = *reinterpret_cast<const uint4 *>(a.X + p * kInPad + gc * 8);
+    switch (gc) {
+      case 0: lab = a.mu_base[p]; break;
+      case 1: lab = a.nph[p]; break;
+      case 2: lab = a.k[p]; break;
+      case 3: lab = a.n_t[p]; break;
+      case 4: lab = a.s1[p]; break;
+      case 5: lab = a.s2[p]; break;
+      case 6: lab = a.w ? a.w[p] : 1.0f; break;
+      default: break;
+    }
+  }
+  float2 cdf[3], grad[3];
+  float bias[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int q = tid + k * kTrainThreads;
+    if (q <= kCdfN) cdf[k] = kCdfTable[q], grad[k] = kGeluGradTable[q];
+    if (q < 4 * kHidden + kOutPad) bias[k] = q < 4 * kHidden ? a.b[q / kHidden][q % kHidden] : a.b[4][q - 4 * kHidden];
+  }
   // two fragment sets: each layer's weights are loaded two layers ahead
   WFrags fa, fb;
   load_w<kS0, kInPad>(fa, a.wb[0], lane, wave);
   load_w<kS, kHidden>(fb, a.wb[1], lane, wave);
-  // the rows: thread -> (row, 16-byte chunk of its 64 features); chunks
-  // 0..6 also fetch one label each
   if (tid < kTrainRows * 8) {
-    const int r = tid >> 3, c = tid & 7;
-    const int64_t i = i0 + r;
-    const bool real = i < a.count;
-    const uint64_t p = real ? (a.mul * (uint64_t)(a.first + i) + a.add) % a.P : 0;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (real) v = *reinterpret_cast<const uint4 *>(a.X + p * kInPad + c * 8);
-    *reinterpret_cast<uint4 *>(s_act + r * kTrainLd + c * 8) = v;
-    float x = 0.0f;
-    if (real) switch (c) {
-        case 0: x = a.mu_base[p]; break;
-        case 1: x = a.nph[p]; break;
-        case 2: x = a.k[p]; break;
-        case 3: x = a.n_t[p]; break;
-        case 4: x = a.s1[p]; break;
-        case 5: x = a.s2[p]; break;
-        case 6: x = a.w ? a.w[p] : 1.0f; break;
-        default: break;
-      }
-    s_lab[r * 8 + c] = x;
+    *reinterpret_cast<uint4 *>(s_act + gr * kTrainLd + gc * 8) = xrow;
+    s_lab[gr * 8 + gc] = lab;
   }
   for (int q = tid; q < kTrainRows * kDyLd / 8; q += kTrainThreads)
     reinterpret_cast<uint4 *>(s_dy)[q] = make_uint4(0, 0, 0, 0);
-  for (int q = tid; q <= kCdfN; q += kTrainThreads) {
-    const float2 cdf = kCdfTable[q], grad = kGeluGradTable[q];
-    s_tab[q] = make_float4(cdf.x, cdf.y, grad.x, grad.y);
-  }
   // the biases live in LDS: a global load in an epilogue would make its
   // wait cover the weight loads issued before it as well
-  for (int q = tid; q < 4 * kHidden + kOutPad; q += kTrainThreads)
-    s_bias[q] = q < 4 * kHidden ? a.b[q / kHidden][q % kHidden] : a.b[4][q - 4 * kHidden];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int q = tid + k * kTrainThreads;
+    if (q <= kCdfN) s_tab[q] = make_float4(cdf[k].x, cdf[k].y, grad[k].x, grad[k].y);
+    if (q < 4 * kHidden + kOutPad) s_bias[q] = bias[k];
+  }
+  static_assert(3 * kTrainThreads > kCdfN && 3 * kTrainThreads >= 4 * kHidden + kOutPad, "three rounds cover both");
   lds_barrier();
   store_columns(s_act, kTrainLd, kInPad, a.XT, a.M, i0, nullptr);
 
@@ -847,6 +858,11 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
   store_columns(s_act, kTrainLd, kHidden, a.HT[1], a.M, i0, nullptr);
   rows_mma<kS>(acc, fa, s_act, kTrainLd, lane);
   load_w<kSOut, kOutPad>(fa, a.wt[4], lane, wave);  // the first backward product
+  if (wave < 2) {  // and the output layer's (W4 rows 0..15, tile 0) in the set's free slots
+    static_assert(kSOut <= 2 && kFT == 2 && kS == 8, "eight output fragments fit slots 2..7 x 2");
+#pragma unroll
+    for (int s = 0; s < kS; ++s) fa.v[2 + s / 2][s % 2] = load8(a.wb[4] + lane * 8 + s * 512);
+  }
   lds_barrier();
   fwd_epilogue(acc, s_bias + 2 * kHidden, s_tab, s_act, s_gp + 2 * kLayerLds, lane, wave);
   lds_barrier();
@@ -862,15 +878,11 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
   // l < 16 then holds outputs 0..3 of row 16 w + l and takes its loss
   if (wave < 2) {
     const int l16 = lane & 15, kq = (lane >> 4) * 8;
-    const uint16_t *wfrag = a.wb[4] + lane * 8;  // tile 0: rows 0..15
     const uint16_t *hrow = s_act + (wave * 16 + l16) * kTrainLd + kq;
-    bf16x8 wa[kS];
-#pragma unroll
-    for (int s = 0; s < kS; ++s) wa[s] = load8(wfrag + s * 512);
     f32x4 o = {0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < kS; ++s)
-      o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], lds_load8(hrow + s * 32), o, 0, 0, 0);
+      o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa.v[2 + s / 2][s % 2], lds_load8(hrow + s * 32), o, 0, 0, 0);
     if (lane < 16) {
       const int r = wave * 16 + lane;
       const float *L = s_lab + r * 8;
