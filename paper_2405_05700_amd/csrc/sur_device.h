@@ -140,13 +140,13 @@ struct TrainArgs {
   const uint16_t *wb[kLayers];     // bf16 W (out x in), tile-major (frag_offset)
   const uint16_t *wt[kLayers];     // bf16 W^T (in x out), tile-major
   const float *b[kLayers];
-  uint16_t *XT, *HT[4], *dYT, *dZT[4];  // bf16, feature-major with the minibatch row contiguous (ld M)
+  uint16_t *XT, *HT[4], *dYT, *dZT[4];  // bf16, row-block-major: block b's column c at (b n_cols + c) kTrainRows
   float *col_part;                 // (M / kTrainRows) x kBiasCols
   double *loss_part;               // M / kTrainRows
 };
 struct WgradArgs {
-  const uint16_t *A[kLayers];  // dZ_l^T (out x M); dY^T for the output layer
-  const uint16_t *B[kLayers];  // H_{l-1}^T (in x M); X^T for the first layer
+  const uint16_t *A[kLayers];  // dZ_l (out columns); dY for the output layer; row-block-major as the row pass writes
+  const uint16_t *B[kLayers];  // H_{l-1} (in columns); X for the first layer
   int M, splits;               // splits <= M / kTrainRows
   float *ws;                   // layer l: splits x out x in partials from ws + splits * wb_offset(l)
 };

@@ -115,11 +115,14 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs &g, int l, int t, in
   const int n = (n_blk - s + g.splits - 1) / g.splits;  // this slice's steps
   // this thread's chunks: row c / 4 of the stage (A rows, then B rows), part c % 4
   const uint16_t *src[L];
+  int64_t blk_stride[L];  // elements from one row block to the next in this chunk's array
   int dst[L];
 #pragma unroll
   for (int q = 0; q < L; ++q) {
     const int c = tid + 256 * q, row = c >> 2, part = c & 3;
-    src[q] = (row < TM ? g.A[l] + (int64_t)(r0 + row) * g.M : g.B[l] + (int64_t)(c0 + row - TM) * g.M) + part * 8;
+    src[q] = (row < TM ? g.A[l] + (int64_t)(r0 + row) * kTrainRows : g.B[l] + (int64_t)(c0 + row - TM) * kTrainRows) +
+             part * 8;
+    blk_stride[q] = (int64_t)(row < TM ? n_out : n_in) * kTrainRows;
     dst[q] = row * kWgradLd + part * 8;
   }
   f32x4 acc[MI][NI];
@@ -132,10 +135,14 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs &g, int l, int t, in
   // set, so every index is static and the sets stay in VGPRs.
   static_assert(D == 4, "the ring below has four sets");
   u32x4 ra[L], rb[L], rc[L], rd[L];  // native vectors: a uint4 struct would be copied through memory
+  // Every step issues its loads, past the slice's end from its last block
+  // (loaded, never used): the same count of loads in flight on every path
+  // lets the compiler wait for exactly the set it needs (loads complete in
+  // issue order).
 #define WGRAD_LOAD(R, J)                                                                \
   {                                                                                     \
-    const int64_t k0_ = (int64_t)(s + (J) * g.splits) * kTrainRows;                     \
-    _Pragma("unroll") for (int q = 0; q < L; ++q) R[q] = *reinterpret_cast<const u32x4 *>(src[q] + k0_); \
+    const int64_t b_ = s + min((J), n - 1) * g.splits;                                  \
+    _Pragma("unroll") for (int q = 0; q < L; ++q) R[q] = *reinterpret_cast<const u32x4 *>(src[q] + b_ * blk_stride[q]); \
   }
   // step j: its rows (in R) to LDS stage j & 1, the set reloaded with step
   // j + D, then the products. Stage j & 1 was last read by step j - 2,
@@ -145,14 +152,14 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs &g, int l, int t, in
     const int j_ = (J);                                                                 \
     uint16_t *st_ = stage + (j_ & 1) * kStage;                                          \
     _Pragma("unroll") for (int q = 0; q < L; ++q) *reinterpret_cast<u32x4 *>(st_ + dst[q]) = R[q]; \
-    if (j_ + D < n) WGRAD_LOAD(R, j_ + D);                                              \
+    WGRAD_LOAD(R, j_ + D);                                                              \
     lds_barrier();                                                                      \
     wgrad_products<MI, NI>(acc, st_ + wr * (TM / 2) * kWgradLd + fr, st_ + (TM + wc * (TN / 2)) * kWgradLd + fr); \
   }
-  if (0 < n) WGRAD_LOAD(ra, 0);
-  if (1 < n) WGRAD_LOAD(rb, 1);
-  if (2 < n) WGRAD_LOAD(rc, 2);
-  if (3 < n) WGRAD_LOAD(rd, 3);
+  WGRAD_LOAD(ra, 0);
+  WGRAD_LOAD(rb, 1);
+  WGRAD_LOAD(rc, 2);
+  WGRAD_LOAD(rd, 3);
   // whole rounds of the ring, then the last n % D steps
   int j0 = 0;
   for (; j0 + D <= n; j0 += D) {
@@ -741,13 +748,14 @@ __device__ __forceinline__ void bwd_epilogue(const f32x4 (&acc)[kFT][2], const u
 }
 
 // Copies the workgroup's kTrainRows x n_cols bf16 tile in LDS (ld elements
-// per row) to the feature-major dst (column c at dst + c * M + i0). Four
+// per row) to its block of the row-block-major dst: column c of row block
+// blk at dst + (blk n_cols + c) kTrainRows, the 32 rows contiguous. Four
 // consecutive lanes share a column, each taking 8 rows as one 16-byte
-// store, so a store instruction covers 16 columns' 64-byte runs. If col_sum
-// is not null it also gets each column's sum over the rows: each lane adds
-// its 8 rows in order, then the four lanes combine pairwise.
-__device__ __forceinline__ void store_columns(const uint16_t *s, int ld, int n_cols, uint16_t *dst, int64_t M,
-                                              int64_t i0, float *col_sum) {
+// store, so a wavefront's store covers 1 KB contiguous. If col_sum is not
+// null it also gets each column's sum over the rows: each lane adds its 8
+// rows in order, then the four lanes combine pairwise.
+__device__ __forceinline__ void store_columns(const uint16_t *s, int ld, int n_cols, uint16_t *dst, int blk,
+                                              float *col_sum) {
   static_assert(kTrainRows == 32, "four lanes of 8 rows per column");
   const int part = threadIdx.x & 3;
 #pragma unroll
@@ -765,7 +773,8 @@ __device__ __forceinline__ void store_columns(const uint16_t *s, int ld, int n_c
       sum += bf_to_f(hi);
     }
     if (live)
-      *reinterpret_cast<uint4 *>(dst + (int64_t)c * M + i0 + 8 * part) = make_uint4(w[0], w[1], w[2], w[3]);
+      *reinterpret_cast<uint4 *>(dst + ((int64_t)blk * n_cols + c) * kTrainRows + 8 * part) =
+          make_uint4(w[0], w[1], w[2], w[3]);
     if (col_sum) {
       sum += __shfl_xor(sum, 1, 64);  // addition is commutative: both lanes get the same value
       sum += __shfl_xor(sum, 2, 64);
@@ -840,7 +849,7 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
   }
   static_assert(3 * kTrainThreads > kCdfN && 3 * kTrainThreads >= 4 * kHidden + kOutPad, "three rounds cover both");
   lds_barrier();
-  store_columns(s_act, kTrainLd, kInPad, a.XT, a.M, i0, nullptr);
+  store_columns(s_act, kTrainLd, kInPad, a.XT, blk, nullptr);
 
   // forward
   f32x4 acc[kFT][2];
@@ -849,13 +858,13 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
   lds_barrier();  // every wavefront has read the layer's input
   fwd_epilogue(acc, s_bias, s_tab, s_act, s_gp, lane, wave);
   lds_barrier();  // the layer's output is complete
-  store_columns(s_act, kTrainLd, kHidden, a.HT[0], a.M, i0, nullptr);
+  store_columns(s_act, kTrainLd, kHidden, a.HT[0], blk, nullptr);
   rows_mma<kS>(acc, fb, s_act, kTrainLd, lane);
   load_w<kS, kHidden>(fb, a.wb[3], lane, wave);
   lds_barrier();
   fwd_epilogue(acc, s_bias + kHidden, s_tab, s_act, s_gp + kLayerLds, lane, wave);
   lds_barrier();
-  store_columns(s_act, kTrainLd, kHidden, a.HT[1], a.M, i0, nullptr);
+  store_columns(s_act, kTrainLd, kHidden, a.HT[1], blk, nullptr);
   rows_mma<kS>(acc, fa, s_act, kTrainLd, lane);
   load_w<kSOut, kOutPad>(fa, a.wt[4], lane, wave);  // the first backward product
   if (wave < 2) {  // and the output layer's (W4 rows 0..15, tile 0) in the set's free slots
@@ -866,13 +875,13 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
   lds_barrier();
   fwd_epilogue(acc, s_bias + 2 * kHidden, s_tab, s_act, s_gp + 2 * kLayerLds, lane, wave);
   lds_barrier();
-  store_columns(s_act, kTrainLd, kHidden, a.HT[2], a.M, i0, nullptr);
+  store_columns(s_act, kTrainLd, kHidden, a.HT[2], blk, nullptr);
   rows_mma<kS>(acc, fb, s_act, kTrainLd, lane);
   load_w<kS, kHidden>(fb, a.wt[3], lane, wave);
   lds_barrier();
   fwd_epilogue(acc, s_bias + 3 * kHidden, s_tab, s_act, s_gp + 3 * kLayerLds, lane, wave);
   lds_barrier();
-  store_columns(s_act, kTrainLd, kHidden, a.HT[3], a.M, i0, nullptr);
+  store_columns(s_act, kTrainLd, kHidden, a.HT[3], blk, nullptr);
 
   // output layer (outputs 0..15 of W4) for rows 16 w .. + 16, w = 0, 1; lane
   // l < 16 then holds outputs 0..3 of row 16 w + l and takes its loss
@@ -902,30 +911,30 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
     for (int off = 16; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
     if (lane == 0) a.loss_part[blk] = sum;
   }
-  store_columns(s_dy, kDyLd, kOutPad, a.dYT, a.M, i0, col_part + 4 * kHidden);
+  store_columns(s_dy, kDyLd, kOutPad, a.dYT, blk, col_part + 4 * kHidden);
 
   // backward; every read of H_3 in s_act happened before the barrier above
   rows_mma<kSOut>(acc, fa, s_dy, kDyLd, lane);  // dH_3^T = W_4^T dY^T
   load_w<kS, kHidden>(fa, a.wt[2], lane, wave);
   bwd_epilogue(acc, s_gp + 3 * kLayerLds, s_act, lane, wave);
   lds_barrier();
-  store_columns(s_act, kTrainLd, kHidden, a.dZT[3], a.M, i0, col_part + 3 * kHidden);
+  store_columns(s_act, kTrainLd, kHidden, a.dZT[3], blk, col_part + 3 * kHidden);
   rows_mma<kS>(acc, fb, s_act, kTrainLd, lane);  // dH_2^T = W_3^T dZ_3^T
   load_w<kS, kHidden>(fb, a.wt[1], lane, wave);
   lds_barrier();
   bwd_epilogue(acc, s_gp + 2 * kLayerLds, s_act, lane, wave);
   lds_barrier();
-  store_columns(s_act, kTrainLd, kHidden, a.dZT[2], a.M, i0, col_part + 2 * kHidden);
+  store_columns(s_act, kTrainLd, kHidden, a.dZT[2], blk, col_part + 2 * kHidden);
   rows_mma<kS>(acc, fa, s_act, kTrainLd, lane);  // dH_1^T = W_2^T dZ_2^T
   lds_barrier();
   bwd_epilogue(acc, s_gp + kLayerLds, s_act, lane, wave);
   lds_barrier();
-  store_columns(s_act, kTrainLd, kHidden, a.dZT[1], a.M, i0, col_part + kHidden);
+  store_columns(s_act, kTrainLd, kHidden, a.dZT[1], blk, col_part + kHidden);
   rows_mma<kS>(acc, fb, s_act, kTrainLd, lane);  // dH_0^T = W_1^T dZ_1^T
   lds_barrier();
   bwd_epilogue(acc, s_gp, s_act, lane, wave);
   lds_barrier();
-  store_columns(s_act, kTrainLd, kHidden, a.dZT[0], a.M, i0, col_part);
+  store_columns(s_act, kTrainLd, kHidden, a.dZT[0], blk, col_part);
 }
 
 __global__ void k_zero_u64(unsigned long long *p, int64_t n) {
