@@ -115,7 +115,7 @@ constexpr int kTrainRows = 32;                    // minibatch rows per workgrou
 constexpr int kTrainLd = kHidden + 8;             // LDS row stride (elements) of activations and GELU'
 constexpr int kDyLd = kOutPad + 8;                // LDS row stride of the output gradient
 constexpr int kBiasCols = 4 * kHidden + kOutPad;  // bias-gradient columns per row block: dZ_0..dZ_3, then dY
-constexpr int kWgradSplits = 8;                   // K slices of the weight gradients (at most)
+constexpr int kWgradSplits = 16;                  // K slices of the weight gradients (at most)
 
 // Tiles of layer l's weight gradient: 128 x 128, or the layer's whole
 // extent where it is 64 (inputs of layer 0, outputs of the last), and

@@ -74,8 +74,8 @@ __device__ __forceinline__ bf16x8 lds_load8(const uint16_t *p) {
 // Slice s takes the minibatch's 32-row blocks s, s + splits, s + 2 splits,
 // ...; the row pass wrote block b from its workgroup b, and consecutive
 // workgroups are dispatched to the eight XCDs in turn, so with splits a
-// multiple of 8 a slice reads only blocks written on the XCD it runs on,
-// from that XCD's L2 where they are still resident.
+// multiple of 8 a slice reads only blocks written on the XCD it runs on
+// (whatever of them that XCD's L2 still holds is read from there).
 //
 // A tile of TM x TN: each 32-row step stages the A rows (TM x 32) and B rows
 // (TN x 32) in LDS (row stride 40 elements: the 16 rows a fragment read
