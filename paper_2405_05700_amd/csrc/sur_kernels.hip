@@ -31,15 +31,18 @@ __device__ __forceinline__ bf16x8 load8(const uint16_t *p) {
 }
 
 // GELU for the fused inference kernel: z Phi(z) with Phi linear between the
-// 1025 nodes of a table in LDS (gelu_table.py beside this file derives it
-// and bounds the error: |error| <= 5.3e-6 for all z, 2^-12 relative where
-// |GELU| > 0.01). Eight full-rate operations and one 8-byte LDS read;
-// t = N (z >= 6) lands on the last node, whose difference is 0, and a NaN
-// converts to index 0.
-__device__ __forceinline__ float gelu_table(float z, const float2 *cdf) {
+// 1025 nodes of a table in LDS, read as float16 pairs (Phi_i, Phi_(i+1) -
+// Phi_i) packed in 32 bits (gelu_table.py beside this file derives it and
+// bounds the error: within 5.0e-4 relative where |GELU| > 0.01, a quarter of
+// the bf16 rounding the activation then takes). Eight full-rate operations
+// and one 4-byte LDS read; t = N (z >= 6) lands on the last node, whose
+// difference is 0, and a NaN converts to index 0.
+__device__ __forceinline__ float gelu_table(float z, const uint32_t *cdf) {
   const float t = __builtin_amdgcn_fmed3f(__builtin_fmaf(z, kCdfA, kCdfB), 0.0f, (float)kCdfN);
-  const float2 e = cdf[(uint32_t)t];
-  return z * __builtin_fmaf(__builtin_amdgcn_fractf(t), e.y, e.x);
+  const uint32_t e = cdf[(uint32_t)t];
+  const float p = (float)__builtin_bit_cast(_Float16, (uint16_t)e);
+  const float d = (float)__builtin_bit_cast(_Float16, (uint16_t)(e >> 16));
+  return z * __builtin_fmaf(__builtin_amdgcn_fractf(t), d, p);
 }
 
 // Digamma for x > 0: recurrence psi(x) = psi(x + 1) - 1/x up to x >= 6, then
@@ -509,17 +512,21 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
 
 template <int K, int LDW>
 __device__ __forceinline__ void fused_hidden_layer(uint16_t *lds_h, const uint16_t *__restrict__ w,
-                                                   const float *__restrict__ bias, const float2 *cdf, int lane,
+                                                   const float *__restrict__ bias, const uint32_t *cdf, int lane,
                                                    int wave) {
   const int fg = wave;
   const int l16 = lane & 15, kq = (lane >> 4) * 8;
   const uint16_t *wfrag = w + lane * 8;  // + 512 (tile index): this lane's 16 bytes of a tile
   const uint16_t *hrow = lds_h + l16 * kFusedLd + kq;
+  // the accumulators start at the biases (a lane's four values are features
+  // f0 .. f0 + 3 of one pair), which saves the epilogue an addition per value
   f32x4 acc[4][8];
 #pragma unroll
-  for (int ft = 0; ft < 4; ++ft)
+  for (int ft = 0; ft < 4; ++ft) {
+    const float4 b = *reinterpret_cast<const float4 *>(bias + fg * 64 + ft * 16 + 4 * (lane >> 4));
 #pragma unroll
-    for (int pt = 0; pt < 8; ++pt) acc[ft][pt] = f32x4{0, 0, 0, 0};
+    for (int pt = 0; pt < 8; ++pt) acc[ft][pt] = f32x4{b.x, b.y, b.z, b.w};
+  }
 #pragma unroll 2  // two K steps in flight fit the 256-register budget of 2 waves per SIMD without spills
   for (int k = 0; k < K; k += 32) {
     bf16x8 wa[4], hb[8];
@@ -537,12 +544,11 @@ __device__ __forceinline__ void fused_hidden_layer(uint16_t *lds_h, const uint16
 #pragma unroll
   for (int ft = 0; ft < 4; ++ft) {
     const int f0 = fg * 64 + ft * 16 + 4 * (lane >> 4);
-    const float b0 = bias[f0], b1 = bias[f0 + 1], b2 = bias[f0 + 2], b3 = bias[f0 + 3];
 #pragma unroll
     for (int pt = 0; pt < 8; ++pt) {
       const f32x4 v = acc[ft][pt];
-      const uint2 h = make_uint2(pack_bf16(gelu_table(v[0] + b0, cdf), gelu_table(v[1] + b1, cdf)),
-                                 pack_bf16(gelu_table(v[2] + b2, cdf), gelu_table(v[3] + b3, cdf)));
+      const uint2 h = make_uint2(pack_bf16(gelu_table(v[0], cdf), gelu_table(v[1], cdf)),
+                                 pack_bf16(gelu_table(v[2], cdf), gelu_table(v[3], cdf)));
       *reinterpret_cast<uint2 *>(lds_h + (pt * 16 + l16) * kFusedLd + f0) = h;
     }
   }
@@ -553,13 +559,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   extern __shared__ __align__(16) uint16_t lds_h[];  // kFusedRows x kFusedLd bf16, then scale and module id
   float *s_scale = reinterpret_cast<float *>(lds_h + kFusedRows * kFusedLd);
   int *s_dom = reinterpret_cast<int *>(s_scale + kFusedRows);
-  float2 *s_cdf = reinterpret_cast<float2 *>(s_dom + kFusedRows);
+  uint32_t *s_cdf = reinterpret_cast<uint32_t *>(s_dom + kFusedRows);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t q0 = (int64_t)blockIdx.x * kFusedRows;
 
   // the GELU table, then features: one pair per thread of the first half;
   // input columns kInReal..31 are zero
-  for (int i = tid; i <= kCdfN; i += blockDim.x) s_cdf[i] = kCdfTable[i];
+  for (int i = tid; i <= kCdfN; i += blockDim.x) s_cdf[i] = kCdfTableHalf[i];
   if (tid < kFusedRows) {
     float x[kInReal];
 #pragma unroll
@@ -693,8 +699,8 @@ __device__ __forceinline__ void rows_mma(f32x4 (&acc)[kFT][2], const WFrags &w, 
 }
 
 // GELU(z) and GELU'(z) from the two tables interleaved in LDS as
-// (Phi_i, dPhi_i, G_i, dG_i): the same map and interpolation as
-// gelu_table(), so the forward activations equal inference's.
+// (Phi_i, dPhi_i, G_i, dG_i), float32: the map and interpolation of
+// gelu_table().
 __device__ __forceinline__ void gelu_and_grad(float z, const float4 *tab, float &h, float &g) {
   const float t = __builtin_amdgcn_fmed3f(__builtin_fmaf(z, kCdfA, kCdfB), 0.0f, (float)kCdfN);
   const float4 e = tab[(uint32_t)t];
@@ -973,7 +979,7 @@ hipError_t launch_reduce_adam(const AdamArgs &a, hipStream_t s) {
 }
 
 size_t fused_lds_bytes() {
-  return sizeof(uint16_t) * kFusedRows * kFusedLd + 2 * sizeof(float) * kFusedRows + sizeof(float2) * (kCdfN + 1);
+  return sizeof(uint16_t) * kFusedRows * kFusedLd + 2 * sizeof(float) * kFusedRows + sizeof(uint32_t) * (kCdfN + 1);
 }
 
 hipError_t launch_infer_fused(const FusedArgs &a, hipStream_t s) {
