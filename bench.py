@@ -121,7 +121,45 @@ def parse():
     ap.add_argument("--only-inference", action="store_true",
                     help="only time the surrogate's fused inference over 1e5 segments x 5160 modules, with "
                          "untrained weights (for profiling)")
+    ap.add_argument("--only-training", action="store_true",
+                    help="only time surrogate training: labels from 24000 near-module segments (2e5 photons "
+                         "each), then three epochs at the bench's minibatch size (for profiling)")
     return ap.parse_args()
+
+
+def training_rate(args):
+    """Surrogate training alone, on the bench's recipe at a quarter of its
+    segments and a tenth of its label photons (the work per row does not
+    depend on them): 24000 near-module segments, pair sampling, one warm-up
+    epoch, then three timed epochs of --sur-batch rows per step."""
+    import torch
+    from paper_2405_05700_amd import pp, surrogate
+    from paper_2405_05700_amd import workloads as W
+    det = W.full_detector(n_sources=1, photons_per_source=1)
+    ctx = pp.Context(0, seed=7)
+    ctx.load_workload(det)
+    ctx.set_launch_config(hit_capacity=20_000_000)
+    targets = W.training_targets(det, 24_000, args.sur_structured_frac, seed=77)
+    tr = W.near_module_segments(det, 24_000, 200_000, seed=101, r_min=3.0, r_max=args.sur_train_rmax,
+                                targets=targets)
+    b = ctx.submit(tr)
+    ctx.propagate(b)
+    m = surrogate.Surrogate(ctx, seed=1)
+    m.set_sampling(args.sur_near_m, args.sur_far_stride)
+    m.set_training_set(b)
+    ctx.release(b)
+    rows = m.training_size()
+    m.train(epochs=1, batch_size=args.sur_batch, lr=args.sur_lr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.train(epochs=3, batch_size=args.sur_batch, lr=args.sur_lr)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    steps = 3 * ((rows + args.sur_batch - 1) // args.sur_batch)
+    m.close()
+    ctx.close()
+    return {"rows": rows, "epochs": 3, "batch": args.sur_batch, "train_s": t, "pairs_per_s": 3 * rows / t,
+            "us_per_step": t / steps * 1e6}
 
 
 def copy_calibration():
@@ -499,6 +537,9 @@ def main():
         return
     if args.only_inference:
         print(json.dumps(inference_rate(args.sur_infer_sources)), flush=True)
+        return
+    if args.only_training:
+        print(json.dumps(training_rate(args)), flush=True)
         return
     from paper_2405_05700_amd import pp
     from paper_2405_05700_amd import workloads as W
