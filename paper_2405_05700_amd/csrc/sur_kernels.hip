@@ -638,12 +638,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 //            row;
 //   backward dZ_{l-1}^T = (W_l^T dZ_l^T) * GELU'(Z_{l-1}), from dY down to
 //            dZ_0.
-// Each layer's weight fragments are loaded into VGPRs before the previous
-// layer's epilogue, so their L2 latency overlaps it; the barriers order LDS
+// Each layer's weight fragments are loaded into VGPRs two layers ahead
+// (two fragment sets alternate), from the tile-major bf16 copies, so a
+// wavefront's fragment load reads 1 KB contiguous; the barriers order LDS
 // only, so those loads stay in flight across them. After each layer the
-// workgroup copies the layer's output from LDS to a feature-major global
-// array, where the weight-gradient pass reads it; the copies of dY and dZ_l
-// also sum each column over the 32 rows (the bias-gradient parts).
+// workgroup copies the layer's output from LDS to its block of a
+// row-block-major global array, where the weight-gradient pass reads it;
+// the copies of dY and dZ_l also sum each column over the 32 rows (the
+// bias-gradient parts).
 constexpr int kTrainThreads = 512;
 constexpr int kWaveFeat = kHidden / (kTrainThreads / 64);  // output features per wavefront
 constexpr int kFT = kWaveFeat / 16;                         // 16-feature MFMA tiles per wavefront
