@@ -96,15 +96,19 @@ pp_status pp_sur_get_training_rows(pp_surrogate *sur, uint64_t first, uint64_t c
                                    float *mu_base, float *k, float *n_t, float *s1, float *s2);
 
 /* Loss and gradient (f32, parameter layout) over training rows
- * [first, first + count) as one batch, without an update. */
+ * [first, first + count) as one batch, without an update. PP_EINVAL unless
+ * 0 < count <= 2^30 and the rows lie within the training set. Work buffers
+ * grow with count (about 4.4 KB per row for the activations the weight
+ * gradients read). */
 pp_status pp_sur_loss_grad(pp_surrogate *sur, uint64_t first, uint64_t count, double *loss, float *grad);
 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr on
- * rows [first, first + count); *loss gets the loss before the step. */
+ * rows [first, first + count) (the same bounds); *loss gets the loss before
+ * the step. */
 pp_status pp_sur_train_step(pp_surrogate *sur, uint64_t first, uint64_t count, float lr, double *loss);
 
 /* Trains for the given epochs over the whole training set in minibatches of
- * batch_size rows (a multiple of 64) on hip_stream. Every epoch visits the
+ * batch_size rows (a multiple of 64, at most 2^30) on hip_stream. Every epoch visits the
  * rows in a fresh pseudo-random order (an affine permutation of the row
  * index modulo the set size, multiplier coprime to it), so each minibatch
  * mixes pairs of many sources. The Adam learning rate follows a cosine from

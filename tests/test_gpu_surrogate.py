@@ -177,6 +177,39 @@ def test_forward_and_gradients_match_oracle(mods, small_set):
             assert err < GRAD_REL and cos > GRAD_COS, (li, part, err, cos)
 
 
+def test_gradients_on_ragged_unaligned_minibatches(mods, small_set):
+    """Minibatches that start inside a 32-row block and end in a ragged tail
+    give the oracle's loss and gradients too: 1001 rows from row 5037 (padded
+    to 1024: 32 row blocks, 16 weight-gradient slices of two steps each) and
+    37 rows from row 19990 (one 64-row tile: two row blocks, the second all
+    padding past row 32)."""
+    pp, surrogate, M = mods
+    w, ctx, b, sur = small_set
+    theta = flatten(M, M.init_params(3))
+    sur.set_params(theta)
+    P = sur.training_size()
+    rows = sur.training_rows(0, P)
+    nph = np.repeat(w.sources["n_photons"].astype(float), len(w.doms))
+    for first, count in ((5037, 1001), (19990, 37)):
+        loss, grad = sur.loss_grad(first, count)
+        X, params = oracle_on_gpu_inputs(M, rows, theta, first, count)
+        Y, cache = M.forward(params, X)
+        sl = slice(first, first + count)
+        loss_ref, dY = M.loss_and_grad_out(Y, rows["mu_base"][sl].astype(float), nph[sl], rows["k"][sl],
+                                           rows["n_t"][sl], rows["s1"][sl], rows["s2"][sl])
+        g_ref = flatten(M, M.backward(params, cache, dY)).astype(np.float64)
+        say(f"rows [{first}, {first + count}): loss gpu {loss} oracle {loss_ref}")
+        assert abs(loss - loss_ref) <= LOSS_REL * abs(loss_ref) + 1e-6
+        o = 0
+        for li, (n_out, n_in) in enumerate(M.LAYER_SHAPES):
+            for part, size in (("W", n_out * n_in), ("b", n_out)):
+                a, r = grad[o:o + size].astype(np.float64), g_ref[o:o + size]
+                o += size
+                err = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
+                cos = a @ r / max(np.linalg.norm(a) * np.linalg.norm(r), 1e-30)
+                assert err < GRAD_REL and cos > GRAD_COS, (first, count, li, part, err, cos)
+
+
 def test_fused_expected_hits_equal_pair_sums(mods):
     """The fused inference kernel adds every pair's expectation to its
     module's sum: 37 sources x 5160 modules is 746 full tiles of 256 pairs
