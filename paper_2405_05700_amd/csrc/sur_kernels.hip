@@ -214,6 +214,11 @@ __device__ __forceinline__ int layer_of(float z, float z_lo, float inv_dz, int n
 // p % n_doms) and its diffusion baseline.
 __device__ __forceinline__ void pair_features(const FeatureArgs &f, int64_t p, float x[kInReal],
                                               float &mu_base, float &nph, float &R, int &dom) {
+  // Divisions by constants are multiplications by their reciprocals, the
+  // others hardware reciprocals, and square roots, logarithms and
+  // exponentials the hardware's (each within about an ulp of float32): the
+  // features are stored as bf16, 2^-8 relative, and the baseline is a smooth
+  // physics estimate.
   const int i = (int)(p / f.n_doms), j = (int)(p % f.n_doms);
   const pp::DevSource &S = f.sources[i];
   const float4 m = f.doms[j];
@@ -221,8 +226,9 @@ __device__ __forceinline__ void pair_features(const FeatureArgs &f, int64_t p, f
   const float cx = S.pos_t0.x + half * S.dir_len.x, cy = S.pos_t0.y + half * S.dir_len.y;
   const float cz = S.pos_t0.z + half * S.dir_len.z;
   const float dx = m.x - cx, dy = m.y - cy, dz = m.z - cz;
-  R = fmaxf(sqrtf(dx * dx + dy * dy + dz * dz), 0.5f);
-  const float ux = dx / R, uy = dy / R, uz = dz / R;
+  R = fmaxf(__builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz), 0.5f);
+  const float rR = __builtin_amdgcn_rcpf(R);
+  const float ux = dx * rR, uy = dy * rR, uz = dz * rR;
   const float cos_eta = ux * S.dir_len.x + uy * S.dir_len.y + uz * S.dir_len.z;
   const pp::DevLayer Ls = f.layers[layer_of(cz, f.z_lo, f.inv_dz, f.n_layers)];
   const pp::DevLayer Ld = f.layers[layer_of(m.z, f.z_lo, f.inv_dz, f.n_layers)];
@@ -230,19 +236,19 @@ __device__ __forceinline__ void pair_features(const FeatureArgs &f, int64_t p, f
   // depth only): vertical parts, horizontal and vertical offsets, distance,
   // angle to the track and the relative azimuth of the horizontal parts.
   const float h = S.dir_len.x * ux + S.dir_len.y * uy;
-  const float hh = sqrtf((S.dir_len.x * S.dir_len.x + S.dir_len.y * S.dir_len.y) * (ux * ux + uy * uy));
+  const float hh = __builtin_amdgcn_sqrtf((S.dir_len.x * S.dir_len.x + S.dir_len.y * S.dir_len.y) * (ux * ux + uy * uy));
   x[0] = uz;
-  x[1] = sqrtf(dx * dx + dy * dy) / 100.0f;
-  x[2] = dz / 100.0f;
-  x[3] = R / 100.0f;
-  x[4] = logf(R / 10.0f) / 3.0f;
+  x[1] = __builtin_amdgcn_sqrtf(dx * dx + dy * dy) * 0.01f;
+  x[2] = dz * 0.01f;
+  x[3] = R * 0.01f;
+  x[4] = (__builtin_amdgcn_logf(R) - 3.32192809488736235f) * 0.23104906018664843f;  // ln(R / 10) / 3 via log2
   x[5] = cos_eta;
   x[6] = cos_eta - 0.75470958022277199f;  // cos 41 deg
   x[7] = S.dir_len.z;
   x[8] = h;
-  x[9] = hh > 1e-9f ? fminf(fmaxf(h / hh, -1.0f), 1.0f) : 0.0f;
-  x[10] = cz / 500.0f;
-  x[11] = m.z / 500.0f;
+  x[9] = hh > 1e-9f ? fminf(fmaxf(h * __builtin_amdgcn_rcpf(hh), -1.0f), 1.0f) : 0.0f;
+  x[10] = cz * 0.002f;
+  x[11] = m.z * 0.002f;
   x[12] = 100.0f * Ls.coef.x;
   x[13] = 10.0f * Ls.coef.y;
   x[14] = 100.0f * Ld.coef.x;
@@ -255,13 +261,13 @@ __device__ __forceinline__ void pair_features(const FeatureArgs &f, int64_t p, f
   const float vx = m.x - S.pos_t0.x, vy = m.y - S.pos_t0.y, vz = m.z - S.pos_t0.z;
   const float along = vx * S.dir_len.x + vy * S.dir_len.y + vz * S.dir_len.z;
   const float px = vx - along * S.dir_len.x, py = vy - along * S.dir_len.y, pz = vz - along * S.dir_len.z;
-  const float bimp = sqrtf(px * px + py * py + pz * pz);
+  const float bimp = __builtin_amdgcn_sqrtf(px * px + py * py + pz * pz);
   const float ex = vx - L * S.dir_len.x, ey = vy - L * S.dir_len.y, ez = vz - L * S.dir_len.z;
-  x[16] = bimp / 100.0f;
-  x[17] = (along - 0.5f * L) / 100.0f;
-  x[18] = fminf(fmaxf((along - bimp / kTanCherenkov) / L, -1.0f), 2.0f);
-  x[19] = sqrtf(vx * vx + vy * vy + vz * vz) / 100.0f;
-  x[20] = sqrtf(ex * ex + ey * ey + ez * ez) / 100.0f;
+  x[16] = bimp * 0.01f;
+  x[17] = (along - 0.5f * L) * 0.01f;
+  x[18] = fminf(fmaxf((along - bimp * (1.0f / kTanCherenkov)) * __builtin_amdgcn_rcpf(L), -1.0f), 2.0f);
+  x[19] = __builtin_amdgcn_sqrtf(vx * vx + vy * vy + vz * vz) * 0.01f;
+  x[20] = __builtin_amdgcn_sqrtf(ex * ex + ey * ey + ez * ez) * 0.01f;
   // The optics 20 m above and below the segment centre and the module:
   // where the depth profile changes within the range light diffuses over
   // (a dust layer), the two end layers alone do not say so.
@@ -275,10 +281,12 @@ __device__ __forceinline__ void pair_features(const FeatureArgs &f, int64_t p, f
   // diffusion baseline with the two layers' mean absorption and
   // effective scattering lengths (lambda_e = (1/b) / (1 - g))
   const float lam_a = 0.5f * (Ls.coef.z + Ld.coef.z);
-  const float lam_e = 0.5f * (Ls.coef.w / Ls.hg.x + Ld.coef.w / Ld.hg.x);
-  const float D = lam_e / 3.0f;
-  const float dl = sqrtf(D * lam_a);
-  mu_base = f.radius * f.radius * expf(-R / dl) / (4.0f * D * R);
+  const float lam_e = 0.5f * (Ls.coef.w * __builtin_amdgcn_rcpf(Ls.hg.x) + Ld.coef.w * __builtin_amdgcn_rcpf(Ld.hg.x));
+  const float D = lam_e * (1.0f / 3.0f);
+  const float dl = __builtin_amdgcn_sqrtf(D * lam_a);
+  // r^2 exp(-R / dl) / (4 D R), the exponential as 2^(-R log2(e) / dl)
+  mu_base = f.radius * f.radius * __builtin_amdgcn_exp2f(-1.44269504088896341f * R * __builtin_amdgcn_rcpf(dl)) *
+            __builtin_amdgcn_rcpf(4.0f * D * R);
   nph = f.src_nph[i];
   dom = j;
 }
