@@ -286,8 +286,11 @@ pp_status pp_set_acceptance(pp_context *ctx, const pp_acceptance *acc);
 enum { PP_RECORDS_OFF = 0, PP_RECORDS_ON = 1, PP_RECORDS_PRODUCTION = 2 };
 pp_status pp_set_debug_records(pp_context *ctx, int mode);
 
-/* Propagates every photon of the batch: one persistent kernel on hip_stream
- * (a hipStream_t; NULL is the null stream), asynchronous. Ice, geometry and
+/* Propagates every photon of the batch (Sec. 2: the distance to the next
+ * scatter drawn by Monte Carlo from the layer's scattering coefficient, a
+ * new direction from the scattering physics, repeated until the photon
+ * reaches a module or is absorbed): one persistent kernel on hip_stream (a
+ * hipStream_t; NULL is the null stream), asynchronous. Ice, geometry and
  * sources are already resident on the device. May be called again on the
  * same batch; the result is the same. */
 pp_status pp_propagate(pp_context *ctx, uint64_t batch, void *hip_stream);
@@ -298,7 +301,9 @@ pp_status pp_propagate(pp_context *ctx, uint64_t batch, void *hip_stream);
 pp_status pp_hit_count(pp_context *ctx, uint64_t batch, uint64_t *n_total);
 
 /* Copies up to cap hits into host memory out (order unspecified) and sets
- * *n_total. Returns PP_ETRUNC if n_total > cap (cap hits copied). */
+ * *n_total: the compact records of Sec. 4 (hit-record paragraph: particle
+ * id, time, weight), plus event, photon index and module. Returns
+ * PP_ETRUNC if n_total > cap (cap hits copied). */
 pp_status pp_fetch_hits(pp_context *ctx, uint64_t batch, pp_hit *out, uint64_t cap,
                         uint64_t *n_total);
 
@@ -343,7 +348,10 @@ pp_status pp_dom_weights(pp_context *ctx, uint64_t batch, double *dev_sums, void
 pp_status pp_fetch_records(pp_context *ctx, uint64_t batch, pp_photon_record *out,
                            uint64_t first, uint64_t count);
 
-/* Counters and kernel time of the batch's last propagation (synchronises). */
+/* Counters and kernel time of the batch's last propagation (synchronises):
+ * photons, steps, layer crossings, module tests and fates, the figures
+ * behind the GPU-utilisation and time-per-shower comparison of Sec. 5
+ * (Table 1). */
 pp_status pp_get_stats(pp_context *ctx, uint64_t batch, pp_stats *out);
 
 /* Batched uneven events. The paper's server aggregates light-emitting steps
