@@ -343,30 +343,49 @@ __device__ __forceinline__ RowLoss row_loss(float y0, float y1_raw, float y2_raw
 // Sum of part[i * stride] over i < n in a fixed order by one wavefront: lane
 // l adds parts l, l + 64, l + 128, ... in turn, then the lanes combine by a
 // fixed butterfly. The result depends only on the values, not on
-// scheduling, and the wave's loads are independent.
+// scheduling. Four of a lane's loads are issued before their additions, so
+// their latencies overlap.
 template <class T>
 __device__ __forceinline__ T wave_ordered_sum(const T *part, int n, int64_t stride) {
   const int lane = threadIdx.x & 63;
   T sum = 0;
-  for (int i = lane; i < n; i += 64) sum += part[(int64_t)i * stride];
+  int i = lane;
+  for (; i + 192 < n; i += 256) {
+    const T v0 = part[(int64_t)i * stride], v1 = part[(int64_t)(i + 64) * stride];
+    const T v2 = part[(int64_t)(i + 128) * stride], v3 = part[(int64_t)(i + 192) * stride];
+    __builtin_amdgcn_sched_barrier(0);  // keep the four loads ahead of the first addition
+    sum += v0;
+    sum += v1;
+    sum += v2;
+    sum += v3;
+  }
+  for (; i < n; i += 64) sum += part[(int64_t)i * stride];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
   return sum;
 }
 
-// Stores gradient element i and, with adam, takes the Adam step (Kingma &
-// Ba, beta1 0.9, beta2 0.999, eps 1e-8, bias corrections c1, c2); returns
-// the parameter's new value.
+// The Adam step of one parameter (Kingma & Ba, beta1 0.9, beta2 0.999,
+// eps 1e-8, bias corrections c1, c2). The two moment updates are written as
+// explicit fused multiply-adds, so their rounding does not depend on which
+// product the compiler would fuse.
+__device__ __forceinline__ void adam_update(const AdamArgs &a, float g, float &th, float &m, float &v) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  m = __builtin_fmaf(b1, m, (1.0f - b1) * g);
+  v = __builtin_fmaf(b2, v, (1.0f - b2) * g * g);
+  th -= a.lr * (m / a.c1) / (sqrtf(v / a.c2) + eps);
+}
+
+// Stores gradient element i and, with adam, takes its Adam step; returns the
+// parameter's new value.
 __device__ __forceinline__ float grad_step(const AdamArgs &a, int64_t i, float g) {
   a.grad[i] = g;
   float th = a.theta[i];
   if (a.adam) {
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float mi = b1 * a.m[i] + (1.0f - b1) * g;
-    const float vi = b2 * a.v[i] + (1.0f - b2) * g * g;
+    float mi = a.m[i], vi = a.v[i];
+    adam_update(a, g, th, mi, vi);
     a.m[i] = mi;
     a.v[i] = vi;
-    th -= a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + eps);
     a.theta[i] = th;
   }
   return th;
@@ -393,15 +412,29 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const AdamArgs a) {
     const int n_in = in_dim(l), n_out = out_dim(l);
     const int64_t n = (int64_t)n_out * n_in;
     const float4 *p = reinterpret_cast<const float4 *>(a.ws + (int64_t)a.splits * wb_offset(l) + e);
+    const int64_t i = w_offset(l) + e;  // a multiple of 4: the four elements are one 16-byte word
+    // the parameter and its moments, then every slice's partial, are loaded
+    // before the first addition (slices past the count read the last one
+    // again and are not added)
+    float4 th4 = *reinterpret_cast<const float4 *>(a.theta + i);
+    float4 m4 = *reinterpret_cast<const float4 *>(a.m + i), v4 = *reinterpret_cast<const float4 *>(a.v + i);
+    float4 v[kWgradSplits];
+#pragma unroll
+    for (int q = 0; q < kWgradSplits; ++q) v[q] = p[min(q, a.splits - 1) * (n / 4)];
     float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    for (int q = 0; q < a.splits; ++q) {
-      const float4 v = p[q * (n / 4)];
-      g.x += v.x, g.y += v.y, g.z += v.z, g.w += v.w;
-    }
-    const int64_t i = w_offset(l) + e;
-    const float th[4] = {grad_step(a, i, g.x), grad_step(a, i + 1, g.y), grad_step(a, i + 2, g.z),
-                         grad_step(a, i + 3, g.w)};
+#pragma unroll
+    for (int q = 0; q < kWgradSplits; ++q)
+      if (q < a.splits) g.x += v[q].x, g.y += v[q].y, g.z += v[q].z, g.w += v[q].w;
+    *reinterpret_cast<float4 *>(a.grad + i) = g;
     if (a.adam) {
+      adam_update(a, g.x, th4.x, m4.x, v4.x);
+      adam_update(a, g.y, th4.y, m4.y, v4.y);
+      adam_update(a, g.z, th4.z, m4.z, v4.z);
+      adam_update(a, g.w, th4.w, m4.w, v4.w);
+      *reinterpret_cast<float4 *>(a.m + i) = m4;
+      *reinterpret_cast<float4 *>(a.v + i) = v4;
+      *reinterpret_cast<float4 *>(a.theta + i) = th4;
+      const float th[4] = {th4.x, th4.y, th4.z, th4.w};
       const uint16_t h[4] = {f2bf(th[0]), f2bf(th[1]), f2bf(th[2]), f2bf(th[3])};
       const int o = (int)(e / n_in), c = (int)(e % n_in);  // c % 4 == 0: the four share one lane's 8 columns
       *reinterpret_cast<uint2 *>(a.wb + wb_offset(l) + frag_offset(o, c, n_in)) =
