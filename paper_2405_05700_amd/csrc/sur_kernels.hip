@@ -799,35 +799,63 @@ __device__ __forceinline__ void bwd_epilogue(const f32x4 (&acc)[kFT][2], const u
 // Copies the workgroup's kTrainRows x n_cols bf16 tile in LDS (ld elements
 // per row) to its block of the row-block-major dst: column c of row block
 // blk at dst + (blk n_cols + c) kTrainRows, the 32 rows contiguous. Four
-// consecutive lanes share a column, each taking 8 rows as one 16-byte
-// store, so a wavefront's store covers 1 KB contiguous. If col_sum is not
-// null it also gets each column's sum over the rows: each lane adds its 8
-// rows in order, then the four lanes combine pairwise.
+// consecutive lanes share a pair of adjacent columns, each taking 8 rows:
+// eight 4-byte LDS reads (both columns of a row), byte permutes into the
+// two columns' 8-row words, and one 16-byte store per column, so a
+// wavefront's two stores cover 2 KB contiguous. Lanes of parts 2 and 3 read
+// their rows in an order rotated by four, which puts the four parts' reads
+// in different LDS banks. If col_sum is not null it also gets each column's
+// sum over the rows: each lane adds its 8 rows in order, then the four
+// lanes combine pairwise.
 __device__ __forceinline__ void store_columns(const uint16_t *s, int ld, int n_cols, uint16_t *dst, int blk,
                                               float *col_sum) {
-  static_assert(kTrainRows == 32, "four lanes of 8 rows per column");
+  static_assert(kTrainRows == 32, "four lanes of 8 rows per column pair");
   const int part = threadIdx.x & 3;
+  const int rot = 4 * (part >> 1);  // rows read in a rotated order, so the four parts hit different banks
 #pragma unroll
-  for (int c0 = 0; c0 < kHidden; c0 += kTrainThreads / 4) {
-    const int c = c0 + (int)(threadIdx.x >> 2);
+  for (int c0 = 0; c0 < kHidden; c0 += 2 * (kTrainThreads / 4)) {
+    const int c = c0 + 2 * (int)(threadIdx.x >> 2);
     if (c0 >= n_cols) break;  // uniform
     const bool live = c < n_cols;
-    uint32_t w[4];
-    float sum = 0.0f;
+    uint32_t x[8];
 #pragma unroll
-    for (int r = 0; r < 8; r += 2) {
-      const uint16_t lo = live ? s[(8 * part + r) * ld + c] : 0, hi = live ? s[(8 * part + r + 1) * ld + c] : 0;
-      w[r / 2] = lo | ((uint32_t)hi << 16);
-      sum += bf_to_f(lo);
-      sum += bf_to_f(hi);
+    for (int r = 0; r < 8; ++r)
+      x[r] = live ? *reinterpret_cast<const uint32_t *>(s + (8 * part + ((r + rot) & 7)) * ld + c) : 0u;
+    // y[m]: rows (2m + rot) & 7 and the next, low halves (column c) and high halves (column c + 1)
+    uint32_t ylo[4], yhi[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      ylo[m] = __builtin_amdgcn_perm(x[2 * m + 1], x[2 * m], 0x05040100u);
+      yhi[m] = __builtin_amdgcn_perm(x[2 * m + 1], x[2 * m], 0x07060302u);
     }
-    if (live)
+    uint32_t wl[4], wh[4];
+    // word k (rows 2k, 2k + 1) is y[(k + rot / 2) & 3]
+    const bool sw = rot != 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      wl[k] = sw ? ylo[(k + 2) & 3] : ylo[k];
+      wh[k] = sw ? yhi[(k + 2) & 3] : yhi[k];
+    }
+    if (live) {
       *reinterpret_cast<uint4 *>(dst + ((int64_t)blk * n_cols + c) * kTrainRows + 8 * part) =
-          make_uint4(w[0], w[1], w[2], w[3]);
+          make_uint4(wl[0], wl[1], wl[2], wl[3]);
+      *reinterpret_cast<uint4 *>(dst + ((int64_t)blk * n_cols + c + 1) * kTrainRows + 8 * part) =
+          make_uint4(wh[0], wh[1], wh[2], wh[3]);
+    }
     if (col_sum) {
-      sum += __shfl_xor(sum, 1, 64);  // addition is commutative: both lanes get the same value
-      sum += __shfl_xor(sum, 2, 64);
-      if (live && part == 0) col_sum[c] = sum;
+      float sl = 0.0f, sh = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        sl += bf_to_f((uint16_t)wl[k]);
+        sl += bf_to_f((uint16_t)(wl[k] >> 16));
+        sh += bf_to_f((uint16_t)wh[k]);
+        sh += bf_to_f((uint16_t)(wh[k] >> 16));
+      }
+      sl += __shfl_xor(sl, 1, 64);
+      sl += __shfl_xor(sl, 2, 64);
+      sh += __shfl_xor(sh, 1, 64);
+      sh += __shfl_xor(sh, 2, 64);
+      if (live && part == 0) col_sum[c] = sl, col_sum[c + 1] = sh;
     }
   }
 }
