@@ -376,21 +376,6 @@ __device__ __forceinline__ void adam_update(const AdamArgs &a, float g, float &t
   th -= a.lr * (m / a.c1) / (sqrtf(v / a.c2) + eps);
 }
 
-// Stores gradient element i and, with adam, takes its Adam step; returns the
-// parameter's new value.
-__device__ __forceinline__ float grad_step(const AdamArgs &a, int64_t i, float g) {
-  a.grad[i] = g;
-  float th = a.theta[i];
-  if (a.adam) {
-    float mi = a.m[i], vi = a.v[i];
-    adam_update(a, g, th, mi, vi);
-    a.m[i] = mi;
-    a.v[i] = vi;
-    a.theta[i] = th;
-  }
-  return th;
-}
-
 constexpr int kWeightBlocks = (int)((wb_count() / 4 + 255) / 256);
 constexpr int kBiasBlocks = kBiasCols / 4;
 static_assert(wb_count() % 4 == 0 && w_offset(1) % 4 == 0 && wb_offset(1) % 4 == 0,
@@ -444,10 +429,20 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const AdamArgs a) {
     }
   } else if (bid < kWeightBlocks + kBiasBlocks) {
     const int j = (bid - kWeightBlocks) * 4 + (int)(threadIdx.x >> 6);
+    const int l = j < 4 * kHidden ? j / kHidden : 4, f = j < 4 * kHidden ? j % kHidden : j - 4 * kHidden;
+    const int64_t i = b_offset(l) + f;
+    // the parameter and its moments are loaded before the parts, so both
+    // wait for one round trip
+    float th = a.theta[i], m = a.m[i], v = a.v[i];
     const float g = wave_ordered_sum(a.col_part + j, a.n_blocks, kBiasCols);
     if ((threadIdx.x & 63) == 0) {
-      const int l = j < 4 * kHidden ? j / kHidden : 4, f = j < 4 * kHidden ? j % kHidden : j - 4 * kHidden;
-      grad_step(a, b_offset(l) + f, g);
+      a.grad[i] = g;
+      if (a.adam) {
+        adam_update(a, g, th, m, v);
+        a.m[i] = m;
+        a.v[i] = v;
+        a.theta[i] = th;
+      }
     }
   } else if (threadIdx.x < 64) {
     const double sum = wave_ordered_sum(a.loss_part, a.n_blocks, 1);
