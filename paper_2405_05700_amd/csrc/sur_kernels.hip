@@ -677,7 +677,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 // Each layer's weight fragments are loaded into VGPRs two layers ahead
 // (two fragment sets alternate), from the tile-major bf16 copies, so a
 // wavefront's fragment load reads 1 KB contiguous; the barriers order LDS
-// only, so those loads stay in flight across them. After each layer the
+// only, so those loads stay in flight across them. Layers alternate between
+// two activation buffers (a layer reads one and writes the other), so one
+// barrier per layer suffices: the buffer a layer writes was last read two
+// layers before, ahead of the previous layer's barrier. After each layer the
 // workgroup copies the layer's output from LDS to its block of a
 // row-block-major global array, where the weight-gradient pass reads it;
 // the copies of dY and dZ_l also sum each column over the 32 rows (the
@@ -859,7 +862,8 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
   extern __shared__ __align__(16) uint16_t lds[];
   float4 *s_tab = reinterpret_cast<float4 *>(lds);                      // kCdfN + 1 table entries
   uint16_t *s_act = lds + (kCdfN + 1) * 8;                               // kTrainRows x kTrainLd bf16
-  uint16_t *s_gp = s_act + kTrainRows * kTrainLd;                        // 4 layers x kTrainRows x kTrainLd FP16
+  uint16_t *s_act2 = s_act + kTrainRows * kTrainLd;                      // the other activation buffer
+  uint16_t *s_gp = s_act2 + kTrainRows * kTrainLd;                       // 4 layers x kTrainRows x kTrainLd FP16
   uint16_t *s_dy = s_gp + 4 * kTrainRows * kTrainLd;                     // kTrainRows x kDyLd bf16
   float *s_lab = reinterpret_cast<float *>(s_dy + kTrainRows * kDyLd);   // kTrainRows x 8
   double *s_loss = reinterpret_cast<double *>(s_lab + kTrainRows * 8);  // kTrainRows
@@ -927,13 +931,11 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
   f32x4 acc[kFT][2];
   rows_mma<kS0>(acc, fa, s_act, kTrainLd, lane);
   load_w<kS, kHidden>(fa, a.wb[2], lane, wave);
-  lds_barrier();  // every wavefront has read the layer's input
-  fwd_epilogue(acc, s_bias, s_tab, s_act, s_gp, lane, wave);
+  fwd_epilogue(acc, s_bias, s_tab, s_act2, s_gp, lane, wave);
   lds_barrier();  // the layer's output is complete
-  store_columns(s_act, kTrainLd, kHidden, a.HT[0], blk, nullptr);
-  rows_mma<kS>(acc, fb, s_act, kTrainLd, lane);
+  store_columns(s_act2, kTrainLd, kHidden, a.HT[0], blk, nullptr);
+  rows_mma<kS>(acc, fb, s_act2, kTrainLd, lane);
   load_w<kS, kHidden>(fb, a.wb[3], lane, wave);
-  lds_barrier();
   fwd_epilogue(acc, s_bias + kHidden, s_tab, s_act, s_gp + kLayerLds, lane, wave);
   lds_barrier();
   store_columns(s_act, kTrainLd, kHidden, a.HT[1], blk, nullptr);
@@ -944,13 +946,11 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
 #pragma unroll
     for (int s = 0; s < kS; ++s) fa.v[2 + s / 2][s % 2] = load8(a.wb[4] + lane * 8 + s * 512);
   }
+  fwd_epilogue(acc, s_bias + 2 * kHidden, s_tab, s_act2, s_gp + 2 * kLayerLds, lane, wave);
   lds_barrier();
-  fwd_epilogue(acc, s_bias + 2 * kHidden, s_tab, s_act, s_gp + 2 * kLayerLds, lane, wave);
-  lds_barrier();
-  store_columns(s_act, kTrainLd, kHidden, a.HT[2], blk, nullptr);
-  rows_mma<kS>(acc, fb, s_act, kTrainLd, lane);
+  store_columns(s_act2, kTrainLd, kHidden, a.HT[2], blk, nullptr);
+  rows_mma<kS>(acc, fb, s_act2, kTrainLd, lane);
   load_w<kS, kHidden>(fb, a.wt[3], lane, wave);
-  lds_barrier();
   fwd_epilogue(acc, s_bias + 3 * kHidden, s_tab, s_act, s_gp + 3 * kLayerLds, lane, wave);
   lds_barrier();
   store_columns(s_act, kTrainLd, kHidden, a.HT[3], blk, nullptr);
@@ -985,25 +985,22 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
   }
   store_columns(s_dy, kDyLd, kOutPad, a.dYT, blk, col_part + 4 * kHidden);
 
-  // backward; every read of H_3 in s_act happened before the barrier above
+  // backward; every read of H_2 in s_act2 happened before the last forward barrier
   rows_mma<kSOut>(acc, fa, s_dy, kDyLd, lane);  // dH_3^T = W_4^T dY^T
   load_w<kS, kHidden>(fa, a.wt[2], lane, wave);
-  bwd_epilogue(acc, s_gp + 3 * kLayerLds, s_act, lane, wave);
+  bwd_epilogue(acc, s_gp + 3 * kLayerLds, s_act2, lane, wave);
   lds_barrier();
-  store_columns(s_act, kTrainLd, kHidden, a.dZT[3], blk, col_part + 3 * kHidden);
-  rows_mma<kS>(acc, fb, s_act, kTrainLd, lane);  // dH_2^T = W_3^T dZ_3^T
+  store_columns(s_act2, kTrainLd, kHidden, a.dZT[3], blk, col_part + 3 * kHidden);
+  rows_mma<kS>(acc, fb, s_act2, kTrainLd, lane);  // dH_2^T = W_3^T dZ_3^T
   load_w<kS, kHidden>(fb, a.wt[1], lane, wave);
-  lds_barrier();
   bwd_epilogue(acc, s_gp + 2 * kLayerLds, s_act, lane, wave);
   lds_barrier();
   store_columns(s_act, kTrainLd, kHidden, a.dZT[2], blk, col_part + 2 * kHidden);
   rows_mma<kS>(acc, fa, s_act, kTrainLd, lane);  // dH_1^T = W_2^T dZ_2^T
+  bwd_epilogue(acc, s_gp + kLayerLds, s_act2, lane, wave);
   lds_barrier();
-  bwd_epilogue(acc, s_gp + kLayerLds, s_act, lane, wave);
-  lds_barrier();
-  store_columns(s_act, kTrainLd, kHidden, a.dZT[1], blk, col_part + kHidden);
-  rows_mma<kS>(acc, fb, s_act, kTrainLd, lane);  // dH_0^T = W_1^T dZ_1^T
-  lds_barrier();
+  store_columns(s_act2, kTrainLd, kHidden, a.dZT[1], blk, col_part + kHidden);
+  rows_mma<kS>(acc, fb, s_act2, kTrainLd, lane);  // dH_0^T = W_1^T dZ_1^T
   bwd_epilogue(acc, s_gp, s_act, lane, wave);
   lds_barrier();
   store_columns(s_act, kTrainLd, kHidden, a.dZT[0], blk, col_part);
@@ -1019,7 +1016,7 @@ int blocks_for(int64_t n, int threads) { return (int)((n + threads - 1) / thread
 }  // namespace
 
 size_t train_lds_bytes() {
-  return sizeof(float4) * (kCdfN + 1) + sizeof(uint16_t) * (5 * kTrainRows * kTrainLd + kTrainRows * kDyLd) +
+  return sizeof(float4) * (kCdfN + 1) + sizeof(uint16_t) * (6 * kTrainRows * kTrainLd + kTrainRows * kDyLd) +
          sizeof(float) * kTrainRows * 8 + sizeof(double) * kTrainRows + sizeof(float) * (4 * kHidden + kOutPad);
 }
 
