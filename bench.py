@@ -28,11 +28,11 @@ sys.path.insert(0, ROOT)
 # the issue rates measured on gfx950 relative to v_fma_f32. Counts of the
 # arithmetic each unit needs in the FP32 formulation, in gfx950 operations
 # (a three-input xor is one v_bitop3_b32):
-SLOTS_PER_STEP = 254        # one propagation step (Philox block 101 of it)
+SLOTS_PER_STEP = 242        # one propagation step (Philox block 101 of it)
 SLOTS_PER_CROSSING = 28     # each extra layer of the layer walk
 SLOTS_PER_DOM_TEST = 32     # each ray-sphere test
 SLOTS_PER_PHOTON = 185      # emission pass (Philox block 0, cone rotation, setup)
-FLOPS_PER_STEP = 90         # FP32 FLOPs of a step (FMA = 2), for the FLOP form
+FLOPS_PER_STEP = 83         # FP32 FLOPs of a step (FMA = 2), for the FLOP form
 # Peak: MI355X FP32 vector 157.3 TFLOP/s = 256 CUs x 128 FP32 lanes/clock x
 # 2 FLOP per FMA x 2.4 GHz, i.e. 78.65e12 full-rate lane slots/s.
 PEAK_FP32_FLOPS = 157.3e12

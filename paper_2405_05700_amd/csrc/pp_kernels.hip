@@ -129,6 +129,11 @@ __device__ __forceinline__ void test_string(const DevString &st, const float4 *_
                                             const float2 *zid, const Segment &s, float radius, float r2,
                                             float &best_t, uint32_t &best_id, uint32_t &tests) {
   const float dx = st.xy_reach_z0.x - s.px, dy = st.xy_reach_z0.y - s.py;
+  // No point of the step is within reach if its start is farther than
+  // len + reach from the axis (with a margin far above rounding, so this
+  // never drops a step the test below would keep).
+  const float rr = __builtin_fmaf(s.len + st.xy_reach_z0.z, 1.0f / 1024.0f, s.len + st.xy_reach_z0.z) + 1e-3f;
+  if (dx * dx + dy * dy > rr * rr) return;
   // closest approach of the projected segment to the axis: t in [0, len]
   // along v (a vertical segment stays at its start point)
   const float hh = s.vx * s.vx + s.vy * s.vy;
