@@ -1037,6 +1037,8 @@ hipError_t launch_wgrad(const WgradArgs &g, hipStream_t s) {
 }
 
 hipError_t launch_reduce_adam(const AdamArgs &a, hipStream_t s) {
+  // the kernel reads slices 0 .. splits - 1 and holds at most kWgradSplits of them
+  if (a.splits <= 0 || a.splits > kWgradSplits || a.n_blocks <= 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_reduce_adam, dim3(kWeightBlocks + kBiasBlocks + 1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
