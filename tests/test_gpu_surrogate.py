@@ -231,6 +231,57 @@ def test_fused_expected_hits_equal_pair_sums(mods):
     assert np.isfinite(per_pair).all() and (per_pair >= 0).all()
 
 
+def test_inference_at_full_size_on_sampled_pairs(mods):
+    """The benchmarked inference workload, 1e5 full-detector segments x 5160
+    modules (5.16e8 pairs, 4 031 250 workgroups in one launch, as the bench
+    times it): the per-module sums equal the sums of the per-pair
+    expectations, and 2048 sampled pairs (the first and the last among them)
+    match the oracle's network on the oracle's own features within the
+    forward bounds."""
+    pp, surrogate, M = mods
+    import torch
+    w = W.full_detector(n_sources=100_000, photons_per_source=1, seed=303)
+    ctx = pp.Context(0, seed=0)
+    ctx.load_workload(w)
+    b = ctx.submit(w.sources)
+    sur = surrogate.Surrogate(ctx, seed=1)
+    params0 = M.init_params(7)
+    for _, bias in params0:
+        bias[:] = np.random.default_rng(2).normal(0, 0.05, bias.shape)
+    params0[-1][1][M.OUT_REAL:] = 0
+    theta = flatten(M, params0)
+    sur.set_params(theta)
+    sums = sur.expected_hits(b).cpu().numpy()
+    torch.cuda.synchronize()
+    n_dom = len(w.doms)
+    per_pair = sur.predict_pairs(b, len(w.sources))
+    assert per_pair.shape == (100_000, n_dom) and np.isfinite(per_pair).all() and (per_pair >= 0).all()
+    ref = per_pair.sum(0, dtype=np.float64)
+    say("full size: fused sums vs pair sums, max rel", np.max(np.abs(sums - ref) / np.maximum(ref, 1e-300)))
+    assert np.allclose(sums, ref, rtol=1e-6, atol=1e-300)
+    n_pairs = per_pair.size
+    idx = np.concatenate([[0, n_pairs - 1], np.random.default_rng(5).choice(n_pairs, 2046, replace=False)])
+    src, dom = idx // n_dom, idx % n_dom
+    X, mub, _ = M.pair_features(w, src, dom)
+    params = unflatten(M, theta)
+    for q in params:
+        q[0] = bf16_round(q[0])
+    Y, _ = M.forward(params, bf16_round(X))
+    nph = w.sources["n_photons"][src].astype(float)
+    mu_ref = nph * mub * np.exp(Y[:, 0])
+    mu_gpu = per_pair.ravel()[idx].astype(np.float64)
+    # expectations far below float32's normal range are compared as near 0
+    big = mu_ref > 1e-30
+    assert big.mean() > 0.9 and (mu_gpu[~big] <= 1e-29).all()
+    rel = np.abs(mu_gpu[big] - mu_ref[big]) / mu_ref[big]
+    say("full size, sampled pairs:", int(big.sum()), "median rel", np.median(rel), "p99", np.quantile(rel, 0.99),
+        "max", rel.max())
+    assert np.median(rel) < FWD_MEDIAN and np.quantile(rel, 0.99) < FWD_P99
+    del per_pair
+    sur.close()
+    ctx.close()
+
+
 def test_far_pair_sampling_follows_rule_and_oracle(mods):
     """Training-pair sampling on the device: the kept rows are exactly the
     pairs the rule keeps (module within 150 m of the segment centre, or
