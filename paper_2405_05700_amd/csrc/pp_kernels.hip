@@ -86,6 +86,10 @@ __device__ __forceinline__ unsigned long long first_lane_u64(unsigned long long 
   return ((unsigned long long)hi << 32) | lo;
 }
 
+__device__ __forceinline__ float first_lane_f32(float v) {
+  return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
+}
+
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -243,9 +247,14 @@ k_propagate(const PropagateArgs a) {
   const uint32_t lane = __lane_id();
   const float r2 = a.radius2;
 
-  // wave-uniform queue state and counters
+  // wave-uniform queue state and counters; the chunk's source record is
+  // read once per chunk into wave-uniform registers, so handing photons to
+  // free lanes reads no memory
   uint32_t ch_src = 0, ch_left = 0, countdown = 0;
   unsigned long long ch_local = 0;
+  unsigned long long cs_first = 0, cs_seq = 0;
+  uint32_t cs_event = 0, cs_particle = 0;
+  float cs_px = 0, cs_py = 0, cs_pz = 0, cs_t = 0, cs_vx = 0, cs_vy = 0, cs_vz = 1, cs_elen = 0, cs_eom = -1;
   bool more = true;
   uint32_t n_photons = 0, n_hits = 0, n_abs = 0, n_cap = 0, n_esc = 0;
 
@@ -319,31 +328,43 @@ k_propagate(const PropagateArgs a) {
           ch_src = __builtin_amdgcn_readfirstlane(e.src);
           ch_left = __builtin_amdgcn_readfirstlane(e.count);
           ch_local = first_lane_u64(e.local);
+          // The lanes start at the source's reference point on its axis; the
+          // emission pass moves them along the track and turns them onto the
+          // emission cone (or the sphere, for a point source).
+          const DevSource &S = a.sources[ch_src];
+          const bool point = __builtin_amdgcn_readfirstlane(S.ids.x) == 0;
+          cs_first = first_lane_u64(S.first_index);
+          if (kRecords) cs_seq = first_lane_u64(S.seq_base);
+          cs_event = __builtin_amdgcn_readfirstlane(S.ids.y);
+          cs_particle = __builtin_amdgcn_readfirstlane(S.ids.z);
+          cs_px = first_lane_f32(S.pos_t0.x);
+          cs_py = first_lane_f32(S.pos_t0.y);
+          cs_pz = first_lane_f32(S.pos_t0.z);
+          cs_t = first_lane_f32(S.pos_t0.w);
+          cs_vx = first_lane_f32(S.dir_len.x);
+          cs_vy = first_lane_f32(S.dir_len.y);
+          cs_vz = first_lane_f32(S.dir_len.z);
+          cs_elen = point ? 0.0f : first_lane_f32(S.dir_len.w);
+          cs_eom = point ? -1.0f : first_lane_f32(S.emit.x);
         }
         const uint32_t take = min((uint32_t)__popcll(free_mask), ch_left);
         const uint32_t rank = lane_rank(free_mask);
         if (((free_mask >> lane) & 1ull) && rank < take) {
-          // The chunk's source is uniform across the wavefront. The lane
-          // starts at the source's reference point on its axis; the
-          // emission pass moves it along the track and turns it onto the
-          // emission cone (or the sphere, for a point source).
-          const DevSource &S = a.sources[ch_src];
           const unsigned long long local = ch_local + rank;
-          pidx = S.first_index + local;
+          pidx = cs_first + local;
           if (kWave) src = ch_src;
-          if (kRecords) seq = S.seq_base + local;
-          event = S.ids.y;
-          particle = S.ids.z;
-          const bool point = S.ids.x == 0;
-          px = S.pos_t0.x;
-          py = S.pos_t0.y;
-          pz = S.pos_t0.z;
-          t = S.pos_t0.w;
-          vx = S.dir_len.x;
-          vy = S.dir_len.y;
-          vz = S.dir_len.z;
-          elen = point ? 0.0f : S.dir_len.w;
-          eom = point ? -1.0f : S.emit.x;
+          if (kRecords) seq = cs_seq + local;
+          event = cs_event;
+          particle = cs_particle;
+          px = cs_px;
+          py = cs_py;
+          pz = cs_pz;
+          t = cs_t;
+          vx = cs_vx;
+          vy = cs_vy;
+          vz = cs_vz;
+          elen = cs_elen;
+          eom = cs_eom;
           iter = 0;
           ncross = 0;
           fate = kFateCapped;
