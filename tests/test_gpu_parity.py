@@ -171,6 +171,31 @@ def test_launch_configuration_invariance(pp):
         assert (rec == base).all(), launch
 
 
+def test_launch_invariance_with_many_sources(pp):
+    """Records and hits are bit-identical across launch shapes when the
+    chunks switch between many sources of both kinds and of very different
+    sizes (with chunks of one photon, every photon starts a new chunk and a
+    new source record)."""
+    w = W.full_detector(n_sources=40, photons_per_source=1, seed=21).with_radius(2.0)
+    src = w.sources.copy()
+    src["n_photons"] = np.random.default_rng(4).choice([1, 7, 300, 1000], size=len(src))
+    src["type"][::3] = W.SOURCE_POINT
+    src["event_id"] = np.arange(len(src)) // 2
+    src["first_photon_index"] = np.cumsum(src["n_photons"]) - src["n_photons"]
+    w = w.with_sources(src)
+    base = gpu_run(pp, w)
+    base_hits = np.sort(base["hits"], order=["event_id", "photon_index"])
+    assert len(base_hits) > 0
+    for launch in [dict(block_size=64, chunk_size=1, grid_blocks=1), dict(block_size=128, chunk_size=3, refill_interval=1),
+                   dict(block_size=1024, chunk_size=4096), dict(block_size=256, chunk_size=64, grid_blocks=2)]:
+        g = gpu_run(pp, w, launch=launch)
+        say("many sources, launch", launch)
+        assert (g["rec"] == base["rec"]).all(), launch
+        # the benchmarked variant (no records) on the same launch
+        h = gpu_run(pp, w, records=False, launch=launch)["hits"]
+        assert np.array_equal(np.sort(h, order=["event_id", "photon_index"]), base_hits), launch
+
+
 def test_seed_and_step_cap(pp, oracle):
     """Other seeds and small step caps follow the oracle; capped photons
     stop after exactly step_cap steps."""
