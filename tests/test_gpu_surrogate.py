@@ -180,9 +180,10 @@ def test_forward_and_gradients_match_oracle(mods, small_set):
 def test_gradients_on_ragged_unaligned_minibatches(mods, small_set):
     """Minibatches that start inside a 32-row block and end in a ragged tail
     give the oracle's loss and gradients too: 1001 rows from row 5037 (padded
-    to 1024: 32 row blocks, 16 weight-gradient slices of two steps each) and
-    37 rows from row 19990 (one 64-row tile: two row blocks, the second all
-    padding past row 32)."""
+    to 1024: 32 row blocks, 16 weight-gradient slices of two steps each), 37
+    rows from row 19990 (one 64-row tile: two row blocks, the second all
+    padding past row 32), a single row (one row block, one slice) and the
+    set's last three rows."""
     pp, surrogate, M = mods
     w, ctx, b, sur = small_set
     theta = flatten(M, M.init_params(3))
@@ -190,7 +191,7 @@ def test_gradients_on_ragged_unaligned_minibatches(mods, small_set):
     P = sur.training_size()
     rows = sur.training_rows(0, P)
     nph = np.repeat(w.sources["n_photons"].astype(float), len(w.doms))
-    for first, count in ((5037, 1001), (19990, 37)):
+    for first, count in ((5037, 1001), (19990, 37), (0, 1), (P - 3, 3)):
         loss, grad = sur.loss_grad(first, count)
         X, params = oracle_on_gpu_inputs(M, rows, theta, first, count)
         Y, cache = M.forward(params, X)
@@ -229,6 +230,27 @@ def test_fused_expected_hits_equal_pair_sums(mods):
     say("fused sums vs pair sums: max rel", np.max(np.abs(sums - ref) / np.maximum(ref, 1e-300)))
     assert np.allclose(sums, ref, rtol=1e-6, atol=1e-300)
     assert np.isfinite(per_pair).all() and (per_pair >= 0).all()
+
+
+def test_training_calls_refuse_bad_row_ranges(mods, small_set):
+    """Row ranges outside the training set, empty minibatches, batch sizes
+    that are zero or not a multiple of 64 and invalid learning rates are
+    refused with an error, and a refused call leaves the parameters as they
+    were."""
+    pp, surrogate, M = mods
+    w, ctx, b, sur = small_set
+    theta = flatten(M, M.init_params(4))
+    sur.set_params(theta)
+    P = sur.training_size()
+    for first, count in ((0, 0), (P - 2, 5), (P, 1)):
+        with pytest.raises(pp.PPError):
+            sur.loss_grad(first, count)
+        with pytest.raises(pp.PPError):
+            sur.train_step(first, count, 1e-3)
+    for kw in (dict(batch_size=0), dict(batch_size=100), dict(lr=-1e-3), dict(lr=float("nan"))):
+        with pytest.raises(pp.PPError):
+            sur.train(epochs=1, **kw)
+    assert np.array_equal(sur.get_params(), theta)
 
 
 def test_inference_at_full_size_on_sampled_pairs(mods):
