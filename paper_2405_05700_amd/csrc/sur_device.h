@@ -141,7 +141,7 @@ struct TrainArgs {
   const uint16_t *wt[kLayers];     // bf16 W^T (in x out), tile-major
   const float *b[kLayers];
   uint16_t *XT, *HT[4], *dYT, *dZT[4];  // bf16, row-block-major: block b's column c at (b n_cols + c) kTrainRows
-  float *col_part;                 // (M / kTrainRows) x kBiasCols
+  float *col_part;                 // kBiasCols x (M / kTrainRows): a bias column's row-block parts contiguous
   double *loss_part;               // M / kTrainRows
 };
 struct WgradArgs {

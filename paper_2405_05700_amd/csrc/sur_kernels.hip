@@ -434,7 +434,7 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const AdamArgs a) {
     // the parameter and its moments are loaded before the parts, so both
     // wait for one round trip
     float th = a.theta[i], m = a.m[i], v = a.v[i];
-    const float g = wave_ordered_sum(a.col_part + j, a.n_blocks, kBiasCols);
+    const float g = wave_ordered_sum(a.col_part + (int64_t)j * a.n_blocks, a.n_blocks, 1);
     if ((threadIdx.x & 63) == 0) {
       a.grad[i] = g;
       if (a.adam) {
@@ -803,10 +803,10 @@ __device__ __forceinline__ void bwd_epilogue(const f32x4 (&acc)[kFT][2], const u
 // wavefront's two stores cover 2 KB contiguous. Lanes of parts 2 and 3 read
 // their rows in an order rotated by four, which puts the four parts' reads
 // in different LDS banks. If col_sum is not null it also gets each column's
-// sum over the rows: each lane adds its 8 rows in order, then the four
-// lanes combine pairwise.
+// sum over the rows, column c's at col_sum[c cs_stride]: each lane adds its
+// 8 rows in order, then the four lanes combine pairwise.
 __device__ __forceinline__ void store_columns(const uint16_t *s, int ld, int n_cols, uint16_t *dst, int blk,
-                                              float *col_sum) {
+                                              float *col_sum, int cs_stride) {
   static_assert(kTrainRows == 32, "four lanes of 8 rows per column pair");
   const int part = threadIdx.x & 3;
   const int rot = 4 * (part >> 1);  // rows read in a rotated order, so the four parts hit different banks
@@ -853,7 +853,7 @@ __device__ __forceinline__ void store_columns(const uint16_t *s, int ld, int n_c
       sl += __shfl_xor(sl, 2, 64);
       sh += __shfl_xor(sh, 1, 64);
       sh += __shfl_xor(sh, 2, 64);
-      if (live && part == 0) col_sum[c] = sl, col_sum[c + 1] = sh;
+      if (live && part == 0) col_sum[(int64_t)c * cs_stride] = sl, col_sum[(int64_t)(c + 1) * cs_stride] = sh;
     }
   }
 }
@@ -871,7 +871,8 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int blk = blockIdx.x;
   const int64_t i0 = (int64_t)blk * kTrainRows;
-  float *col_part = a.col_part + (int64_t)blk * kBiasCols;
+  const int nb = a.M / kTrainRows;           // row blocks: the bias parts of column c are col_part[c nb ..]
+  float *col_part = a.col_part + blk;
   constexpr int kLayerLds = kTrainRows * kTrainLd;
   constexpr int kS = kHidden / 32, kS0 = kInPad / 32, kSOut = kOutPad / 32;
   static_assert(kS0 <= kS && kSOut <= kS, "weight fragments fit the hidden layers' buffer");
@@ -925,7 +926,7 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
   }
   static_assert(3 * kTrainThreads > kCdfN && 3 * kTrainThreads >= 4 * kHidden + kOutPad, "three rounds cover both");
   lds_barrier();
-  store_columns(s_act, kTrainLd, kInPad, a.XT, blk, nullptr);
+  store_columns(s_act, kTrainLd, kInPad, a.XT, blk, nullptr, 0);
 
   // forward
   f32x4 acc[kFT][2];
@@ -933,12 +934,12 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
   load_w<kS, kHidden>(fa, a.wb[2], lane, wave);
   fwd_epilogue(acc, s_bias, s_tab, s_act2, s_gp, lane, wave);
   lds_barrier();  // the layer's output is complete
-  store_columns(s_act2, kTrainLd, kHidden, a.HT[0], blk, nullptr);
+  store_columns(s_act2, kTrainLd, kHidden, a.HT[0], blk, nullptr, 0);
   rows_mma<kS>(acc, fb, s_act2, kTrainLd, lane);
   load_w<kS, kHidden>(fb, a.wb[3], lane, wave);
   fwd_epilogue(acc, s_bias + kHidden, s_tab, s_act, s_gp + kLayerLds, lane, wave);
   lds_barrier();
-  store_columns(s_act, kTrainLd, kHidden, a.HT[1], blk, nullptr);
+  store_columns(s_act, kTrainLd, kHidden, a.HT[1], blk, nullptr, 0);
   rows_mma<kS>(acc, fa, s_act, kTrainLd, lane);
   load_w<kSOut, kOutPad>(fa, a.wt[4], lane, wave);  // the first backward product
   if (wave < 2) {  // and the output layer's (W4 rows 0..15, tile 0) in the set's free slots
@@ -948,12 +949,12 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
   }
   fwd_epilogue(acc, s_bias + 2 * kHidden, s_tab, s_act2, s_gp + 2 * kLayerLds, lane, wave);
   lds_barrier();
-  store_columns(s_act2, kTrainLd, kHidden, a.HT[2], blk, nullptr);
+  store_columns(s_act2, kTrainLd, kHidden, a.HT[2], blk, nullptr, 0);
   rows_mma<kS>(acc, fb, s_act2, kTrainLd, lane);
   load_w<kS, kHidden>(fb, a.wt[3], lane, wave);
   fwd_epilogue(acc, s_bias + 3 * kHidden, s_tab, s_act, s_gp + 3 * kLayerLds, lane, wave);
   lds_barrier();
-  store_columns(s_act, kTrainLd, kHidden, a.HT[3], blk, nullptr);
+  store_columns(s_act, kTrainLd, kHidden, a.HT[3], blk, nullptr, 0);
 
   // output layer (outputs 0..15 of W4) for rows 16 w .. + 16, w = 0, 1; lane
   // l < 16 then holds outputs 0..3 of row 16 w + l and takes its loss
@@ -983,27 +984,27 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_rows(const TrainArgs a)
     for (int off = 16; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
     if (lane == 0) a.loss_part[blk] = sum;
   }
-  store_columns(s_dy, kDyLd, kOutPad, a.dYT, blk, col_part + 4 * kHidden);
+  store_columns(s_dy, kDyLd, kOutPad, a.dYT, blk, col_part + (int64_t)4 * kHidden * nb, nb);
 
   // backward; every read of H_2 in s_act2 happened before the last forward barrier
   rows_mma<kSOut>(acc, fa, s_dy, kDyLd, lane);  // dH_3^T = W_4^T dY^T
   load_w<kS, kHidden>(fa, a.wt[2], lane, wave);
   bwd_epilogue(acc, s_gp + 3 * kLayerLds, s_act2, lane, wave);
   lds_barrier();
-  store_columns(s_act2, kTrainLd, kHidden, a.dZT[3], blk, col_part + 3 * kHidden);
+  store_columns(s_act2, kTrainLd, kHidden, a.dZT[3], blk, col_part + (int64_t)3 * kHidden * nb, nb);
   rows_mma<kS>(acc, fb, s_act2, kTrainLd, lane);  // dH_2^T = W_3^T dZ_3^T
   load_w<kS, kHidden>(fb, a.wt[1], lane, wave);
   bwd_epilogue(acc, s_gp + 2 * kLayerLds, s_act, lane, wave);
   lds_barrier();
-  store_columns(s_act, kTrainLd, kHidden, a.dZT[2], blk, col_part + 2 * kHidden);
+  store_columns(s_act, kTrainLd, kHidden, a.dZT[2], blk, col_part + (int64_t)2 * kHidden * nb, nb);
   rows_mma<kS>(acc, fa, s_act, kTrainLd, lane);  // dH_1^T = W_2^T dZ_2^T
   bwd_epilogue(acc, s_gp + kLayerLds, s_act2, lane, wave);
   lds_barrier();
-  store_columns(s_act2, kTrainLd, kHidden, a.dZT[1], blk, col_part + kHidden);
+  store_columns(s_act2, kTrainLd, kHidden, a.dZT[1], blk, col_part + (int64_t)kHidden * nb, nb);
   rows_mma<kS>(acc, fb, s_act2, kTrainLd, lane);  // dH_0^T = W_1^T dZ_1^T
   bwd_epilogue(acc, s_gp, s_act, lane, wave);
   lds_barrier();
-  store_columns(s_act, kTrainLd, kHidden, a.dZT[0], blk, col_part);
+  store_columns(s_act, kTrainLd, kHidden, a.dZT[0], blk, col_part, nb);
 }
 
 __global__ void k_zero_u64(unsigned long long *p, int64_t n) {
