@@ -331,6 +331,28 @@ def test_chromatic_optics_per_photon(pp, oracle):
     check_conservation(g["stats"], w.n_photons)
 
 
+def test_chromatic_full_detector_per_photon(pp, oracle):
+    """Wavelength-dependent optics and acceptance in the full detector (the
+    171 dusty layers, 1000 Cherenkov segments, 2000 photons each): every
+    photon follows its FP64 twin, and the benchmarked kernel variant (no
+    records) gives the same hits and weights as the recording one."""
+    w = W.full_detector(n_sources=1000, photons_per_source=2000)
+    src = w.sources.copy()
+    src["lambda_min_nm"], src["lambda_max_nm"] = 300.0, 600.0
+    w = W.dataclasses.replace(w.with_sources(src), chromatic=(400.0, 1.5, 0.9),
+                              acceptance={"l0": 300.0, "dl": 150.0, "table": [0.5, 1.5, 1.0], "poly": [0.2, 0.8]})
+    g = gpu_run(pp, w)
+    ref = oracle.run(w, threads=THREADS, dom_mode=1)  # per-string pre-filter, pinned against brute force
+    frac, ok = agreement(g["rec"], ref)
+    lam_ok = np.abs(g["rec"]["wavelength_nm"] - ref.wavelength) <= 1e-5 * ref.wavelength
+    say("chromatic full detector per-photon agreement", frac, "wavelengths", lam_ok.mean(), "hits", len(g["hits"]))
+    assert frac >= MIN_AGREE and lam_ok.mean() >= MIN_AGREE
+    check_conservation(g["stats"], w.n_photons)
+    prod = gpu_run(pp, w, records=False)
+    order = ["event_id", "photon_index"]
+    assert np.array_equal(np.sort(prod["hits"], order=order), np.sort(g["hits"], order=order))
+
+
 def test_hit_weights_match_oracle(pp, oracle):
     """Hit weights (acceptance at the wavelength x polynomial in the cosine
     of incidence) agree with the oracle's for the same photons."""
