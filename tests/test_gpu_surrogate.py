@@ -182,8 +182,10 @@ def test_gradients_on_ragged_unaligned_minibatches(mods, small_set):
     give the oracle's loss and gradients too: 1001 rows from row 5037 (padded
     to 1024: 32 row blocks, 16 weight-gradient slices of two steps each), 37
     rows from row 19990 (one 64-row tile: two row blocks, the second all
-    padding past row 32), a single row (one row block, one slice) and the
-    set's last three rows."""
+    padding past row 32), a single row (one row block, one slice), the
+    set's last three rows, and the benchmarked minibatch of 8192 rows (256
+    row blocks, 16 slices of 16 steps: four full rounds of the load
+    ring)."""
     pp, surrogate, M = mods
     w, ctx, b, sur = small_set
     theta = flatten(M, M.init_params(3))
@@ -191,7 +193,7 @@ def test_gradients_on_ragged_unaligned_minibatches(mods, small_set):
     P = sur.training_size()
     rows = sur.training_rows(0, P)
     nph = np.repeat(w.sources["n_photons"].astype(float), len(w.doms))
-    for first, count in ((5037, 1001), (19990, 37), (0, 1), (P - 3, 3)):
+    for first, count in ((5037, 1001), (19990, 37), (0, 1), (P - 3, 3), (100, 8192)):
         loss, grad = sur.loss_grad(first, count)
         X, params = oracle_on_gpu_inputs(M, rows, theta, first, count)
         Y, cache = M.forward(params, X)
