@@ -118,8 +118,11 @@ def test_graph_replays_match_eager(pp):
 
 def test_full_uneven_spectrum_conserves_photons(pp):
     """All 4096 events of the power-law spectrum (about 1e7 photons) in one
-    launch: every photon is processed exactly once."""
+    launch: every photon is processed exactly once, the totals of steps,
+    layer crossings and hits match the oracle's over all photons, and every
+    GPU hit is the oracle's hit for the same photon."""
     import torch
+    from oracle import pyoracle
     w = W.uneven_events(4096, seed=0)
     n = w.n_photons
     assert 5e6 < n < 2e7
@@ -135,6 +138,24 @@ def test_full_uneven_spectrum_conserves_photons(pp):
     assert len(hits) == st["hits"]
     assert set(np.unique(hits["event_id"])) <= set(w.sources["event_id"].tolist())
     torch.cuda.synchronize()
+    ref = pyoracle.run(w, threads=THREADS, records=False, dom_mode=1)
+    c = ref.counters
+    say("uneven totals gpu/oracle: steps", st["iterations"], c["iterations"], "crossings", st["layer_crossings"],
+        c["crossings"], "hits", st["hits"], c["hits"])
+    assert c["photons"] == n
+    assert abs(st["iterations"] - c["iterations"]) <= 1e-4 * c["iterations"]
+    assert abs(st["layer_crossings"] - c["crossings"]) <= 1e-4 * c["crossings"]
+    assert abs(st["hits"] - c["hits"]) <= 0.002 * c["hits"] + 2
+    ids = w.sources["event_id"].astype(np.int64)
+    order = np.argsort(ids)
+    src = order[np.searchsorted(ids[order], hits["event_id"].astype(np.int64))]
+    local = hits["photon_index"].astype(np.int64) - w.sources["first_photon_index"][src].astype(np.int64)
+    sel = pyoracle.run(w, sel_src=src.astype(np.uint64), sel_local=local.astype(np.uint64), dom_mode=1,
+                       threads=THREADS)
+    ok = (sel.fate == 1) & (sel.dom == hits["dom_id"]) & \
+         (np.abs(hits["time_ns"] - sel.t) <= 1e-4 * np.abs(sel.t) + 1e-6)
+    say("uneven: GPU hits confirmed by the oracle", int(ok.sum()), "of", len(ok))
+    assert len(ok) > 100 and ok.mean() >= 0.999
 
 
 def test_reused_batch_memory_gives_identical_results(pp):
