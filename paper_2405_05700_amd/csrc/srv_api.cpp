@@ -203,9 +203,32 @@ bool admit(pp_server *s) {
         d.local = l;
       }
     }
-    if (e == hipSuccess) e = upload_range(s->d_src, s->h_src, scap, r->src_pos, r->dev.size(), s->upload);
-    if (e == hipSuccess) e = upload_range(s->d_chunks, s->h_chunks, ccap, r->chunk_pos, r->chunks, s->upload);
   }
+  // One copy per run of admitted blocks that follow one another in a ring
+  // without crossing its end (blocks never straddle it), not one per block.
+  auto upload_runs = [&](auto *dev, const auto *host, uint64_t cap, auto pos_of, auto count_of) -> hipError_t {
+    uint64_t run_pos = 0, run_end = 0;
+    for (Request *r : rs) {
+      const uint64_t p = pos_of(r), n = count_of(r);
+      if (n == 0) continue;
+      if (run_end != run_pos && p == run_end && p % cap != 0) {
+        run_end += n;
+        continue;
+      }
+      if (run_end != run_pos) {
+        const hipError_t u = upload_range(dev, host, cap, run_pos, run_end - run_pos, s->upload);
+        if (u != hipSuccess) return u;
+      }
+      run_pos = p;
+      run_end = p + n;
+    }
+    return run_end != run_pos ? upload_range(dev, host, cap, run_pos, run_end - run_pos, s->upload) : hipSuccess;
+  };
+  e = upload_runs(s->d_src, s->h_src, scap, [](const Request *r) { return r->src_pos; },
+                  [](const Request *r) { return static_cast<uint64_t>(r->dev.size()); });
+  if (e == hipSuccess)
+    e = upload_runs(s->d_chunks, s->h_chunks, ccap, [](const Request *r) { return r->chunk_pos; },
+                    [](const Request *r) { return r->chunks; });
   if (e == hipSuccess) e = hipEventRecord(s->ev_upload, s->upload);
   std::lock_guard<std::mutex> lk(s->mu);
   for (size_t i = 0; i < admitted.size(); ++i) {
